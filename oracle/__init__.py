@@ -1,0 +1,177 @@
+"""Python access to the CPU oracle (``oracle/xdg_oracle.c``).
+
+TEST INFRASTRUCTURE ONLY: imported by the test suite, the smoke check and
+the CPU-baseline leg of the benchmark, never by the product path.  It shares
+nothing with the GPU library but the seeded inputs of ``workloads``.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+import subprocess
+from typing import Optional, Tuple
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "xdg_oracle.c")
+_LIB = os.path.join(_HERE, "liboracle.so")
+_lib = None
+
+
+def build(force: bool = False) -> str:
+    """Compile the oracle with gcc (OpenMP, -O2, plain IEEE double)."""
+    if force or not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
+        tmp = _LIB + ".tmp"
+        subprocess.check_call(["gcc", "-O2", "-std=c11", "-fopenmp", "-fPIC", "-shared",
+                               "-fno-fast-math", "-o", tmp, _SRC, "-lm"])
+        os.replace(tmp, _LIB)
+    return _LIB
+
+
+def _load():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(_LIB):
+            build()
+        lib = C.CDLL(_LIB)
+        P = C.c_void_p
+        lib.orc_act.restype = C.c_uint64
+        lib.orc_act.argtypes = [C.c_int, P, C.c_uint64]
+        lib.orc_rep.restype = C.c_uint64
+        lib.orc_rep.argtypes = [C.c_int, C.c_int, P, C.c_uint64, P, P]
+        lib.orc_basis.restype = C.c_int64
+        lib.orc_basis.argtypes = [C.c_int, C.c_int, C.c_int, P, P, P, C.c_int64]
+        lib.orc_index.restype = C.c_int64
+        lib.orc_index.argtypes = [P, C.c_int64, C.c_uint64]
+        lib.orc_row_terms.restype = C.c_int
+        lib.orc_row_terms.argtypes = [C.c_int, C.c_int, P, P, C.c_int, P, P, P, C.c_uint64,
+                                      P, P, P, C.c_int]
+        lib.orc_apply.restype = C.c_int
+        lib.orc_apply.argtypes = [C.c_int, C.c_int, P, P, C.c_int, P, P, P, P, C.c_int64,
+                                  C.c_int64, P, P]
+        lib.orc_tridiag_eigvals.restype = C.c_int
+        lib.orc_tridiag_eigvals.argtypes = [C.c_int, P, P, C.c_int, P]
+        lib.orc_lanczos.restype = C.c_int
+        lib.orc_lanczos.argtypes = [C.c_int, C.c_int, P, P, C.c_int, P, P, P, P, C.c_int64, P,
+                                    C.c_int, C.c_double, C.c_int, C.c_int, P, P, P, P]
+        lib.orc_num_threads.restype = C.c_int
+        lib.orc_set_num_threads.argtypes = [C.c_int]
+        _lib = lib
+    return _lib
+
+
+def _p(a: Optional[np.ndarray]):
+    return None if a is None else a.ctypes.data_as(C.c_void_p)
+
+
+def _model_arrays(m):
+    perm = None if m.perm is None else np.ascontiguousarray(m.perm, dtype=np.int32)
+    chi = m.chi_interleaved()
+    sites = np.ascontiguousarray(m.sites, dtype=np.int32)
+    jz = np.ascontiguousarray(m.jz, dtype=np.float64)
+    jxy = np.ascontiguousarray(m.jxy, dtype=np.float64)
+    return perm, chi, sites, jz, jxy
+
+
+def num_threads() -> int:
+    return _load().orc_num_threads()
+
+
+def set_num_threads(n: int) -> None:
+    _load().orc_set_num_threads(int(n))
+
+
+def act(n_sites: int, g, s: int) -> int:
+    g = np.ascontiguousarray(g, dtype=np.int32)
+    return int(_load().orc_act(n_sites, _p(g), s))
+
+
+def rep(n_sites: int, perm, s: int) -> Tuple[int, int, int]:
+    """(representative, first minimising element, number of minimisers)."""
+    perm = np.ascontiguousarray(perm, dtype=np.int32)
+    u = np.zeros(1, np.int32)
+    n = np.zeros(1, np.int32)
+    r = _load().orc_rep(n_sites, perm.shape[0], _p(perm), s, _p(u), _p(n))
+    return int(r), int(u[0]), int(n[0])
+
+
+def basis(m) -> np.ndarray:
+    """Ascending basis list (uint64) of the model's sector."""
+    perm, chi, *_ = _model_arrays(m)
+    lib = _load()
+    n_sym = m.n_sym
+    if chi is None and n_sym:
+        chi = np.zeros((n_sym, 2))
+        chi[:, 0] = 1.0
+    d = lib.orc_basis(m.n_sites, m.n_up, n_sym, _p(perm), _p(chi), None, 0)
+    if d < 0:
+        raise ValueError(f"orc_basis failed ({d})")
+    out = np.empty(max(d, 1), dtype=np.uint64)
+    d2 = lib.orc_basis(m.n_sites, m.n_up, n_sym, _p(perm), _p(chi), _p(out), d)
+    assert d2 == d
+    return out[:d]
+
+
+def index(basis_list: np.ndarray, s: int) -> int:
+    b = np.ascontiguousarray(basis_list, dtype=np.uint64)
+    return int(_load().orc_index(_p(b), len(b), s))
+
+
+def row_terms(m, r: int):
+    """(diag, targets uint64[n], amps complex128[n]) of row r (pull form)."""
+    perm, chi, sites, jz, jxy = _model_arrays(m)
+    cap = len(jz) + 1
+    tg = np.zeros(cap, np.uint64)
+    am = np.zeros(2 * cap, np.float64)
+    d = np.zeros(1, np.float64)
+    n = _load().orc_row_terms(m.n_sites, m.n_sym, _p(perm), _p(chi), len(jz), _p(sites), _p(jz),
+                              _p(jxy), r, _p(d), _p(tg), _p(am), cap)
+    if n < 0:
+        raise RuntimeError("orc_row_terms failed")
+    return float(d[0]), tg[:n].copy(), am[: 2 * n].view(np.complex128).copy()
+
+
+def apply(m, basis_list: np.ndarray, x: np.ndarray) -> np.ndarray:
+    """y = H x; x of shape [dim] or [dim, nvec], any real/complex dtype."""
+    perm, chi, sites, jz, jxy = _model_arrays(m)
+    b = np.ascontiguousarray(basis_list, dtype=np.uint64)
+    squeeze = x.ndim == 1
+    xc = np.ascontiguousarray(x.reshape(len(b), -1), dtype=np.complex128)
+    nvec = xc.shape[1]
+    y = np.zeros_like(xc)
+    rc = _load().orc_apply(m.n_sites, m.n_sym, _p(perm), _p(chi), len(jz), _p(sites), _p(jz),
+                           _p(jxy), _p(b), len(b), nvec, _p(xc), _p(y))
+    if rc != 0:
+        raise RuntimeError("orc_apply failed")
+    return y[:, 0] if squeeze else y
+
+
+def tridiag_eigvals(alpha, beta, k: int) -> np.ndarray:
+    a = np.ascontiguousarray(alpha, dtype=np.float64)
+    m = len(a)
+    b = np.zeros(max(m, 1), np.float64)
+    b[: m - 1] = np.asarray(beta, dtype=np.float64)[: m - 1]
+    out = np.zeros(k, np.float64)
+    if _load().orc_tridiag_eigvals(m, _p(a), _p(b), k, _p(out)) != 0:
+        raise ValueError("bad tridiagonal arguments")
+    return out
+
+
+def lanczos(m, basis_list: np.ndarray, x0: np.ndarray, k: int = 1, tol: float = 1e-12,
+            max_iter: int = 300, reorth: bool = False):
+    """Returns (status, evals[k], alpha[n], beta[n])."""
+    perm, chi, sites, jz, jxy = _model_arrays(m)
+    b = np.ascontiguousarray(basis_list, dtype=np.uint64)
+    x = np.ascontiguousarray(x0, dtype=np.complex128)
+    al = np.zeros(max_iter, np.float64)
+    be = np.zeros(max_iter, np.float64)
+    ev = np.zeros(k, np.float64)
+    nit = np.zeros(1, np.int32)
+    st = _load().orc_lanczos(m.n_sites, m.n_sym, _p(perm), _p(chi), len(jz), _p(sites), _p(jz),
+                             _p(jxy), _p(b), len(b), _p(x), k, tol, max_iter, int(reorth),
+                             _p(al), _p(be), _p(nit), _p(ev))
+    if st < 0:
+        raise RuntimeError(f"orc_lanczos failed ({st})")
+    n = int(nit[0])
+    return st, ev, al[:n].copy(), be[:n].copy()
