@@ -1,0 +1,226 @@
+/*
+ * xdg.h - C ABI of the MI355X library for symmetry-adapted spin-1/2 exact
+ * diagonalisation: sector bases, the matrix-free Hamiltonian application
+ * y = H x, and the Lanczos iteration built on it.
+ *
+ * Paper: XDiag, "Exact Diagonalization for Quantum Many-Body Systems"
+ * (arXiv 2505.02901).  Each entry point names the passage that defines the
+ * operation it performs.
+ *
+ * General rules
+ *   - Pure C ABI: plain integers, doubles and pointers; no exceptions cross it.
+ *   - Every function returns XDG_OK (0) on success or a negative XDG_E* code;
+ *     xdg_last_error() then returns a message (thread-local, valid until the
+ *     next failing call on the same thread).  XDG_ENOCONV is the one
+ *     "soft" failure: the outputs are written anyway.
+ *   - Sites are 0-based (as in the C++ listings of Sec. 3.1 and 3.10.1).
+ *     A product state is an integer whose bit i is site i, bit value 1 = up.
+ *   - Permutations are rows perm[g * n_sites + i] = g(i); the action on a
+ *     product state follows the definition in Sec. 3.11: (g.s) has at site i
+ *     the spin of s at site g(i).
+ *   - A sector basis is the ascending list of orbit representatives (the
+ *     smallest integer of each orbit, Sec. 3.11) whose orbit carries a
+ *     symmetric state for the chosen characters; with no group it is the
+ *     ascending list of all states with n_up up spins (Sec. 3.1).
+ *     Basis vectors are unit normalised: |s~> = N_s^-1 sum_g chi(g)^* g|s>,
+ *     N_s = sqrt(|G| |Stab(s)|).
+ *   - Vectors are device pointers in HBM laid out [dim][nvec] row-major
+ *     (the nvec values of one basis index are contiguous); complex values
+ *     are (re, im) interleaved.  The caller owns them.  Handles own every
+ *     table and work buffer they allocate and free them on destroy.
+ *   - All device work runs on the current HIP device.  Functions that take
+ *     a `stream` (hipStream_t passed as void*; NULL = default stream) only
+ *     enqueue work; the others synchronise before returning.
+ */
+#ifndef XDG_H
+#define XDG_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ---- status codes ------------------------------------------------------ */
+#define XDG_OK        0
+#define XDG_EINVAL   -1  /* bad argument: n_up outside [0, N], N > 64, bad site, bad dtype ... */
+#define XDG_EGROUP   -2  /* permutations do not form a group (Sec. 3.10.1: identity, inverses, closure) */
+#define XDG_ECHAR    -3  /* characters are not a 1-d representation (Sec. 3.10.2: |chi| = 1, homomorphism) */
+#define XDG_ENOTSYM  -4  /* bond list not invariant under the group: no well-defined sector (Sec. 3.6, 3.10) */
+#define XDG_ENOMEM   -5  /* device allocation failed */
+#define XDG_EHIP     -6  /* HIP runtime error */
+#define XDG_ENOCONV  -7  /* Lanczos reached max_iter before the tolerance; outputs still written */
+
+/* ---- scalar types of vectors -------------------------------------------- */
+#define XDG_F64   0   /* double */
+#define XDG_F32   1   /* float */
+#define XDG_C128  2   /* complex double, (re, im) */
+#define XDG_C64   3   /* complex float, (re, im) */
+
+/* ---- representative search kinds (Sec. 5.1 backends, Sec. 5.2) ---------- */
+#define XDG_SEARCH_AUTO        0  /* pick the fastest kind that applies */
+#define XDG_SEARCH_U1          1  /* no permutation group: Lin-table index (Sec. 5.2) */
+#define XDG_SEARCH_AFFINE      2  /* every g is i -> (+-i + a) mod N: images by bit rotation/reversal */
+#define XDG_SEARCH_SUBLATTICE  3  /* sublattice coding: sites labelled in n_s contiguous blocks, each g maps blocks onto blocks */
+#define XDG_SEARCH_TABLE       4  /* any group: images from per-element byte lookup tables */
+
+/* ---- Lanczos precision forms --------------------------------------------- */
+#define XDG_PREC_F64          0  /* FP64 (or complex FP64) vectors */
+#define XDG_PREC_F32VEC       1  /* FP32 (or complex FP32) vectors; FP64 dot products, norms, update, tridiagonal solve */
+#define XDG_PREC_F32VEC_REORTH 2 /* as F32VEC plus full reorthogonalisation (classical Gram-Schmidt twice, FP64 coefficients) */
+#define XDG_PREC_F64_REORTH   3  /* FP64 vectors plus full reorthogonalisation */
+
+typedef struct xdg_basis_s *xdg_basis;
+typedef struct xdg_ham_s *xdg_ham;
+
+/* Options for xdg_create_basis; pass NULL for defaults (all zero). */
+typedef struct xdg_basis_opts {
+    int search;          /* XDG_SEARCH_*; 0 = auto */
+    int n_sublattices;   /* for XDG_SEARCH_SUBLATTICE: 2..5; 0 = detect */
+    int reserved[6];     /* must be zero */
+} xdg_basis_opts;
+
+/* Version string of the library (cf. the version banner, Sec. 2). */
+const char *xdg_version(void);
+
+/* Message of the last failing call on this thread (cf. error traces, Sec. 2). */
+const char *xdg_last_error(void);
+
+/* Host-only validation of a permutation group and its characters, exactly as
+ * xdg_create_basis performs it (Sec. 3.10.1: identity, inverse of every
+ * element and closure under products must be present; Sec. 3.10.2:
+ * f*g = h implies chi(f) chi(g) = chi(h), and |chi| = 1).
+ * perm: host int32[n_sym * n_sites]; chi: host double[2 * n_sym] (re, im)
+ * or NULL (all 1).  Needs no GPU.  Tolerance 1e-12 absolute on characters.
+ * Returns XDG_OK, XDG_EINVAL, XDG_EGROUP or XDG_ECHAR. */
+int xdg_check_group(int n_sites, int n_sym, const int32_t *perm, const double *chi);
+
+/* Host-only check that a bond list (with couplings) is mapped onto itself by
+ * every group element (a Hamiltonian with a well-defined sector, Sec. 3.6).
+ * Bonds are unordered pairs; duplicate bonds add their couplings.
+ * Relative tolerance 1e-12.  Returns XDG_OK, XDG_EINVAL or XDG_ENOTSYM. */
+int xdg_check_bonds(int n_sites, int n_sym, const int32_t *perm, int n_bonds,
+                    const int32_t *sites, const double *jz, const double *jxy);
+
+/* Search kind that xdg_create_basis would pick (host only, no GPU).
+ * Writes the XDG_SEARCH_* kind and, for sublattice coding, the number of
+ * sublattices. */
+int xdg_plan_search(int n_sites, int n_sym, const int32_t *perm, const xdg_basis_opts *opts,
+                    int *kind, int *n_sublattices);
+
+/* Block Spinhalf(N, nup) or Spinhalf(N, nup, irrep) (Sec. 3.1, 3.11).
+ *   n_sites in [1, 64]; n_up in [0, n_sites];
+ *   n_sym = 0 and perm = NULL for the U(1)-only block;
+ *   perm: host int32[n_sym * n_sites]; chi: host double[2 * n_sym] or NULL.
+ * Validates the group and characters (xdg_check_group), enumerates the basis
+ * on the GPU and builds its device index.  The handle is immutable.
+ * Errors: XDG_EINVAL, XDG_EGROUP, XDG_ECHAR, XDG_ENOMEM, XDG_EHIP.
+ * A sector of dimension 0 is legal. */
+int xdg_create_basis(int n_sites, int n_up, int n_sym, const int32_t *perm, const double *chi,
+                     const xdg_basis_opts *opts, xdg_basis *out);
+
+/* Release a basis (Hamiltonians hold their own reference; NULL is ignored). */
+void xdg_destroy_basis(xdg_basis b);
+
+/* Dimension of the block (size(block), Sec. 3.1). */
+int xdg_basis_dim(xdg_basis b, int64_t *dim);
+
+/* 1 if the characters are not all real, so that H is complex on the block
+ * and vectors must be XDG_C128 / XDG_C64. */
+int xdg_basis_is_complex(xdg_basis b, int *is_complex);
+
+/* Search kind in use and its number of sublattices (0 unless sublattice). */
+int xdg_basis_search_kind(xdg_basis b, int *kind, int *n_sublattices);
+
+/* Copy basis states [begin, begin + count) (ascending representatives) to
+ * host memory (iteration over a block, Sec. 3.1 / 3.11). */
+int xdg_basis_copy_states(xdg_basis b, int64_t begin, int64_t count, uint64_t *host_out);
+
+/* Copy the stabiliser sizes |Stab(s)| of basis states [begin, begin+count)
+ * to host memory (int32; all 1 for the U(1) block). */
+int xdg_basis_copy_stabilisers(xdg_basis b, int64_t begin, int64_t count, int32_t *host_out);
+
+/* index(block, state) (Sec. 3.1): 0-based positions of n host states, -1
+ * for a state that is not a basis state (not a representative, wrong
+ * popcount, or an orbit without a symmetric state).  Runs the device index. */
+int xdg_basis_index(xdg_basis b, const uint64_t *states, int64_t n, int64_t *idx_out);
+
+/* Hamiltonian H = sum_b [ jz[b] Sz_i Sz_j + jxy[b]/2 (S+_i S-_j + S-_i S+_j) ]
+ * on a block: Appendix A types SzSz and Exchange (real coupling); SdotS is
+ * jz = jxy = J; the XXZ chain of Sec. 4 is jz = J Delta, jxy = J.
+ *   sites: host int32[2 * n_bonds] (i, j) pairs, i != j, both < n_sites;
+ *   jz, jxy: host double[n_bonds].
+ * The bond list must be invariant under the block's group (XDG_ENOTSYM).
+ * The handle keeps a reference to the basis. */
+int xdg_create_hamiltonian(xdg_basis b, int n_bonds, const int32_t *sites, const double *jz,
+                           const double *jxy, xdg_ham *out);
+
+void xdg_destroy_hamiltonian(xdg_ham h);
+
+/* Number of nonzero matrix elements one application touches per vector:
+ * dim (the diagonal, counted once per row) plus the off-diagonal (row, bond)
+ * terms whose target lies in the block.  Computed on the GPU once, cached. */
+int xdg_ham_nnz(xdg_ham h, int64_t *nnz);
+
+/* y = H x, matrix-free (apply, Sec. 3.6 and Sec. 5.1: elements are computed
+ * on the fly; several vectors at once as for a matrix of coefficients).
+ *   x, y: device pointers, [dim][nvec], dtype XDG_F64/F32/C128/C64; x != y.
+ *   Real dtypes need a real block (xdg_basis_is_complex == 0).
+ * One lane owns each output row and writes it once: no atomics, and the
+ * result is bitwise reproducible for any launch configuration.
+ * Enqueued on `stream`. */
+int xdg_apply(xdg_ham h, const void *x, void *y, int64_t nvec, int dtype, void *stream);
+
+/* Several blocks (of possibly different dimension) in one persistent fused
+ * launch: y_i = H_i x_i for i < n, all with the same nvec and dtype.  Work
+ * items are (block, row tile) pairs drawn from one queue. */
+int xdg_apply_batched(int n, const xdg_ham *hams, const void *const *xs, void *const *ys,
+                      int64_t nvec, int dtype, void *stream);
+
+/* Seeded random vector of `dim * nvec` scalars (random_state, Sec. 3.6):
+ * SplitMix64 (Steele, Lea, Flood 2014), counter based: output n of seed
+ * is mix(seed + n * 0x9E3779B97F4A7C15).  Scalar q (flat over [dim][nvec],
+ * complex re/im interleaved) uses outputs 2q+1, 2q+2:
+ *   kind 0: uniform on [-1, 1]: 2 u - 1;
+ *   kind 1: Gaussian: sqrt(-2 log1p(-u1)) cos(2 pi u2)   (Box-Muller),
+ * u = top 53 bits * 2^-53.  out: device pointer. */
+int xdg_random_state(int64_t dim, int64_t nvec, uint64_t seed, int kind, int dtype, void *out,
+                     void *stream);
+
+/* Lowest eigenvalues by Lanczos (eigval0 / eigvals_lanczos, Sec. 3.7.1).
+ *   v0: device start vector [dim] of the dtype the precision form uses
+ *       (F64/C128 or F32/C64), or NULL for xdg_random_state(seed, Gaussian);
+ *   k: number of lowest eigenvalues; tol: stop when the k-th lowest Ritz
+ *       value changes by <= tol * |value| between iterations (0 = run
+ *       max_iter iterations); breakdown (beta <= 1e-13 max(1,|alpha|)) stops;
+ *   prec: XDG_PREC_*;
+ *   evals: host double[k]; n_iter: host int (iterations done);
+ *   alpha, beta: host double[max_iter] or NULL: the tridiagonal matrix,
+ *       beta[j] couples j and j+1 (beta[n_iter-1] is the last residual norm).
+ * Returns XDG_OK, or XDG_ENOCONV when tol > 0 was not reached. */
+int xdg_lanczos_eigval(xdg_ham h, const void *v0, int k, double tol, int max_iter, uint64_t seed,
+                       int prec, double *evals, int *n_iter, double *alpha, double *beta,
+                       void *stream);
+
+/* n blocks x nvec independent Lanczos recurrences advanced in lockstep; each
+ * step is one batched application (xdg_apply_batched) plus batched vector
+ * operations, replayed from a captured HIP graph.  Fixed iteration count.
+ *   v0s: n device pointers [dim_i][nvec] or NULL (seeds seed + i);
+ *   prec: XDG_PREC_F64 or XDG_PREC_F32VEC (vector dtype complex if any block
+ *         is complex, so that all blocks share one dtype);
+ *   evals: host double[n * nvec] lowest Ritz value of each recurrence
+ *         (block-major); alpha, beta: host double[n * nvec * n_iter] or NULL. */
+int xdg_lanczos_eigval_batched(int n, const xdg_ham *hams, const void *const *v0s, int64_t nvec,
+                               int n_iter, uint64_t seed, int prec, double *evals, double *alpha,
+                               double *beta, void *stream);
+
+/* Timing of the last xdg_lanczos_eigval[_batched] call on this thread:
+ * total seconds in the iteration loop and seconds spent in the apply
+ * kernels (HIP events); either may be NULL. */
+int xdg_last_lanczos_timing(double *total_s, double *apply_s);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* XDG_H */

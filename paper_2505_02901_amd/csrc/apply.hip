@@ -1,0 +1,351 @@
+// Host side of the matrix-free application: sector descriptors, launch
+// shapes, the autotuner, the batched persistent launch and nnz counting.
+#include <algorithm>
+#include <chrono>
+#include <cstring>
+#include <vector>
+
+#include "apply_impl.hpp"
+
+namespace xdg {
+
+size_t lds_limit();
+
+size_t dtype_size(int dtype) {
+    switch (dtype) {
+        case XDG_F64: return 8;
+        case XDG_F32: return 4;
+        case XDG_C128: return 16;
+        case XDG_C64: return 8;
+    }
+    return 0;
+}
+bool dtype_complex(int dtype) { return dtype == XDG_C128 || dtype == XDG_C64; }
+bool dtype_single(int dtype) { return dtype == XDG_F32 || dtype == XDG_C64; }
+
+namespace {
+
+int launch_dispatch(int kind, bool wide, bool single, bool cplx, int nv, const ApplyArgs &A,
+                    unsigned grid, unsigned block, size_t lds, hipStream_t st) {
+    switch (kind) {
+        case K_U1: return launch_kind<K_U1>(wide, single, cplx, nv, A, grid, block, lds, st);
+        case K_AFF: return launch_kind<K_AFF>(wide, single, cplx, nv, A, grid, block, lds, st);
+        case K_SUB: return launch_kind<K_SUB>(wide, single, cplx, nv, A, grid, block, lds, st);
+        case K_TAB: return launch_kind<K_TAB>(wide, single, cplx, nv, A, grid, block, lds, st);
+    }
+    set_error("unknown search kind %d", kind);
+    return XDG_EINVAL;
+}
+
+SectorDesc make_desc(const xdg_ham_s *h, bool single, const void *x, void *y) {
+    const xdg_basis_s *b = h->basis;
+    SectorDesc d{};
+    d.reps = b->reps.p;
+    d.stab = b->stab.as<uint16_t>();
+    d.dim = b->dim;
+    d.hash = b->hash.p;
+    d.n_lines = b->hidx.n_lines;
+    d.empty = b->wide ? (b->n_up == b->n_sites ? 0ull : ~0ull)
+                      : (b->n_up == b->n_sites ? 0ull : 0xFFFFFFFFull);
+    d.lin = b->lin.as<uint32_t>();
+    d.nlo = b->lin_nlo;
+    d.n_sites = b->n_sites;
+    d.n_sym = b->n_sym;
+    d.n_bonds = h->n_bonds;
+    d.aff = b->t_aff.as<AffineElem>();
+    d.bytetab = b->t_bytes.as<uint64_t>();
+    d.n_bchunks = b->plan.bytes.n_chunks;
+    d.mintop = b->t_mintop.as<uint16_t>();
+    d.cand_off = b->t_candoff.as<uint32_t>();
+    d.cand_list = b->t_candlist.as<uint16_t>();
+    d.src = b->t_src.as<uint8_t>();
+    d.img = b->t_img.as<uint16_t>();
+    d.n_s = b->plan.sub.n_s;
+    d.m = b->plan.sub.m;
+    d.n_cand = (uint32_t)b->plan.sub.cand_list.size();
+    d.bonds = single ? h->bonds_f.p : h->bonds_d.p;
+    d.chi = single ? b->chi_f.p : b->chi_d.p;
+    d.sqrtt = single ? b->sqrt_f.p : b->sqrt_d.p;
+    d.x = x;
+    d.y = y;
+    return d;
+}
+
+// Real-valued kernels serve complex vectors on a real block: the real and
+// imaginary parts are independent columns of a [dim][2 nvec] real block.
+struct Form {
+    bool single, cplx_kernel;
+    int64_t cols;   // columns seen by the kernel
+};
+
+int form_of(const xdg_basis_s *b, int dtype, int64_t nvec, Form *f) {
+    if (dtype < XDG_F64 || dtype > XDG_C64) {
+        set_error("unknown dtype %d", dtype);
+        return XDG_EINVAL;
+    }
+    if (nvec < 1) {
+        set_error("nvec = %lld must be >= 1", (long long)nvec);
+        return XDG_EINVAL;
+    }
+    if (b->is_complex && !dtype_complex(dtype)) {
+        set_error("the block has complex characters: vectors must be XDG_C128 or XDG_C64");
+        return XDG_EINVAL;
+    }
+    f->single = dtype_single(dtype);
+    f->cplx_kernel = b->is_complex;
+    f->cols = (dtype_complex(dtype) && !b->is_complex) ? 2 * nvec : nvec;
+    return XDG_OK;
+}
+
+int pick_nv(int64_t remaining, int cap) {
+    int nv = 8;
+    while (nv > 1 && (nv > remaining || nv > cap)) nv >>= 1;
+    return nv;
+}
+
+}  // namespace
+
+int apply_launch(xdg_ham_s *h, const void *x, void *y, int64_t nvec, int dtype, hipStream_t st,
+                 const LaunchCfg *cfg) {
+    const xdg_basis_s *b = h->basis;
+    Form f;
+    XDG_RETURN_IF(form_of(b, dtype, nvec, &f));
+    if (b->dim == 0) return XDG_OK;
+    if (!x || !y || x == y) {
+        set_error("x and y must be distinct non-null device pointers");
+        return XDG_EINVAL;
+    }
+    LaunchCfg c = cfg ? *cfg : LaunchCfg{};
+    const unsigned block = 256;
+    const int64_t need = (b->dim + block - 1) / block;
+    const int64_t gmax = c.grid > 0 ? c.grid : (int64_t)device_cu_count() * 16;
+    const unsigned grid = (unsigned)std::max<int64_t>(1, std::min<int64_t>(need, gmax));
+    ApplyArgs A{};
+    A.one = make_desc(h, f.single, x, y);
+    A.nvec = f.cols;
+    size_t lds = f.single ? stage_bytes<float>(A.one, b->plan.kind, 1)
+                          : stage_bytes<double>(A.one, b->plan.kind, 1);
+    A.stage_sub = 1;
+    if (lds > lds_limit()) {
+        A.stage_sub = 0;
+        lds = f.single ? stage_bytes<float>(A.one, b->plan.kind, 0)
+                       : stage_bytes<double>(A.one, b->plan.kind, 0);
+    }
+    const int cap = c.nv > 0 ? c.nv : 8;
+    for (int64_t v0 = 0; v0 < f.cols;) {
+        const int nv = pick_nv(f.cols - v0, cap);
+        A.v0 = (int)v0;
+        XDG_RETURN_IF(launch_dispatch(b->plan.kind, b->wide, f.single, f.cplx_kernel, nv, A, grid,
+                                      block, lds, st));
+        v0 += nv;
+    }
+    return XDG_OK;
+}
+
+// Launch-shape autotuner: times a few grid sizes and vectors-per-pass on
+// the first call for a (dtype, nvec) pair; the result is bitwise identical
+// for every candidate, so the timing runs also leave the right y behind.
+int apply_tuned(xdg_ham_s *h, const void *x, void *y, int64_t nvec, int dtype, hipStream_t st) {
+    TuneKey key{dtype, nvec};
+    auto it = h->tuned.find(key);
+    if (it != h->tuned.end()) return apply_launch(h, x, y, nvec, dtype, st, &it->second);
+    const xdg_basis_s *b = h->basis;
+    Form f;
+    XDG_RETURN_IF(form_of(b, dtype, nvec, &f));
+    const int64_t need = (b->dim + 255) / 256;
+    if (b->dim < 4096 * 256) {   // small blocks: one row per lane is already optimal
+        LaunchCfg c{256, (int)std::min<int64_t>(need, 1 << 30), 8};
+        h->tuned[key] = c;
+        return apply_launch(h, x, y, nvec, dtype, st, &c);
+    }
+    std::vector<LaunchCfg> cands;
+    const int cu = device_cu_count();
+    for (int mult : {4, 8, 16, 32}) {
+        cands.push_back({256, cu * mult, 8});
+        if (f.cols > 1) cands.push_back({256, cu * mult, (int)std::max<int64_t>(1, f.cols / 2)});
+    }
+    cands.push_back({256, (int)std::min<int64_t>(need, 1 << 30), 8});
+    hipEvent_t e0, e1;
+    XDG_TRY_HIP(hipEventCreate(&e0));
+    XDG_TRY_HIP(hipEventCreate(&e1));
+    float best = 1e30f;
+    LaunchCfg bestc = cands[0];
+    for (const LaunchCfg &c : cands) {
+        XDG_RETURN_IF(apply_launch(h, x, y, nvec, dtype, st, &c));   // warm
+        XDG_TRY_HIP(hipEventRecord(e0, st));
+        for (int r = 0; r < 2; ++r) XDG_RETURN_IF(apply_launch(h, x, y, nvec, dtype, st, &c));
+        XDG_TRY_HIP(hipEventRecord(e1, st));
+        XDG_TRY_HIP(hipEventSynchronize(e1));
+        float ms = 0;
+        XDG_TRY_HIP(hipEventElapsedTime(&ms, e0, e1));
+        if (ms < best) {
+            best = ms;
+            bestc = c;
+        }
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    h->tuned[key] = bestc;
+    return apply_launch(h, x, y, nvec, dtype, st, &bestc);
+}
+
+int ham_count_nnz(xdg_ham_s *h, int64_t *nnz) {
+    if (h->nnz >= 0) {
+        *nnz = h->nnz;
+        return XDG_OK;
+    }
+    const xdg_basis_s *b = h->basis;
+    if (b->dim == 0) {
+        h->nnz = 0;
+        *nnz = 0;
+        return XDG_OK;
+    }
+    DevBuf cnt;
+    XDG_RETURN_IF(cnt.alloc(sizeof(unsigned long long)));
+    XDG_TRY_HIP(hipMemset(cnt.p, 0, sizeof(unsigned long long)));
+    ApplyArgs A{};
+    A.one = make_desc(h, false, nullptr, nullptr);
+    A.count = cnt.as<unsigned long long>();
+    A.stage_sub = 1;
+    size_t lds = stage_bytes<double>(A.one, b->plan.kind, 1);
+    if (lds > lds_limit()) {
+        A.stage_sub = 0;
+        lds = stage_bytes<double>(A.one, b->plan.kind, 0);
+    }
+    const unsigned block = 256;
+    const unsigned grid =
+        (unsigned)std::min<int64_t>((b->dim + block - 1) / block, (int64_t)device_cu_count() * 16);
+    int rc;
+    switch (b->plan.kind) {
+        case K_U1: rc = launch_count_kind<K_U1>(b->wide, A, grid, block, lds, 0); break;
+        case K_AFF: rc = launch_count_kind<K_AFF>(b->wide, A, grid, block, lds, 0); break;
+        case K_SUB: rc = launch_count_kind<K_SUB>(b->wide, A, grid, block, lds, 0); break;
+        default: rc = launch_count_kind<K_TAB>(b->wide, A, grid, block, lds, 0); break;
+    }
+    XDG_RETURN_IF(rc);
+    unsigned long long c = 0;
+    XDG_TRY_HIP(hipMemcpy(&c, cnt.p, sizeof c, hipMemcpyDeviceToHost));
+    h->nnz = b->dim + (int64_t)c;
+    *nnz = h->nnz;
+    return XDG_OK;
+}
+
+int batch_prepare(int n, xdg_ham_s *const *hams, const void *const *xs, void *const *ys,
+                  int64_t nvec, int dtype, BatchPlan *P) {
+    if (n < 1) {
+        set_error("batched apply needs at least one block");
+        return XDG_EINVAL;
+    }
+    const xdg_basis_s *b0 = hams[0]->basis;
+    bool any_cplx = false;
+    for (int i = 0; i < n; ++i) {
+        const xdg_basis_s *b = hams[i]->basis;
+        if (b->plan.kind != b0->plan.kind || b->wide != b0->wide) {
+            set_error("batched blocks must share the search kind and the state word width");
+            return XDG_EINVAL;
+        }
+        if (b->is_complex && !dtype_complex(dtype)) {
+            set_error("block %d is complex: vectors must be complex", i);
+            return XDG_EINVAL;
+        }
+        any_cplx |= b->is_complex;
+    }
+    if (dtype < XDG_F64 || dtype > XDG_C64 || nvec < 1) {
+        set_error("bad dtype or nvec");
+        return XDG_EINVAL;
+    }
+    P->n = n;
+    P->kind = b0->plan.kind;
+    P->wide = b0->wide;
+    P->single = dtype_single(dtype);
+    P->cplx = any_cplx;
+    P->cols = (dtype_complex(dtype) && !any_cplx) ? 2 * nvec : nvec;
+    P->tile_rows = 1024;
+    std::vector<SectorDesc> descs(n);
+    std::vector<uint32_t> prefix(n + 1, 0);
+    size_t lds_full = 0, lds_part = 0;
+    for (int i = 0; i < n; ++i) {
+        descs[i] = make_desc(hams[i], P->single, xs[i], ys[i]);
+        const uint64_t tiles = (hams[i]->basis->dim + P->tile_rows - 1) / P->tile_rows;
+        if ((uint64_t)prefix[i] + tiles >= 0xFFFFFFFFull) {
+            set_error("too many row tiles in the batch");
+            return XDG_EINVAL;
+        }
+        prefix[i + 1] = prefix[i] + (uint32_t)tiles;
+        const size_t f1 = P->single ? stage_bytes<float>(descs[i], P->kind, 1)
+                                    : stage_bytes<double>(descs[i], P->kind, 1);
+        const size_t f0 = P->single ? stage_bytes<float>(descs[i], P->kind, 0)
+                                    : stage_bytes<double>(descs[i], P->kind, 0);
+        lds_full = std::max(lds_full, f1);
+        lds_part = std::max(lds_part, f0);
+    }
+    P->n_tiles = prefix[n];
+    P->stage_sub = lds_full <= lds_limit();
+    P->lds = P->stage_sub ? lds_full : lds_part;
+    XDG_RETURN_IF(P->descs.upload(descs.data(), sizeof(SectorDesc) * n));
+    XDG_RETURN_IF(P->prefix.upload(prefix.data(), sizeof(uint32_t) * (n + 1)));
+    XDG_RETURN_IF(P->queue.alloc(sizeof(uint32_t)));
+    return XDG_OK;
+}
+
+int batch_launch(const BatchPlan &P, int grid, int nv_cap, hipStream_t st) {
+    if (P.n_tiles == 0) return XDG_OK;
+    ApplyArgs A{};
+    A.descs = P.descs.as<SectorDesc>();
+    A.tile_prefix = P.prefix.as<uint32_t>();
+    A.n_secs = P.n;
+    A.n_tiles = P.n_tiles;
+    A.tile_rows = P.tile_rows;
+    A.queue = P.queue.as<uint32_t>();
+    A.nvec = P.cols;
+    A.stage_sub = P.stage_sub;
+    const unsigned g = (unsigned)(grid > 0 ? grid : device_cu_count() * 8);
+    for (int64_t v0 = 0; v0 < P.cols;) {
+        const int nv = pick_nv(P.cols - v0, nv_cap > 0 ? nv_cap : 8);
+        A.v0 = (int)v0;
+        hipLaunchKernelGGL(k_zero_u32, dim3(1), dim3(1), 0, st, A.queue);
+        XDG_TRY_HIP(hipGetLastError());
+        XDG_RETURN_IF(launch_dispatch(P.kind, P.wide, P.single, P.cplx, nv, A, g, 256, P.lds, st));
+        v0 += nv;
+    }
+    return XDG_OK;
+}
+
+int apply_batched_launch(int n, xdg_ham_s *const *hams, const void *const *xs, void *const *ys,
+                         int64_t nvec, int dtype, hipStream_t st, uint32_t *, int grid, int) {
+    for (int i = 0; i < n; ++i)
+        if (!hams[i] || !xs[i] || !ys[i] || xs[i] == ys[i]) {
+            set_error("batched apply: null handle/pointer or x == y at %d", i);
+            return XDG_EINVAL;
+        }
+    // plans are cached by the exact argument tuple so that repeated calls
+    // (iterative methods) upload nothing
+    struct Key {
+        std::vector<const void *> p;
+        int64_t nvec;
+        int dtype;
+        bool operator==(const Key &o) const { return p == o.p && nvec == o.nvec && dtype == o.dtype; }
+    };
+    thread_local std::vector<std::pair<Key, std::unique_ptr<BatchPlan>>> cache;
+    Key k;
+    for (int i = 0; i < n; ++i) {
+        k.p.push_back(hams[i]);
+        k.p.push_back(xs[i]);
+        k.p.push_back(ys[i]);
+    }
+    k.nvec = nvec;
+    k.dtype = dtype;
+    BatchPlan *P = nullptr;
+    for (auto &e : cache)
+        if (e.first == k) P = e.second.get();
+    if (!P) {
+        auto up = std::make_unique<BatchPlan>();
+        XDG_RETURN_IF(batch_prepare(n, hams, xs, ys, nvec, dtype, up.get()));
+        if (cache.size() >= 8) cache.erase(cache.begin());
+        cache.emplace_back(k, std::move(up));
+        P = cache.back().second.get();
+    }
+    return batch_launch(*P, grid, 8, st);
+}
+
+}  // namespace xdg

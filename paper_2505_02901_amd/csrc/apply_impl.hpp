@@ -1,0 +1,384 @@
+// The matrix-free application y = H x on a sector (apply, Sec. 3.6; the
+// on-the-fly element loop of Sec. 5.1 and the indexing of Sec. 5.2).
+//
+// Pull form: one lane owns one output row r (a basis state).  For every bond
+// with unequal spins it forms t = r with both spins exchanged, finds the
+// representative s of t, the first group element u with u.t = s and the
+// number of such elements (= |Stab(s)|), looks up the index of s, and adds
+//      (Jxy/2) chi(u) sqrt(|Stab s| / |Stab r|) x[idx(s)]
+// to the row, after the diagonal Sum_b Jz_b (+-1/4) x[r].  The row is
+// written once: no atomics, bitwise reproducible for any launch shape.
+// Up to NV vectors of the [dim][nvec] block share each search and lookup.
+#pragma once
+
+#include "device_common.hpp"
+
+namespace xdg {
+
+template <class T> struct Vec2;
+template <> struct Vec2<float> { using type = float2; };
+template <> struct Vec2<double> { using type = double2; };
+
+template <class T>
+__device__ __forceinline__ T fmadd(T a, T b, T c) {
+    if constexpr (sizeof(T) == 4)
+        return __builtin_fmaf(a, b, c);
+    else
+        return __builtin_fma(a, b, c);
+}
+
+template <class T> struct BondT;
+template <> struct BondT<float> { using type = BondF; };
+template <> struct BondT<double> { using type = BondD; };
+
+// Everything one sector needs on the device (type-erased pointers).
+struct SectorDesc {
+    const void *reps;            // u32 / u64 [dim]
+    const uint16_t *stab;        // [dim]
+    int64_t dim;
+    const void *hash;
+    uint64_t n_lines;
+    uint64_t empty;
+    const uint32_t *lin;         // Lin tables (U(1))
+    int nlo;
+    int n_sites, n_sym, n_bonds;
+    const AffineElem *aff;
+    const uint64_t *bytetab;
+    int n_bchunks;
+    const uint16_t *mintop;
+    const uint32_t *cand_off;
+    const uint16_t *cand_list;
+    const uint8_t *src;
+    const uint16_t *img;
+    int n_s, m;
+    uint32_t n_cand;
+    const void *bonds;           // BondD / BondF [n_bonds]
+    const void *chi;             // double2 / float2 [n_sym]
+    const void *sqrtt;           // T [2 (n_sym + 1)]: sqrt(c), then 1/sqrt(c)
+    const void *x;
+    void *y;
+};
+
+struct ApplyArgs {
+    SectorDesc one;              // used when descs == nullptr
+    const SectorDesc *descs;     // batched: device array [n_secs]
+    const uint32_t *tile_prefix; // batched: [n_secs + 1] cumulative tile counts
+    int n_secs;
+    uint32_t n_tiles;
+    uint32_t tile_rows;
+    uint32_t *queue;             // batched: work counter, zero at launch
+    int64_t nvec;
+    int v0;                      // first vector of this pass
+    int stage_sub;               // copy sublattice tables into LDS
+    unsigned long long *count;   // nnz counting mode (nullptr otherwise)
+};
+
+__host__ __device__ inline size_t a16(size_t x) { return (x + 15) & ~(size_t)15; }
+
+// LDS bytes needed to stage a sector's tables.
+template <class T>
+__host__ __device__ inline size_t stage_bytes(const SectorDesc &d, int kind, int stage_sub) {
+    size_t n = a16(sizeof(typename BondT<T>::type) * d.n_bonds);
+    if (kind != K_U1) {
+        n += a16(sizeof(typename Vec2<T>::type) * d.n_sym);
+        n += a16(sizeof(T) * 2 * (d.n_sym + 1));
+        if (kind == K_AFF) n += a16(sizeof(AffineElem) * d.n_sym);
+        if (kind == K_SUB && stage_sub) {
+            const size_t NV = (size_t)d.n_s << d.m;
+            n += a16(2 * NV) + a16(4 * (NV + 1)) + a16(2 * (size_t)d.n_cand);
+        }
+    }
+    return n;
+}
+
+template <class T>
+struct Staged {
+    const typename BondT<T>::type *bonds;
+    const typename Vec2<T>::type *chi;
+    const T *sq;       // sqrt(c)
+    const T *rsq;      // 1/sqrt(c)
+    const AffineElem *aff;
+    SubCtx sub;
+};
+
+template <int KIND, class T>
+__device__ inline void stage(const SectorDesc &d, unsigned char *smem, int stage_sub, Staged<T> &S) {
+    using B = typename BondT<T>::type;
+    using T2 = typename Vec2<T>::type;
+    size_t off = 0;
+    B *lb = reinterpret_cast<B *>(smem + off);
+    off = a16(off + sizeof(B) * d.n_bonds);
+    for (int e = threadIdx.x; e < d.n_bonds; e += blockDim.x)
+        lb[e] = reinterpret_cast<const B *>(d.bonds)[e];
+    S.bonds = lb;
+    S.sub = SubCtx{d.mintop, d.cand_off, d.cand_list, d.src, d.img, d.n_s, d.m};
+    if constexpr (KIND != K_U1) {
+        T2 *lc = reinterpret_cast<T2 *>(smem + off);
+        off = a16(off + sizeof(T2) * d.n_sym);
+        for (int e = threadIdx.x; e < d.n_sym; e += blockDim.x)
+            lc[e] = reinterpret_cast<const T2 *>(d.chi)[e];
+        T *ls = reinterpret_cast<T *>(smem + off);
+        off = a16(off + sizeof(T) * 2 * (d.n_sym + 1));
+        for (int e = threadIdx.x; e < 2 * (d.n_sym + 1); e += blockDim.x)
+            ls[e] = reinterpret_cast<const T *>(d.sqrtt)[e];
+        S.chi = lc;
+        S.sq = ls;
+        S.rsq = ls + d.n_sym + 1;
+        if constexpr (KIND == K_AFF) {
+            AffineElem *la = reinterpret_cast<AffineElem *>(smem + off);
+            off = a16(off + sizeof(AffineElem) * d.n_sym);
+            for (int e = threadIdx.x; e < d.n_sym; e += blockDim.x) la[e] = d.aff[e];
+            S.aff = la;
+        }
+        if constexpr (KIND == K_SUB) {
+            if (stage_sub) {
+                const uint32_t NV = (uint32_t)d.n_s << d.m;
+                uint16_t *lmt = reinterpret_cast<uint16_t *>(smem + off);
+                off = a16(off + 2 * (size_t)NV);
+                uint32_t *lco = reinterpret_cast<uint32_t *>(smem + off);
+                off = a16(off + 4 * ((size_t)NV + 1));
+                uint16_t *lcl = reinterpret_cast<uint16_t *>(smem + off);
+                for (uint32_t e = threadIdx.x; e < NV; e += blockDim.x) lmt[e] = d.mintop[e];
+                for (uint32_t e = threadIdx.x; e <= NV; e += blockDim.x) lco[e] = d.cand_off[e];
+                for (uint32_t e = threadIdx.x; e < d.n_cand; e += blockDim.x)
+                    lcl[e] = d.cand_list[e];
+                S.sub.mintop = lmt;
+                S.sub.cand_off = lco;
+                S.sub.cand_list = lcl;
+            }
+        }
+    }
+}
+
+// Locate the representative of t and its index; returns -1 when the orbit
+// is not in the block.  On success writes u and |Stab(s)|.
+template <class W, int KIND, class T>
+__device__ __forceinline__ int64_t locate(const SectorDesc &d, const Staged<T> &S, W t, int &u,
+                                          int &cnt) {
+    if constexpr (KIND == K_U1) {
+        const uint64_t lo = (uint64_t)t & ((1ull << d.nlo) - 1);
+        const uint64_t hi = (uint64_t)t >> d.nlo;
+        u = 0;
+        cnt = 1;
+        return (int64_t)d.lin[(1ull << d.nlo) + hi] + (int64_t)d.lin[lo];
+    } else {
+        W rep;
+        if constexpr (KIND == K_AFF)
+            aff_search<W>(S.aff, d.n_sym, d.n_sites, t, rep, u, cnt);
+        else if constexpr (KIND == K_SUB)
+            sub_search<W>(S.sub, t, rep, u, cnt);
+        else
+            tab_search<W>(d.bytetab, d.n_bchunks, d.n_sym, t, rep, u, cnt);
+        return hash_find<W>(d.hash, d.n_lines, (W)d.empty, rep);
+    }
+}
+
+template <class W, int KIND, class T, bool CPLX, int NV>
+__device__ __forceinline__ void process_row(const SectorDesc &d, const Staged<T> &S, int64_t row,
+                                            int64_t nvec, int v0) {
+    using B = typename BondT<T>::type;
+    constexpr int C = CPLX ? 2 : 1;
+    const W s = reinterpret_cast<const W *>(d.reps)[row];
+    const T *X = reinterpret_cast<const T *>(d.x);
+    T *Y = reinterpret_cast<T *>(d.y);
+    const int nb = d.n_bonds;
+    T diag = 0;
+    for (int b = 0; b < nb; ++b) {
+        const B bd = S.bonds[b];
+        const bool eq = ((s >> bd.i) & 1) == ((s >> bd.j) & 1);
+        diag += (eq ? T(0.25) : T(-0.25)) * bd.jz;
+    }
+    T acc[NV * C];
+    const size_t base = ((size_t)row * nvec + v0) * C;
+#pragma unroll
+    for (int v = 0; v < NV * C; ++v) acc[v] = diag * X[base + v];
+    T rn = T(1);
+    if constexpr (KIND != K_U1) rn = S.rsq[d.stab[row]];
+    for (int b = 0; b < nb; ++b) {
+        const B bd = S.bonds[b];
+        if (((s >> bd.i) & 1) == ((s >> bd.j) & 1)) continue;
+        const W t = s ^ ((W(1) << bd.i) | (W(1) << bd.j));
+        int u, cnt;
+        const int64_t idx = locate<W, KIND, T>(d, S, t, u, cnt);
+        if (idx < 0) continue;
+        T ar = bd.h, ai = 0;
+        if constexpr (KIND != K_U1) {
+            const T f = bd.h * S.sq[cnt] * rn;
+            const auto c = S.chi[u];
+            ar = f * c.x;
+            if constexpr (CPLX) ai = f * c.y;
+        }
+        const size_t xb = ((size_t)idx * nvec + v0) * C;
+        // explicit fused multiply-adds: a complex kernel on a block with real
+        // characters (ai = 0) rounds exactly like the real kernel
+#pragma unroll
+        for (int v = 0; v < NV; ++v) {
+            if constexpr (CPLX) {
+                const T xr = X[xb + 2 * v], xi = X[xb + 2 * v + 1];
+                acc[2 * v] = fmadd<T>(-ai, xi, fmadd<T>(ar, xr, acc[2 * v]));
+                acc[2 * v + 1] = fmadd<T>(ai, xr, fmadd<T>(ar, xi, acc[2 * v + 1]));
+            } else {
+                acc[v] = fmadd<T>(ar, X[xb + v], acc[v]);
+            }
+        }
+    }
+#pragma unroll
+    for (int v = 0; v < NV * C; ++v) Y[base + v] = acc[v];
+}
+
+// count of the off-diagonal terms of a row that land in the block
+template <class W, int KIND>
+__device__ __forceinline__ uint32_t count_row(const SectorDesc &d, const Staged<double> &S,
+                                              int64_t row) {
+    const W s = reinterpret_cast<const W *>(d.reps)[row];
+    uint32_t n = 0;
+    for (int b = 0; b < d.n_bonds; ++b) {
+        const BondD bd = S.bonds[b];
+        if (((s >> bd.i) & 1) == ((s >> bd.j) & 1)) continue;
+        const W t = s ^ ((W(1) << bd.i) | (W(1) << bd.j));
+        int u, cnt;
+        if (locate<W, KIND, double>(d, S, t, u, cnt) >= 0) ++n;
+    }
+    return n;
+}
+
+template <class W, int KIND, class T, bool CPLX, int NV>
+__global__ __launch_bounds__(256) void k_apply(ApplyArgs A) {
+    extern __shared__ __align__(16) unsigned char smem[];
+    __shared__ uint32_t s_tile;
+    __shared__ SectorDesc s_desc;
+    Staged<T> S;
+    if (A.descs == nullptr) {
+        const SectorDesc &d = A.one;
+        stage<KIND, T>(d, smem, A.stage_sub, S);
+        __syncthreads();
+        const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+        for (int64_t row = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; row < d.dim; row += stride)
+            process_row<W, KIND, T, CPLX, NV>(d, S, row, A.nvec, A.v0);
+        return;
+    }
+    // persistent: (sector, row tile) items from one queue
+    int cur = -1;
+    for (;;) {
+        if (threadIdx.x == 0) s_tile = atomicAdd(A.queue, 1u);
+        __syncthreads();
+        const uint32_t tile = s_tile;
+        if (tile >= A.n_tiles) break;
+        int lo = 0, hi = A.n_secs - 1;   // last sector with tile_prefix <= tile
+        while (lo < hi) {
+            const int mid = (lo + hi + 1) >> 1;
+            if (A.tile_prefix[mid] <= tile) lo = mid; else hi = mid - 1;
+        }
+        if (lo != cur) {
+            if (threadIdx.x == 0) s_desc = A.descs[lo];
+            __syncthreads();
+            stage<KIND, T>(s_desc, smem, A.stage_sub, S);
+            __syncthreads();
+            cur = lo;
+        }
+        const SectorDesc &d = s_desc;
+        const int64_t r0 = (int64_t)(tile - A.tile_prefix[lo]) * A.tile_rows;
+        int64_t r1 = r0 + A.tile_rows;
+        r1 = r1 < d.dim ? r1 : d.dim;
+        for (int64_t row = r0 + threadIdx.x; row < r1; row += blockDim.x)
+            process_row<W, KIND, T, CPLX, NV>(d, S, row, A.nvec, A.v0);
+        __syncthreads();
+    }
+}
+
+template <class W, int KIND>
+__global__ __launch_bounds__(256) void k_count(ApplyArgs A) {
+    extern __shared__ __align__(16) unsigned char smem[];
+    __shared__ unsigned long long s_sum;
+    Staged<double> S;
+    const SectorDesc &d = A.one;
+    stage<KIND, double>(d, smem, A.stage_sub, S);
+    if (threadIdx.x == 0) s_sum = 0;
+    __syncthreads();
+    unsigned long long n = 0;
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t row = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; row < d.dim; row += stride)
+        n += count_row<W, KIND>(d, S, row);
+    atomicAdd(&s_sum, n);
+    __syncthreads();
+    if (threadIdx.x == 0) atomicAdd(A.count, s_sum);
+}
+
+static __global__ void k_zero_u32(uint32_t *p) { *p = 0; }
+
+// Host launcher for one search kind (instantiated in one translation unit per kind).
+template <int KIND>
+int launch_kind(bool wide, bool single, bool cplx, int nv, const ApplyArgs &A, unsigned grid,
+                unsigned block, size_t lds, hipStream_t st);
+
+template <int KIND>
+int launch_count_kind(bool wide, const ApplyArgs &A, unsigned grid, unsigned block, size_t lds,
+                      hipStream_t st);
+
+}  // namespace xdg
+
+namespace xdg {
+
+template <class W, int KIND, class T, bool CPLX>
+int launch_nv(int nv, const ApplyArgs &A, unsigned grid, unsigned block, size_t lds,
+              hipStream_t st) {
+    void (*f)(ApplyArgs) = nullptr;
+    switch (nv) {
+        case 1: f = k_apply<W, KIND, T, CPLX, 1>; break;
+        case 2: f = k_apply<W, KIND, T, CPLX, 2>; break;
+        case 4: f = k_apply<W, KIND, T, CPLX, 4>; break;
+        case 8: f = k_apply<W, KIND, T, CPLX, 8>; break;
+        default:
+            set_error("vectors per pass %d not in {1, 2, 4, 8}", nv);
+            return XDG_EINVAL;
+    }
+    if (lds > 65536)
+        XDG_TRY_HIP(hipFuncSetAttribute((const void *)f,
+                                        hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
+    hipLaunchKernelGGL(f, dim3(grid), dim3(block), lds, st, A);
+    XDG_TRY_HIP(hipGetLastError());
+    return XDG_OK;
+}
+
+template <int KIND>
+int launch_kind_impl(bool wide, bool single, bool cplx, int nv, const ApplyArgs &A, unsigned grid,
+                     unsigned block, size_t lds, hipStream_t st) {
+    if constexpr (KIND == K_U1) {
+        if (cplx) {
+            set_error("complex kernel requested for a U(1) block");
+            return XDG_EINVAL;
+        }
+        if (wide)
+            return single ? launch_nv<uint64_t, KIND, float, false>(nv, A, grid, block, lds, st)
+                          : launch_nv<uint64_t, KIND, double, false>(nv, A, grid, block, lds, st);
+        return single ? launch_nv<uint32_t, KIND, float, false>(nv, A, grid, block, lds, st)
+                      : launch_nv<uint32_t, KIND, double, false>(nv, A, grid, block, lds, st);
+    } else {
+        if (wide) {
+            if (cplx)
+                return single ? launch_nv<uint64_t, KIND, float, true>(nv, A, grid, block, lds, st)
+                              : launch_nv<uint64_t, KIND, double, true>(nv, A, grid, block, lds, st);
+            return single ? launch_nv<uint64_t, KIND, float, false>(nv, A, grid, block, lds, st)
+                          : launch_nv<uint64_t, KIND, double, false>(nv, A, grid, block, lds, st);
+        }
+        if (cplx)
+            return single ? launch_nv<uint32_t, KIND, float, true>(nv, A, grid, block, lds, st)
+                          : launch_nv<uint32_t, KIND, double, true>(nv, A, grid, block, lds, st);
+        return single ? launch_nv<uint32_t, KIND, float, false>(nv, A, grid, block, lds, st)
+                      : launch_nv<uint32_t, KIND, double, false>(nv, A, grid, block, lds, st);
+    }
+}
+
+template <int KIND>
+int launch_count_impl(bool wide, const ApplyArgs &A, unsigned grid, unsigned block, size_t lds,
+                      hipStream_t st) {
+    void (*f)(ApplyArgs) = wide ? k_count<uint64_t, KIND> : k_count<uint32_t, KIND>;
+    if (lds > 65536)
+        XDG_TRY_HIP(hipFuncSetAttribute((const void *)f,
+                                        hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
+    hipLaunchKernelGGL(f, dim3(grid), dim3(block), lds, st, A);
+    XDG_TRY_HIP(hipGetLastError());
+    return XDG_OK;
+}
+
+}  // namespace xdg

@@ -1,0 +1,18 @@
+// Instantiation of the apply / count kernels for one search kind.
+#include "apply_impl.hpp"
+
+namespace xdg {
+
+template <>
+int launch_kind<K_U1>(bool wide, bool single, bool cplx, int nv, const ApplyArgs &A, unsigned grid,
+                    unsigned block, size_t lds, hipStream_t st) {
+    return launch_kind_impl<K_U1>(wide, single, cplx, nv, A, grid, block, lds, st);
+}
+
+template <>
+int launch_count_kind<K_U1>(bool wide, const ApplyArgs &A, unsigned grid, unsigned block, size_t lds,
+                          hipStream_t st) {
+    return launch_count_impl<K_U1>(wide, A, grid, block, lds, st);
+}
+
+}  // namespace xdg

@@ -1,0 +1,323 @@
+// The C ABI of include/xdg.h: argument checks, handle lifetime, dispatch.
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <new>
+#include <vector>
+
+#include "xdg_internal.hpp"
+
+using namespace xdg;
+
+namespace xdg {
+int last_timing(double *total, double *apply);
+}
+
+namespace {
+
+void basis_release(xdg_basis_s *b) {
+    if (b && b->refs.fetch_sub(1) == 1) delete b;
+}
+
+template <class F>
+int guarded(F &&f) {
+    try {
+        return f();
+    } catch (const std::bad_alloc &) {
+        set_error("host allocation failed");
+        return XDG_ENOMEM;
+    } catch (...) {
+        set_error("unexpected C++ exception");
+        return XDG_EINVAL;
+    }
+}
+
+}  // namespace
+
+extern "C" {
+
+const char *xdg_version(void) { return "xdg-mi355x 0.1.0 (gfx950, HIP)"; }
+
+const char *xdg_last_error(void) { return get_error(); }
+
+int xdg_check_group(int n_sites, int n_sym, const int32_t *perm, const double *chi) {
+    return guarded([&] { return validate_group(n_sites, n_sym, perm, chi); });
+}
+
+int xdg_check_bonds(int n_sites, int n_sym, const int32_t *perm, int n_bonds,
+                    const int32_t *sites, const double *jz, const double *jxy) {
+    return guarded([&] {
+        XDG_RETURN_IF(validate_group(n_sites, n_sym, perm, nullptr));
+        return validate_bonds(n_sites, n_sym, perm, n_bonds, sites, jz, jxy);
+    });
+}
+
+int xdg_plan_search(int n_sites, int n_sym, const int32_t *perm, const xdg_basis_opts *opts,
+                    int *kind, int *n_sublattices) {
+    return guarded([&] {
+        XDG_RETURN_IF(validate_group(n_sites, n_sym, perm, nullptr));
+        Plan p;
+        XDG_RETURN_IF(make_plan(n_sites, n_sym, perm, opts, &p, false));
+        if (kind) *kind = p.kind;
+        if (n_sublattices) *n_sublattices = p.kind == XDG_SEARCH_SUBLATTICE ? p.sub.n_s : 0;
+        return XDG_OK;
+    });
+}
+
+int xdg_create_basis(int n_sites, int n_up, int n_sym, const int32_t *perm, const double *chi,
+                     const xdg_basis_opts *opts, xdg_basis *out) {
+    return guarded([&]() -> int {
+        if (!out) {
+            set_error("out is NULL");
+            return XDG_EINVAL;
+        }
+        *out = nullptr;
+        if (n_sites < 1 || n_sites > 64) {
+            set_error("n_sites = %d outside [1, 64]", n_sites);
+            return XDG_EINVAL;
+        }
+        if (n_up < 0 || n_up > n_sites) {
+            set_error("n_up = %d outside [0, %d]", n_up, n_sites);
+            return XDG_EINVAL;
+        }
+        XDG_RETURN_IF(validate_group(n_sites, n_sym, perm, chi));
+        auto *b = new xdg_basis_s();
+        b->n_sites = n_sites;
+        b->n_up = n_up;
+        b->n_sym = n_sym;
+        b->wide = n_sites > 32;
+        if (n_sym) {
+            b->perm.assign(perm, perm + (size_t)n_sym * n_sites);
+            b->chi.assign(2 * (size_t)n_sym, 0.0);
+            for (int g = 0; g < n_sym; ++g) {
+                b->chi[2 * g] = chi ? chi[2 * g] : 1.0;
+                b->chi[2 * g + 1] = chi ? chi[2 * g + 1] : 0.0;
+                if (std::fabs(b->chi[2 * g + 1]) > 1e-13) b->is_complex = true;
+            }
+        }
+        int rc = make_plan(n_sites, n_sym, n_sym ? b->perm.data() : nullptr, opts, &b->plan, true);
+        if (rc == XDG_OK) {
+            hipError_t e = hipGetDevice(&b->device);
+            if (e != hipSuccess) {
+                set_error("no HIP device: %s", hipGetErrorString(e));
+                rc = XDG_EHIP;
+            }
+        }
+        if (rc == XDG_OK) rc = basis_build_device(b);
+        if (rc != XDG_OK) {
+            delete b;
+            return rc;
+        }
+        *out = b;
+        return XDG_OK;
+    });
+}
+
+void xdg_destroy_basis(xdg_basis b) { basis_release(b); }
+
+int xdg_basis_dim(xdg_basis b, int64_t *dim) {
+    if (!b || !dim) {
+        set_error("null argument");
+        return XDG_EINVAL;
+    }
+    *dim = b->dim;
+    return XDG_OK;
+}
+
+int xdg_basis_is_complex(xdg_basis b, int *is_complex) {
+    if (!b || !is_complex) {
+        set_error("null argument");
+        return XDG_EINVAL;
+    }
+    *is_complex = b->is_complex ? 1 : 0;
+    return XDG_OK;
+}
+
+int xdg_basis_search_kind(xdg_basis b, int *kind, int *n_sublattices) {
+    if (!b) {
+        set_error("null basis");
+        return XDG_EINVAL;
+    }
+    if (kind) *kind = b->plan.kind;
+    if (n_sublattices) *n_sublattices = b->plan.kind == XDG_SEARCH_SUBLATTICE ? b->plan.sub.n_s : 0;
+    return XDG_OK;
+}
+
+int xdg_basis_copy_states(xdg_basis b, int64_t begin, int64_t count, uint64_t *host_out) {
+    return guarded([&]() -> int {
+        if (!b || (count > 0 && !host_out) || begin < 0 || count < 0 || begin + count > b->dim) {
+            set_error("bad range [%lld, +%lld) for dimension %lld", (long long)begin,
+                      (long long)count, b ? (long long)b->dim : -1LL);
+            return XDG_EINVAL;
+        }
+        if (count == 0) return XDG_OK;
+        if (b->wide) {
+            XDG_TRY_HIP(hipMemcpy(host_out, b->reps.as<uint64_t>() + begin, 8 * (size_t)count,
+                                  hipMemcpyDeviceToHost));
+        } else {
+            std::vector<uint32_t> tmp((size_t)count);
+            XDG_TRY_HIP(hipMemcpy(tmp.data(), b->reps.as<uint32_t>() + begin, 4 * (size_t)count,
+                                  hipMemcpyDeviceToHost));
+            for (int64_t i = 0; i < count; ++i) host_out[i] = tmp[(size_t)i];
+        }
+        return XDG_OK;
+    });
+}
+
+int xdg_basis_copy_stabilisers(xdg_basis b, int64_t begin, int64_t count, int32_t *host_out) {
+    return guarded([&]() -> int {
+        if (!b || (count > 0 && !host_out) || begin < 0 || count < 0 || begin + count > b->dim) {
+            set_error("bad range");
+            return XDG_EINVAL;
+        }
+        if (count == 0) return XDG_OK;
+        if (b->n_sym == 0) {
+            std::fill(host_out, host_out + count, 1);
+            return XDG_OK;
+        }
+        std::vector<uint16_t> tmp((size_t)count);
+        XDG_TRY_HIP(hipMemcpy(tmp.data(), b->stab.as<uint16_t>() + begin, 2 * (size_t)count,
+                              hipMemcpyDeviceToHost));
+        for (int64_t i = 0; i < count; ++i) host_out[i] = tmp[(size_t)i];
+        return XDG_OK;
+    });
+}
+
+int xdg_basis_index(xdg_basis b, const uint64_t *states, int64_t n, int64_t *idx_out) {
+    return guarded([&]() -> int {
+        if (!b || n < 0 || (n > 0 && (!states || !idx_out))) {
+            set_error("bad arguments");
+            return XDG_EINVAL;
+        }
+        if (n == 0) return XDG_OK;
+        if (b->dim == 0) {
+            std::fill(idx_out, idx_out + n, -1);
+            return XDG_OK;
+        }
+        DevBuf ds, di;
+        XDG_RETURN_IF(ds.upload(states, 8 * (size_t)n));
+        XDG_RETURN_IF(di.alloc(8 * (size_t)n));
+        XDG_RETURN_IF(basis_lookup(b, ds.as<uint64_t>(), n, di.as<int64_t>(), 0));
+        XDG_TRY_HIP(hipMemcpy(idx_out, di.p, 8 * (size_t)n, hipMemcpyDeviceToHost));
+        return XDG_OK;
+    });
+}
+
+int xdg_create_hamiltonian(xdg_basis b, int n_bonds, const int32_t *sites, const double *jz,
+                           const double *jxy, xdg_ham *out) {
+    return guarded([&]() -> int {
+        if (!b || !out) {
+            set_error("null argument");
+            return XDG_EINVAL;
+        }
+        *out = nullptr;
+        XDG_RETURN_IF(validate_bonds(b->n_sites, b->n_sym, b->perm.data(), n_bonds, sites, jz, jxy));
+        auto *h = new xdg_ham_s();
+        h->basis = b;
+        b->refs.fetch_add(1);
+        h->n_bonds = n_bonds;
+        h->sites.assign(sites, sites + 2 * (size_t)n_bonds);
+        h->jz.assign(jz, jz + n_bonds);
+        h->jxy.assign(jxy, jxy + n_bonds);
+        std::vector<BondD> bd(n_bonds);
+        std::vector<BondF> bf(n_bonds);
+        for (int i = 0; i < n_bonds; ++i) {
+            bd[i] = BondD{(uint32_t)sites[2 * i], (uint32_t)sites[2 * i + 1], jz[i], 0.5 * jxy[i]};
+            bf[i] = BondF{bd[i].i, bd[i].j, (float)jz[i], (float)(0.5 * jxy[i])};
+        }
+        int rc = h->bonds_d.upload(bd.data(), sizeof(BondD) * std::max(n_bonds, 1));
+        if (rc == XDG_OK) rc = h->bonds_f.upload(bf.data(), sizeof(BondF) * std::max(n_bonds, 1));
+        if (rc != XDG_OK) {
+            basis_release(h->basis);
+            delete h;
+            return rc;
+        }
+        *out = h;
+        return XDG_OK;
+    });
+}
+
+void xdg_destroy_hamiltonian(xdg_ham h) {
+    if (!h) return;
+    basis_release(h->basis);
+    delete h;
+}
+
+int xdg_ham_nnz(xdg_ham h, int64_t *nnz) {
+    return guarded([&]() -> int {
+        if (!h || !nnz) {
+            set_error("null argument");
+            return XDG_EINVAL;
+        }
+        return ham_count_nnz(h, nnz);
+    });
+}
+
+int xdg_apply(xdg_ham h, const void *x, void *y, int64_t nvec, int dtype, void *stream) {
+    return guarded([&]() -> int {
+        if (!h) {
+            set_error("null hamiltonian");
+            return XDG_EINVAL;
+        }
+        return apply_tuned(h, x, y, nvec, dtype, (hipStream_t)stream);
+    });
+}
+
+int xdg_apply_batched(int n, const xdg_ham *hams, const void *const *xs, void *const *ys,
+                      int64_t nvec, int dtype, void *stream) {
+    return guarded([&]() -> int {
+        if (n < 1 || !hams || !xs || !ys) {
+            set_error("bad batched arguments");
+            return XDG_EINVAL;
+        }
+        std::vector<xdg_ham_s *> hv(hams, hams + n);
+        return apply_batched_launch(n, hv.data(), xs, ys, nvec, dtype, (hipStream_t)stream,
+                                    nullptr, 0, 256);
+    });
+}
+
+int xdg_random_state(int64_t dim, int64_t nvec, uint64_t seed, int kind, int dtype, void *out,
+                     void *stream) {
+    return guarded([&]() -> int {
+        if (dim < 0 || nvec < 1 || (kind != 0 && kind != 1) || dtype < XDG_F64 ||
+            dtype > XDG_C64 || (dim > 0 && !out)) {
+            set_error("bad random_state arguments");
+            return XDG_EINVAL;
+        }
+        const int64_t n = dim * nvec * (dtype_complex(dtype) ? 2 : 1);
+        return random_fill(n, seed, kind, dtype_single(dtype), out, (hipStream_t)stream);
+    });
+}
+
+int xdg_lanczos_eigval(xdg_ham h, const void *v0, int k, double tol, int max_iter, uint64_t seed,
+                       int prec, double *evals, int *n_iter, double *alpha, double *beta,
+                       void *stream) {
+    return guarded([&]() -> int {
+        if (!h) {
+            set_error("null hamiltonian");
+            return XDG_EINVAL;
+        }
+        return lanczos_single(h, v0, k, tol, max_iter, seed, prec, evals, n_iter, alpha, beta,
+                              (hipStream_t)stream, nullptr, nullptr);
+    });
+}
+
+int xdg_lanczos_eigval_batched(int n, const xdg_ham *hams, const void *const *v0s, int64_t nvec,
+                               int n_iter, uint64_t seed, int prec, double *evals, double *alpha,
+                               double *beta, void *stream) {
+    return guarded([&]() -> int {
+        if (n < 1 || !hams) {
+            set_error("bad batched arguments");
+            return XDG_EINVAL;
+        }
+        std::vector<xdg_ham_s *> hv(hams, hams + n);
+        return lanczos_batched(n, hv.data(), v0s, nvec, n_iter, seed, prec, evals, alpha, beta,
+                               (hipStream_t)stream, nullptr, nullptr);
+    });
+}
+
+int xdg_last_lanczos_timing(double *total_s, double *apply_s) {
+    return last_timing(total_s, apply_s);
+}
+
+}  // extern "C"

@@ -1,0 +1,333 @@
+// Device-side building blocks shared by the basis and apply kernels:
+// bit rotations of ring states, the hash index of the basis, and the three
+// representative searches (ring bit operations, sublattice coding, generic
+// byte tables).  gfx950, wave64.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "xdg_internal.hpp"
+
+namespace xdg {
+
+enum : int { K_U1 = XDG_SEARCH_U1, K_AFF = XDG_SEARCH_AFFINE, K_SUB = XDG_SEARCH_SUBLATTICE,
+             K_TAB = XDG_SEARCH_TABLE };
+
+// ------------------------------------------------------------ bit helpers --
+template <class W>
+__device__ __forceinline__ W rotr_n(W t, int a, int N) {
+    if constexpr (sizeof(W) == 4) {
+        if (N == 32) return __builtin_amdgcn_alignbit(t, t, (uint32_t)a);
+        if (a == 0) return t;
+        const W mask = (W(1) << N) - 1;
+        return ((t >> a) | (t << (N - a))) & mask;
+    } else {
+        if (a == 0) return t;
+        const W mask = N == 64 ? ~W(0) : ((W(1) << N) - 1);
+        return ((t >> a) | (t << (N - a))) & mask;
+    }
+}
+
+template <class W>
+__device__ __forceinline__ W rev_n(W t, int N) {
+    if constexpr (sizeof(W) == 4)
+        return __builtin_bitreverse32(t) >> (32 - N);
+    else
+        return __builtin_bitreverse64(t) >> (64 - N);
+}
+
+// ------------------------------------------------------------- hash index --
+// Open addressing over 64-byte lines; a lookup reads one line in the common
+// case.  A line holds 8 (key u32, value u32) or 5 (key u64, value u32) pairs.
+struct alignas(64) Line32 {
+    uint32_t k[8];
+    uint32_t v[8];
+};
+struct alignas(64) Line64 {
+    uint64_t k[5];
+    uint32_t v[5];
+    uint32_t pad;
+};
+static_assert(sizeof(Line32) == 64 && sizeof(Line64) == 64, "line size");
+
+template <class W>
+__host__ __device__ __forceinline__ uint64_t hash_line(W key, uint64_t n_lines) {
+    uint32_t h;
+    if constexpr (sizeof(W) == 4)
+        h = (uint32_t)key * 0x9E3779B1u;
+    else
+        h = (uint32_t)(((uint64_t)key * 0x9E3779B97F4A7C15ull) >> 32);
+    return ((uint64_t)h * n_lines) >> 32;
+}
+
+template <class W>
+__device__ __forceinline__ int64_t hash_find(const void *table, uint64_t n_lines, W empty, W key) {
+    uint64_t line = hash_line<W>(key, n_lines);
+    for (;;) {
+        if constexpr (sizeof(W) == 4) {
+            const uint4 *p = reinterpret_cast<const uint4 *>(
+                reinterpret_cast<const Line32 *>(table) + line);
+            const uint4 k0 = p[0], k1 = p[1], v0 = p[2], v1 = p[3];
+            const uint32_t ks[8] = {k0.x, k0.y, k0.z, k0.w, k1.x, k1.y, k1.z, k1.w};
+            const uint32_t vs[8] = {v0.x, v0.y, v0.z, v0.w, v1.x, v1.y, v1.z, v1.w};
+            int64_t found = -1;
+            bool any_empty = false;
+#pragma unroll
+            for (int s = 0; s < 8; ++s) {
+                if (ks[s] == key) found = vs[s];
+                any_empty |= ks[s] == empty;
+            }
+            if (found >= 0) return found;
+            if (any_empty) return -1;
+        } else {
+            const uint4 *p = reinterpret_cast<const uint4 *>(
+                reinterpret_cast<const Line64 *>(table) + line);
+            const uint4 a = p[0], b = p[1], c = p[2], d = p[3];
+            const uint64_t ks[5] = {((uint64_t)a.y << 32) | a.x, ((uint64_t)a.w << 32) | a.z,
+                                    ((uint64_t)b.y << 32) | b.x, ((uint64_t)b.w << 32) | b.z,
+                                    ((uint64_t)c.y << 32) | c.x};
+            const uint32_t vs[5] = {c.z, c.w, d.x, d.y, d.z};
+            int64_t found = -1;
+            bool any_empty = false;
+#pragma unroll
+            for (int s = 0; s < 5; ++s) {
+                if (ks[s] == key) found = vs[s];
+                any_empty |= ks[s] == empty;
+            }
+            if (found >= 0) return found;
+            if (any_empty) return -1;
+        }
+        line = line + 1 == n_lines ? 0 : line + 1;
+    }
+}
+
+// ---------------------------------------------------- search: ring (affine) --
+// Element g: image = rotr_N(t, a) (eps = +1) or rotr_N(rev_N(t), a) (eps = -1).
+template <class W>
+__device__ __forceinline__ void aff_search(const AffineElem *aff, int n_sym, int N, W t, W &best,
+                                           int &u, int &cnt) {
+    const W rt = rev_n<W>(t, N);
+    best = ~W(0);
+    u = 0;
+    cnt = 0;
+    for (int g = 0; g < n_sym; ++g) {
+        const AffineElem e = aff[g];
+        const W img = rotr_n<W>(e.eps > 0 ? t : rt, e.a, N);
+        if (img < best) {
+            best = img;
+            u = g;
+            cnt = 1;
+        } else if (img == best) {
+            ++cnt;
+        }
+    }
+}
+
+// Representative test for enumeration: false as soon as some image is smaller.
+// On true, stab = |Stab(s)| and (cr, ci) = sum of chi over the stabiliser.
+template <class W>
+__device__ __forceinline__ bool aff_is_rep(const AffineElem *aff, int n_sym, int N, W s,
+                                           const double2 *chi, int &stab, double &cr, double &ci) {
+    const W rs = rev_n<W>(s, N);
+    stab = 0;
+    cr = 0.0;
+    ci = 0.0;
+    for (int g = 0; g < n_sym; ++g) {
+        const AffineElem e = aff[g];
+        const W img = rotr_n<W>(e.eps > 0 ? s : rs, e.a, N);
+        if (img < s) return false;
+        if (img == s) {
+            ++stab;
+            cr += chi[g].x;
+            ci += chi[g].y;
+        }
+    }
+    return true;
+}
+
+// ------------------------------------------------ search: sublattice coding --
+// Sites come in n_s blocks of m bits; every group element maps blocks onto
+// blocks, so the top block of g.t is a lookup of one block of t.  The
+// smallest possible top block over the whole group is the minimum of
+// mintop[k][chunk_k(t)] over the source blocks k; only the elements listed
+// for the blocks reaching that minimum can produce the representative, and
+// only for them is the full image assembled, block by block from the top,
+// abandoning an element as soon as its image prefix exceeds the best one.
+struct SubCtx {
+    const uint16_t *mintop;    // [n_s][V]       (LDS)
+    const uint32_t *cand_off;  // [n_s*V + 1]    (LDS)
+    const uint16_t *cand_list; //                (LDS)
+    const uint8_t *src;        // [n_sym][n_s]   (global)
+    const uint16_t *img;       // [n_sym][n_s][V](global)
+    int n_s, m;
+};
+
+template <class W>
+__device__ __forceinline__ uint32_t chunk_of(W t, int k, int m, uint32_t vmask) {
+    return (uint32_t)(t >> (k * m)) & vmask;
+}
+
+template <class W>
+__device__ __forceinline__ void sub_search(const SubCtx &C, W t, W &best, int &u, int &cnt) {
+    const int m = C.m, ns = C.n_s, top = ns - 1;
+    const uint32_t V = 1u << m, vmask = V - 1;
+    uint32_t mt = 0xFFFFu;
+    for (int k = 0; k < ns; ++k) {
+        const uint32_t v = C.mintop[k * V + chunk_of<W>(t, k, m, vmask)];
+        mt = v < mt ? v : mt;
+    }
+    best = ~W(0);
+    u = 0x7fffffff;
+    cnt = 0;
+    for (int k = 0; k < ns; ++k) {
+        const uint32_t e = k * V + chunk_of<W>(t, k, m, vmask);
+        if (C.mintop[e] != mt) continue;
+        const uint32_t q1 = C.cand_off[e + 1];
+        for (uint32_t q = C.cand_off[e]; q < q1; ++q) {
+            const int g = C.cand_list[q];
+            const uint8_t *sg = C.src + (size_t)g * ns;
+            const uint16_t *ig = C.img + (size_t)g * ns * V;
+            W img = (W)mt << (top * m);
+            bool lose = false;
+            int a = top - 1;
+            for (; a >= 0; --a) {
+                img |= (W)ig[a * V + chunk_of<W>(t, sg[a], m, vmask)] << (a * m);
+                const W hi = img >> (a * m), hb = best >> (a * m);
+                if (hi > hb) {
+                    lose = true;
+                    break;
+                }
+                if (hi < hb) {
+                    for (--a; a >= 0; --a)
+                        img |= (W)ig[a * V + chunk_of<W>(t, sg[a], m, vmask)] << (a * m);
+                    break;
+                }
+            }
+            if (lose) continue;
+            if (img < best) {
+                best = img;
+                u = g;
+                cnt = 1;
+            } else if (img == best) {
+                ++cnt;
+                u = g < u ? g : u;
+            }
+        }
+    }
+}
+
+template <class W>
+__device__ __forceinline__ bool sub_is_rep(const SubCtx &C, W s, const double2 *chi, int &stab,
+                                           double &cr, double &ci) {
+    const int m = C.m, ns = C.n_s, top = ns - 1;
+    const uint32_t V = 1u << m, vmask = V - 1;
+    const uint32_t ct = chunk_of<W>(s, top, m, vmask);
+    for (int k = 0; k < ns; ++k)
+        if (C.mintop[k * V + chunk_of<W>(s, k, m, vmask)] < ct) return false;
+    stab = 0;
+    cr = 0.0;
+    ci = 0.0;
+    for (int k = 0; k < ns; ++k) {
+        const uint32_t e = k * V + chunk_of<W>(s, k, m, vmask);
+        if (C.mintop[e] != ct) continue;
+        const uint32_t q1 = C.cand_off[e + 1];
+        for (uint32_t q = C.cand_off[e]; q < q1; ++q) {
+            const int g = C.cand_list[q];
+            const uint8_t *sg = C.src + (size_t)g * ns;
+            const uint16_t *ig = C.img + (size_t)g * ns * V;
+            W img = (W)ct << (top * m);
+            int cmp = 0;   // -1: image < s, +1: image > s
+            for (int a = top - 1; a >= 0; --a) {
+                img |= (W)ig[a * V + chunk_of<W>(s, sg[a], m, vmask)] << (a * m);
+                const W hi = img >> (a * m), hs = s >> (a * m);
+                if (hi != hs) {
+                    cmp = hi < hs ? -1 : 1;
+                    break;
+                }
+            }
+            if (cmp < 0) return false;
+            if (cmp == 0) {
+                ++stab;
+                cr += chi[g].x;
+                ci += chi[g].y;
+            }
+        }
+    }
+    return true;
+}
+
+// ---------------------------------------------------- search: byte tables --
+template <class W>
+__device__ __forceinline__ W tab_image(const uint64_t *tab, int n_chunks, int g, W t) {
+    W img = 0;
+    const uint64_t *tg = tab + (size_t)g * n_chunks * 256;
+    for (int c = 0; c < n_chunks; ++c) img |= (W)tg[c * 256 + ((uint32_t)(t >> (8 * c)) & 255u)];
+    return img;
+}
+
+template <class W>
+__device__ __forceinline__ void tab_search(const uint64_t *tab, int n_chunks, int n_sym, W t,
+                                           W &best, int &u, int &cnt) {
+    best = ~W(0);
+    u = 0;
+    cnt = 0;
+    for (int g = 0; g < n_sym; ++g) {
+        const W img = tab_image<W>(tab, n_chunks, g, t);
+        if (img < best) {
+            best = img;
+            u = g;
+            cnt = 1;
+        } else if (img == best) {
+            ++cnt;
+        }
+    }
+}
+
+template <class W>
+__device__ __forceinline__ bool tab_is_rep(const uint64_t *tab, int n_chunks, int n_sym, W s,
+                                           const double2 *chi, int &stab, double &cr, double &ci) {
+    stab = 0;
+    cr = 0.0;
+    ci = 0.0;
+    for (int g = 0; g < n_sym; ++g) {
+        const W img = tab_image<W>(tab, n_chunks, g, s);
+        if (img < s) return false;
+        if (img == s) {
+            ++stab;
+            cr += chi[g].x;
+            ci += chi[g].y;
+        }
+    }
+    return true;
+}
+
+// Colexicographic unranking of popcount-n states (ascending integer order):
+// rank r = sum_k C(p_k, k+1) over the set bits p_0 < p_1 < ...
+template <class W>
+__device__ __forceinline__ W unrank_colex(uint64_t r, int N, int n, const uint64_t *binom) {
+    W s = 0;
+    int p = N - 1;
+    for (int k = n; k >= 1; --k) {
+        while (binom[p * 65 + k] > r) --p;
+        s |= W(1) << p;
+        r -= binom[p * 65 + k];
+        --p;
+    }
+    return s;
+}
+
+// next larger integer with the same popcount
+template <class W>
+__device__ __forceinline__ W next_same_popcount(W s) {
+    const W lowest = s & (~s + 1);
+    const W ripple = s + lowest;
+    int tz;
+    if constexpr (sizeof(W) == 4)
+        tz = __builtin_ctz(s);
+    else
+        tz = __builtin_ctzll(s);
+    return ripple | (((s ^ ripple) >> 2) >> tz);
+}
+
+}  // namespace xdg

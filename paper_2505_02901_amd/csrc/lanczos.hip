@@ -1,0 +1,701 @@
+// Lanczos iteration on the GPU (eigval0 / eigvals_lanczos, Sec. 3.7.1; the
+// recurrence of Lanczos 1950):
+//   w = H v_j;  alpha_j = Re<v_j, w>;  w -= alpha_j v_j + beta_j v_{j-1};
+//   [optional: classical Gram-Schmidt against all v_i, twice];
+//   beta_{j+1} = |w|;  v_{j+1} = w / beta_{j+1}.
+// Vectors are stored in FP64 or FP32 (complex if the block is); every dot
+// product, norm, coefficient and the three-term update are computed in FP64
+// and rounded once on store.  Reductions use fixed-order block partials, so
+// the scalars are bitwise reproducible.  The scalars live on the device
+// (no host round trip per step); the host reads them back to test
+// convergence and solves the tridiagonal problem with the implicit QL
+// method (Bowdler, Martin, Reinsch and Wilkinson, 1968).
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstring>
+#include <vector>
+
+#include "xdg_internal.hpp"
+
+namespace xdg {
+
+namespace {
+constexpr int RB = 256;    // threads per block of the vector kernels
+constexpr int MAXC = 16;   // scalar columns per row (nvec <= 8, complex)
+
+// Sum over threads that share a column (t = column mod cols, cols a power of
+// two dividing RB); sh[0 .. cols) holds the block totals afterwards.
+__device__ inline void block_col_reduce(double *sh, int cols) {
+    for (int s = RB / 2; s >= cols; s >>= 1) {
+        __syncthreads();
+        if ((int)threadIdx.x < s) sh[threadIdx.x] += sh[threadIdx.x + s];
+    }
+    __syncthreads();
+}
+
+// partials[block][c] = sum over the block's scalars of column c of a*b.
+// The flat scalar index q has column q % cols because the grid stride is a
+// multiple of cols.
+template <class T>
+__global__ __launch_bounds__(RB) void k_dot(const T *a, const T *b, uint64_t n, int cols,
+                                            double *partials) {
+    __shared__ double sh[RB];
+    double acc = 0.0;
+    const uint64_t stride = (uint64_t)gridDim.x * RB;
+    for (uint64_t q = (uint64_t)blockIdx.x * RB + threadIdx.x; q < n; q += stride)
+        acc += (double)a[q] * (double)b[q];
+    sh[threadIdx.x] = acc;
+    block_col_reduce(sh, cols);
+    if ((int)threadIdx.x < cols) partials[(size_t)blockIdx.x * cols + threadIdx.x] = sh[threadIdx.x];
+}
+
+// Fixed-order total of the partials, pairs of columns combined for complex
+// vectors (Re<a,b> = sum re*re + im*im).  mode 0: out = s; 1: out = sqrt(s).
+// hist (may be null) receives the value at row *jdev.
+__global__ __launch_bounds__(RB) void k_finalize(const double *partials, int n_blocks, int cols,
+                                                 int C, int mode, double *out, double *hist,
+                                                 const int *jdev) {
+    __shared__ double sh[RB];
+    const int c = threadIdx.x % cols;
+    double acc = 0.0;
+    for (int blk = threadIdx.x / cols; blk < n_blocks; blk += RB / cols)
+        acc += partials[(size_t)blk * cols + c];
+    sh[threadIdx.x] = acc;
+    block_col_reduce(sh, cols);
+    if ((int)threadIdx.x < cols / C) {
+        const int v = threadIdx.x;
+        double s = sh[v * C];
+        if (C == 2) s += sh[v * C + 1];
+        const double r = mode == 1 ? sqrt(s) : s;
+        out[v] = r;
+        if (hist) hist[(size_t)(*jdev) * (cols / C) + v] = r;
+    }
+}
+
+// w = w - alpha v - beta vprev (FP64, one rounding), partial |w|^2
+template <class T>
+__global__ __launch_bounds__(RB) void k_update(T *w, const T *v, const T *vprev, uint64_t n,
+                                               int cols, int C, const double *alpha,
+                                               const double *beta, double *partials) {
+    __shared__ double sh[RB];
+    double acc = 0.0;
+    const uint64_t stride = (uint64_t)gridDim.x * RB;
+    for (uint64_t q = (uint64_t)blockIdx.x * RB + threadIdx.x; q < n; q += stride) {
+        const int vec = (int)(q % cols) / C;
+        double x = (double)w[q] - alpha[vec] * (double)v[q];
+        if (vprev) x -= beta[vec] * (double)vprev[q];
+        const T r = (T)x;
+        w[q] = r;
+        acc += (double)r * (double)r;
+    }
+    sh[threadIdx.x] = acc;
+    block_col_reduce(sh, cols);
+    if ((int)threadIdx.x < cols) partials[(size_t)blockIdx.x * cols + threadIdx.x] = sh[threadIdx.x];
+}
+
+// dst = src / beta  (zero where beta vanished: invariant subspace)
+template <class T>
+__global__ __launch_bounds__(RB) void k_scale(const T *src, T *dst, uint64_t n, int cols, int C,
+                                              const double *beta) {
+    const uint64_t stride = (uint64_t)gridDim.x * RB;
+    for (uint64_t q = (uint64_t)blockIdx.x * RB + threadIdx.x; q < n; q += stride) {
+        const double bt = beta[(int)(q % cols) / C];
+        dst[q] = bt > 0.0 ? (T)((double)src[q] / bt) : T(0);
+    }
+}
+
+__global__ void k_step_end(int *jdev, double *prev_beta, const double *cur_beta, int nv) {
+    for (int v = threadIdx.x; v < nv; v += blockDim.x) prev_beta[v] = cur_beta[v];
+    __syncthreads();
+    if (threadIdx.x == 0 && jdev) *jdev += 1;
+}
+
+__global__ void k_set_scalars(int *jdev, double *prev_beta, int nv) {
+    for (int v = threadIdx.x; v < nv; v += blockDim.x) prev_beta[v] = 0.0;
+    if (threadIdx.x == 0) *jdev = 0;
+}
+
+// Reorthogonalisation, single vector.  c_i = <V_i, w> (complex when C = 2)
+// for i < k, accumulated in FP64 over contiguous row ranges per block.
+template <class T, int C>
+__global__ __launch_bounds__(RB) void k_reorth_dots(const T *V, uint64_t ld, int k, const T *w,
+                                                    uint64_t n_rows, double *partials) {
+    __shared__ double sh[RB];
+    const uint64_t per = (n_rows + gridDim.x - 1) / gridDim.x;
+    const uint64_t r0 = (uint64_t)blockIdx.x * per;
+    const uint64_t r1 = r0 + per < n_rows ? r0 + per : n_rows;
+    for (int i = 0; i < k; ++i) {
+        const T *Vi = V + (size_t)i * ld;
+        double re = 0.0, im = 0.0;
+        for (uint64_t r = r0 + threadIdx.x; r < r1; r += RB) {
+            if (C == 1) {
+                re += (double)Vi[r] * (double)w[r];
+            } else {
+                const double a = Vi[2 * r], b = Vi[2 * r + 1], x = w[2 * r], y = w[2 * r + 1];
+                re += a * x + b * y;     // conj(V) w
+                im += a * y - b * x;
+            }
+        }
+        sh[threadIdx.x] = re;
+        block_col_reduce(sh, 1);
+        if (threadIdx.x == 0) partials[((size_t)blockIdx.x * k + i) * 2] = sh[0];
+        __syncthreads();
+        if (C == 2) {
+            sh[threadIdx.x] = im;
+            block_col_reduce(sh, 1);
+            if (threadIdx.x == 0) partials[((size_t)blockIdx.x * k + i) * 2 + 1] = sh[0];
+            __syncthreads();
+        }
+    }
+}
+
+__global__ __launch_bounds__(RB) void k_reorth_finalize(const double *partials, int n_blocks,
+                                                        int k, double *coef) {
+    for (int e = threadIdx.x; e < 2 * k; e += RB) {
+        double s = 0.0;
+        for (int b = 0; b < n_blocks; ++b) s += partials[(size_t)b * 2 * k + e];
+        coef[e] = s;
+    }
+}
+
+// w -= sum_i c_i V_i
+template <class T, int C>
+__global__ __launch_bounds__(RB) void k_reorth_sub(const T *V, uint64_t ld, int k,
+                                                   const double *coef, T *w, uint64_t n_rows) {
+    const uint64_t stride = (uint64_t)gridDim.x * RB;
+    for (uint64_t r = (uint64_t)blockIdx.x * RB + threadIdx.x; r < n_rows; r += stride) {
+        if (C == 1) {
+            double x = w[r];
+            for (int i = 0; i < k; ++i) x -= coef[2 * i] * (double)V[(size_t)i * ld + r];
+            w[r] = (T)x;
+        } else {
+            double x = w[2 * r], y = w[2 * r + 1];
+            for (int i = 0; i < k; ++i) {
+                const double a = V[(size_t)i * ld + 2 * r], b = V[(size_t)i * ld + 2 * r + 1];
+                const double cr = coef[2 * i], ci = coef[2 * i + 1];
+                x -= cr * a - ci * b;
+                y -= cr * b + ci * a;
+            }
+            w[2 * r] = (T)x;
+            w[2 * r + 1] = (T)y;
+        }
+    }
+}
+
+int vec_grid(uint64_t n) {
+    const uint64_t want = (n + RB - 1) / RB;
+    return (int)std::max<uint64_t>(1, std::min<uint64_t>(want, (uint64_t)device_cu_count() * 8));
+}
+
+// One family of vector kernels for a dtype.
+struct VecOps {
+    bool single;
+    int cols, C;
+    uint64_t n;        // scalars per vector block
+    int grid;
+    double *partials;  // [grid][cols]
+    hipStream_t st;
+
+    int dot(const void *a, const void *b) const {
+        if (single)
+            hipLaunchKernelGGL(k_dot<float>, dim3(grid), dim3(RB), 0, st, (const float *)a,
+                               (const float *)b, n, cols, partials);
+        else
+            hipLaunchKernelGGL(k_dot<double>, dim3(grid), dim3(RB), 0, st, (const double *)a,
+                               (const double *)b, n, cols, partials);
+        XDG_TRY_HIP(hipGetLastError());
+        return XDG_OK;
+    }
+    int finalize(int mode, double *out, double *hist, const int *jdev) const {
+        hipLaunchKernelGGL(k_finalize, dim3(1), dim3(RB), 0, st, partials, grid, cols, C, mode,
+                           out, hist, jdev);
+        XDG_TRY_HIP(hipGetLastError());
+        return XDG_OK;
+    }
+    int update(void *w, const void *v, const void *vprev, const double *alpha,
+               const double *beta) const {
+        if (single)
+            hipLaunchKernelGGL(k_update<float>, dim3(grid), dim3(RB), 0, st, (float *)w,
+                               (const float *)v, (const float *)vprev, n, cols, C, alpha, beta,
+                               partials);
+        else
+            hipLaunchKernelGGL(k_update<double>, dim3(grid), dim3(RB), 0, st, (double *)w,
+                               (const double *)v, (const double *)vprev, n, cols, C, alpha, beta,
+                               partials);
+        XDG_TRY_HIP(hipGetLastError());
+        return XDG_OK;
+    }
+    int scale(const void *src, void *dst, const double *beta) const {
+        if (single)
+            hipLaunchKernelGGL(k_scale<float>, dim3(grid), dim3(RB), 0, st, (const float *)src,
+                               (float *)dst, n, cols, C, beta);
+        else
+            hipLaunchKernelGGL(k_scale<double>, dim3(grid), dim3(RB), 0, st, (const double *)src,
+                               (double *)dst, n, cols, C, beta);
+        XDG_TRY_HIP(hipGetLastError());
+        return XDG_OK;
+    }
+};
+
+thread_local double g_t_total = 0.0, g_t_apply = 0.0;
+
+}  // namespace
+
+// Eigenvalues of the symmetric tridiagonal matrix (alpha on the diagonal,
+// beta[i] coupling i and i+1), ascending, by implicit QL with shifts taken
+// from the leading 2x2 block (Bowdler, Martin, Reinsch, Wilkinson 1968).
+void tridiag_eigenvalues(int m, const double *alpha, const double *beta, std::vector<double> &out) {
+    std::vector<double> d(alpha, alpha + m), e(m, 0.0);
+    for (int i = 0; i + 1 < m; ++i) e[i] = beta[i];
+    for (int l = 0; l < m; ++l) {
+        for (int sweep = 0; sweep < 200; ++sweep) {
+            int q = l;
+            while (q < m - 1) {
+                const double scale = std::fabs(d[q]) + std::fabs(d[q + 1]);
+                if (std::fabs(e[q]) <= 1e-16 * scale) break;
+                ++q;
+            }
+            if (q == l) break;
+            double g = (d[l + 1] - d[l]) / (2.0 * e[l]);
+            double r = std::hypot(g, 1.0);
+            g = d[q] - d[l] + e[l] / (g + (g >= 0 ? r : -r));
+            double s = 1.0, c = 1.0, p = 0.0;
+            bool split = false;
+            for (int i = q - 1; i >= l; --i) {
+                const double f = s * e[i], bb = c * e[i];
+                r = std::hypot(f, g);
+                e[i + 1] = r;
+                if (r == 0.0) {
+                    d[i + 1] -= p;
+                    e[q] = 0.0;
+                    split = true;
+                    break;
+                }
+                s = f / r;
+                c = g / r;
+                g = d[i + 1] - p;
+                r = (d[i] - g) * s + 2.0 * c * bb;
+                p = s * r;
+                d[i + 1] = g + p;
+                g = c * r - bb;
+            }
+            if (split) continue;
+            d[l] -= p;
+            e[l] = g;
+            e[q] = 0.0;
+        }
+    }
+    std::sort(d.begin(), d.end());
+    out = d;
+}
+
+int lanczos_single(xdg_ham_s *h, const void *v0, int k, double tol, int max_iter, uint64_t seed,
+                   int prec, double *evals, int *n_iter, double *alpha, double *beta,
+                   hipStream_t st, double *t_total, double *t_apply) {
+    const xdg_basis_s *b = h->basis;
+    if (k < 1 || max_iter < 1 || !evals || !n_iter || !(tol >= 0.0)) {
+        set_error("lanczos: need k >= 1, max_iter >= 1, tol >= 0 and output pointers");
+        return XDG_EINVAL;
+    }
+    if (prec < XDG_PREC_F64 || prec > XDG_PREC_F64_REORTH) {
+        set_error("unknown precision form %d", prec);
+        return XDG_EINVAL;
+    }
+    const int64_t D = b->dim;
+    if (D < 1) {
+        set_error("lanczos on an empty block");
+        return XDG_EINVAL;
+    }
+    const bool single = prec == XDG_PREC_F32VEC || prec == XDG_PREC_F32VEC_REORTH;
+    const bool reorth = prec == XDG_PREC_F32VEC_REORTH || prec == XDG_PREC_F64_REORTH;
+    const int C = b->is_complex ? 2 : 1;
+    const int dtype = C == 2 ? (single ? XDG_C64 : XDG_C128) : (single ? XDG_F32 : XDG_F64);
+    const size_t esz = (single ? 4 : 8) * C;
+    const uint64_t nsc = (uint64_t)D * C;
+    const size_t vbytes = (size_t)D * esz;
+
+    DevBuf bufs, wbuf, scal, parts, rparts;
+    // vectors: reorth keeps every v_j (column j of V); otherwise three rotate
+    const int nstore = reorth ? max_iter + 1 : 3;
+    XDG_RETURN_IF(bufs.alloc(vbytes * nstore));
+    XDG_RETURN_IF(wbuf.alloc(vbytes));
+    // scalars: cur_alpha, cur_beta, prev_beta, hist_alpha[max_iter], hist_beta[max_iter], jdev
+    XDG_RETURN_IF(scal.alloc(sizeof(double) * (3 + 2 * (size_t)max_iter + 2 * (size_t)(max_iter + 1)) + 16));
+    double *cur_alpha = scal.as<double>(), *cur_beta = cur_alpha + 1, *prev_beta = cur_alpha + 2;
+    double *hist_a = cur_alpha + 3, *hist_b = hist_a + max_iter;
+    double *coef = hist_b + max_iter;
+    int *jdev = reinterpret_cast<int *>(coef + 2 * (size_t)(max_iter + 1));
+    VecOps ops{single, C, C, nsc, vec_grid(nsc), nullptr, st};
+    XDG_RETURN_IF(parts.alloc(sizeof(double) * (size_t)ops.grid * MAXC));
+    ops.partials = parts.as<double>();
+    const int rgrid = (int)std::min<int64_t>(std::max<int64_t>(1, D / 4096), device_cu_count() * 2);
+    if (reorth) XDG_RETURN_IF(rparts.alloc(sizeof(double) * 2 * (size_t)rgrid * (max_iter + 1)));
+
+    auto vec = [&](int i) -> char * { return bufs.as<char>() + vbytes * i; };
+    char *w = wbuf.as<char>();
+    if (v0)
+        XDG_TRY_HIP(hipMemcpyAsync(vec(0), v0, vbytes, hipMemcpyDeviceToDevice, st));
+    else
+        XDG_RETURN_IF(random_fill((int64_t)nsc, seed, 1, single, vec(0), st));
+    hipLaunchKernelGGL(k_set_scalars, dim3(1), dim3(64), 0, st, jdev, prev_beta, 1);
+    XDG_RETURN_IF(ops.dot(vec(0), vec(0)));
+    XDG_RETURN_IF(ops.finalize(1, cur_beta, nullptr, jdev));
+    XDG_RETURN_IF(ops.scale(vec(0), vec(0), cur_beta));
+
+    // one event pair per iteration around the apply; summed at the end
+    std::vector<hipEvent_t> evs(2 * (size_t)max_iter, nullptr);
+    struct EvGuard {
+        std::vector<hipEvent_t> &e;
+        ~EvGuard() {
+            for (hipEvent_t x : e)
+                if (x) (void)hipEventDestroy(x);
+        }
+    } ev_guard{evs};
+    for (auto &e : evs) XDG_TRY_HIP(hipEventCreate(&e));
+    std::vector<double> ha(max_iter), hb(max_iter), ritz;
+    double prev_k = NAN;
+    int m = 0, status = XDG_ENOCONV;
+    bool stop = false;
+    double apply_s = 0.0;
+    XDG_TRY_HIP(hipStreamSynchronize(st));
+    const auto t0 = std::chrono::steady_clock::now();
+    int iv = 0, ip = -1, in = 1;   // rotating indices (v, vprev, next) when not reorth
+    for (int j = 0; j < max_iter && !stop; ++j) {
+        char *v = reorth ? vec(j) : vec(iv);
+        char *vp = reorth ? (j ? vec(j - 1) : nullptr) : (ip >= 0 ? vec(ip) : nullptr);
+        XDG_TRY_HIP(hipEventRecord(evs[2 * j], st));
+        XDG_RETURN_IF(apply_tuned(h, v, w, 1, dtype, st));
+        XDG_TRY_HIP(hipEventRecord(evs[2 * j + 1], st));
+        XDG_RETURN_IF(ops.dot(v, w));
+        XDG_RETURN_IF(ops.finalize(0, cur_alpha, hist_a, jdev));
+        XDG_RETURN_IF(ops.update(w, v, vp, cur_alpha, prev_beta));
+        if (reorth) {
+            const int kk = j + 1;
+            for (int pass = 0; pass < 2; ++pass) {
+                if (single) {
+                    if (C == 1)
+                        hipLaunchKernelGGL((k_reorth_dots<float, 1>), dim3(rgrid), dim3(RB), 0, st,
+                                           (const float *)vec(0), (uint64_t)nsc, kk,
+                                           (const float *)w, (uint64_t)D, rparts.as<double>());
+                    else
+                        hipLaunchKernelGGL((k_reorth_dots<float, 2>), dim3(rgrid), dim3(RB), 0, st,
+                                           (const float *)vec(0), (uint64_t)nsc, kk,
+                                           (const float *)w, (uint64_t)D, rparts.as<double>());
+                } else {
+                    if (C == 1)
+                        hipLaunchKernelGGL((k_reorth_dots<double, 1>), dim3(rgrid), dim3(RB), 0,
+                                           st, (const double *)vec(0), (uint64_t)nsc, kk,
+                                           (const double *)w, (uint64_t)D, rparts.as<double>());
+                    else
+                        hipLaunchKernelGGL((k_reorth_dots<double, 2>), dim3(rgrid), dim3(RB), 0,
+                                           st, (const double *)vec(0), (uint64_t)nsc, kk,
+                                           (const double *)w, (uint64_t)D, rparts.as<double>());
+                }
+                hipLaunchKernelGGL(k_reorth_finalize, dim3(1), dim3(RB), 0, st,
+                                   rparts.as<double>(), rgrid, kk, coef);
+                const int sgrid = vec_grid((uint64_t)D);
+                if (single) {
+                    if (C == 1)
+                        hipLaunchKernelGGL((k_reorth_sub<float, 1>), dim3(sgrid), dim3(RB), 0, st,
+                                           (const float *)vec(0), (uint64_t)nsc, kk, coef,
+                                           (float *)w, (uint64_t)D);
+                    else
+                        hipLaunchKernelGGL((k_reorth_sub<float, 2>), dim3(sgrid), dim3(RB), 0, st,
+                                           (const float *)vec(0), (uint64_t)nsc, kk, coef,
+                                           (float *)w, (uint64_t)D);
+                } else {
+                    if (C == 1)
+                        hipLaunchKernelGGL((k_reorth_sub<double, 1>), dim3(sgrid), dim3(RB), 0, st,
+                                           (const double *)vec(0), (uint64_t)nsc, kk, coef,
+                                           (double *)w, (uint64_t)D);
+                    else
+                        hipLaunchKernelGGL((k_reorth_sub<double, 2>), dim3(sgrid), dim3(RB), 0, st,
+                                           (const double *)vec(0), (uint64_t)nsc, kk, coef,
+                                           (double *)w, (uint64_t)D);
+                }
+                XDG_TRY_HIP(hipGetLastError());
+            }
+            XDG_RETURN_IF(ops.dot(w, w));
+        }
+        XDG_RETURN_IF(ops.finalize(1, cur_beta, hist_b, jdev));
+        hipLaunchKernelGGL(k_step_end, dim3(1), dim3(64), 0, st, jdev, prev_beta, cur_beta, 1);
+        XDG_TRY_HIP(hipGetLastError());
+        m = j + 1;
+        const bool check = tol > 0.0 || m == max_iter || (m % 16) == 0;
+        if (check) {
+            XDG_TRY_HIP(hipMemcpyAsync(ha.data(), hist_a, sizeof(double) * m,
+                                       hipMemcpyDeviceToHost, st));
+            XDG_TRY_HIP(hipMemcpyAsync(hb.data(), hist_b, sizeof(double) * m,
+                                       hipMemcpyDeviceToHost, st));
+            XDG_TRY_HIP(hipStreamSynchronize(st));
+            float ms = 0;
+            // breakdown anywhere since the last check truncates the run there
+            for (int t = std::max(0, m - 16); t < m; ++t)
+                if (hb[t] <= 1e-13 * std::max(1.0, std::fabs(ha[t])) || !std::isfinite(hb[t])) {
+                    m = t + 1;
+                    stop = true;
+                    status = XDG_OK;
+                    break;
+                }
+            if (!stop && tol > 0.0 && m >= k) {
+                tridiag_eigenvalues(m, ha.data(), hb.data(), ritz);
+                const double th = ritz[k - 1];
+                if (std::isfinite(prev_k) && std::fabs(th - prev_k) <= tol * std::fabs(th)) {
+                    stop = true;
+                    status = XDG_OK;
+                }
+                prev_k = th;
+            }
+            (void)ms;
+        }
+        if (stop) break;
+        if (reorth) {
+            XDG_RETURN_IF(ops.scale(w, vec(j + 1), cur_beta));
+        } else {
+            XDG_RETURN_IF(ops.scale(w, vec(in), cur_beta));
+            ip = iv;
+            iv = in;
+            in = (in + 1) % 3;
+            if (in == ip) in = (in + 1) % 3;
+        }
+    }
+    XDG_TRY_HIP(hipStreamSynchronize(st));
+    const double total =
+        std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+    for (int j = 0; j < m; ++j) {
+        float ms = 0;
+        if (hipEventElapsedTime(&ms, evs[2 * j], evs[2 * j + 1]) == hipSuccess) apply_s += 1e-3 * ms;
+    }
+    XDG_TRY_HIP(hipMemcpy(ha.data(), hist_a, sizeof(double) * m, hipMemcpyDeviceToHost));
+    XDG_TRY_HIP(hipMemcpy(hb.data(), hist_b, sizeof(double) * m, hipMemcpyDeviceToHost));
+    if (tol == 0.0 && !stop) status = XDG_OK;
+    tridiag_eigenvalues(m, ha.data(), hb.data(), ritz);
+    for (int e = 0; e < k; ++e) evals[e] = e < m ? ritz[e] : NAN;
+    *n_iter = m;
+    if (alpha) std::copy(ha.begin(), ha.begin() + m, alpha);
+    if (beta) std::copy(hb.begin(), hb.begin() + m, beta);
+    g_t_total = total;
+    g_t_apply = apply_s;
+    if (t_total) *t_total = total;
+    if (t_apply) *t_apply = apply_s;
+    return status;
+}
+
+// n blocks x nvec recurrences in lockstep; each step (batched apply, then
+// per-block dot / update / norm / scale) is captured once per buffer
+// rotation phase into a HIP graph and replayed.
+int lanczos_batched(int n, xdg_ham_s *const *hams, const void *const *v0s, int64_t nvec,
+                    int n_iter, uint64_t seed, int prec, double *evals, double *alpha,
+                    double *beta, hipStream_t user_st, double *t_total, double *t_apply) {
+    if (n < 1 || n_iter < 1 || !evals) {
+        set_error("batched lanczos: need n >= 1, n_iter >= 1 and evals");
+        return XDG_EINVAL;
+    }
+    if (nvec != 1 && nvec != 2 && nvec != 4 && nvec != 8) {
+        set_error("batched lanczos: nvec must be 1, 2, 4 or 8");
+        return XDG_EINVAL;
+    }
+    if (prec != XDG_PREC_F64 && prec != XDG_PREC_F32VEC) {
+        set_error("batched lanczos supports XDG_PREC_F64 and XDG_PREC_F32VEC");
+        return XDG_EINVAL;
+    }
+    bool any_c = false;
+    for (int i = 0; i < n; ++i) {
+        if (!hams[i] || hams[i]->basis->dim < 1) {
+            set_error("batched lanczos: block %d is null or empty", i);
+            return XDG_EINVAL;
+        }
+        any_c |= hams[i]->basis->is_complex;
+    }
+    const bool single = prec == XDG_PREC_F32VEC;
+    const int C = any_c ? 2 : 1;
+    const int dtype = any_c ? (single ? XDG_C64 : XDG_C128) : (single ? XDG_F32 : XDG_F64);
+    const size_t ssz = single ? 4 : 8;
+    const int cols = (int)nvec * C;
+
+    hipStream_t st = user_st;
+    hipStream_t own = nullptr;
+    if (!st) {
+        XDG_TRY_HIP(hipStreamCreateWithFlags(&own, hipStreamNonBlocking));
+        st = own;
+    }
+    struct Sec {
+        DevBuf buf, parts, scal;
+        uint64_t nsc;
+        VecOps ops;
+        double *cur_a, *cur_b, *prev_b, *hist_a, *hist_b;
+    };
+    std::vector<Sec> S(n);
+    DevBuf jbuf;
+    XDG_RETURN_IF(jbuf.alloc(16));
+    int *jdev = jbuf.as<int>();
+    for (int i = 0; i < n; ++i) {
+        Sec &s = S[i];
+        const int64_t D = hams[i]->basis->dim;
+        s.nsc = (uint64_t)D * cols;
+        XDG_RETURN_IF(s.buf.alloc(ssz * s.nsc * 4));   // v0, v1, v2 (rotating) + w
+        s.ops = VecOps{single, cols, C, s.nsc, vec_grid(s.nsc), nullptr, st};
+        XDG_RETURN_IF(s.parts.alloc(sizeof(double) * (size_t)s.ops.grid * MAXC));
+        s.ops.partials = s.parts.as<double>();
+        XDG_RETURN_IF(s.scal.alloc(sizeof(double) * (3 * nvec + 2 * (size_t)n_iter * nvec)));
+        s.cur_a = s.scal.as<double>();
+        s.cur_b = s.cur_a + nvec;
+        s.prev_b = s.cur_b + nvec;
+        s.hist_a = s.prev_b + nvec;
+        s.hist_b = s.hist_a + (size_t)n_iter * nvec;
+        char *v = s.buf.as<char>();
+        if (v0s && v0s[i])
+            XDG_TRY_HIP(hipMemcpyAsync(v, v0s[i], ssz * s.nsc, hipMemcpyDeviceToDevice, st));
+        else
+            XDG_RETURN_IF(random_fill((int64_t)s.nsc, seed + (uint64_t)i, 1, single, v, st));
+        hipLaunchKernelGGL(k_set_scalars, dim3(1), dim3(64), 0, st, jdev, s.prev_b, (int)nvec);
+        XDG_RETURN_IF(s.ops.dot(v, v));
+        XDG_RETURN_IF(s.ops.finalize(1, s.cur_b, nullptr, jdev));
+        XDG_RETURN_IF(s.ops.scale(v, v, s.cur_b));
+    }
+    auto vecp = [&](int i, int slot) -> char * { return S[i].buf.as<char>() + ssz * S[i].nsc * slot; };
+    // phase p: v = slot p, vprev = slot (p+2)%3 (none at j = 0), next = slot (p+1)%3, w = slot 3
+    BatchPlan plans[3];
+    std::vector<xdg_ham_s *> hv(hams, hams + n);
+    for (int p = 0; p < 3; ++p) {
+        std::vector<const void *> xs(n);
+        std::vector<void *> ys(n);
+        for (int i = 0; i < n; ++i) {
+            xs[i] = vecp(i, p);
+            ys[i] = vecp(i, 3);
+        }
+        XDG_RETURN_IF(batch_prepare(n, hv.data(), xs.data(), ys.data(), nvec, dtype, &plans[p]));
+    }
+    // choose the persistent grid once (outside capture): a few sizes, timed
+    int best_grid = device_cu_count() * 8;
+    {
+        hipEvent_t e0, e1;
+        XDG_TRY_HIP(hipEventCreate(&e0));
+        XDG_TRY_HIP(hipEventCreate(&e1));
+        float best = 1e30f;
+        for (int mult : {4, 8, 16}) {
+            const int g = device_cu_count() * mult;
+            XDG_RETURN_IF(batch_launch(plans[0], g, 8, st));
+            XDG_TRY_HIP(hipEventRecord(e0, st));
+            XDG_RETURN_IF(batch_launch(plans[0], g, 8, st));
+            XDG_TRY_HIP(hipEventRecord(e1, st));
+            XDG_TRY_HIP(hipEventSynchronize(e1));
+            float ms = 0;
+            XDG_TRY_HIP(hipEventElapsedTime(&ms, e0, e1));
+            if (ms < best) {
+                best = ms;
+                best_grid = g;
+            }
+        }
+        (void)hipEventDestroy(e0);
+        (void)hipEventDestroy(e1);
+    }
+    auto enqueue_step = [&](int p, bool first) -> int {
+        XDG_RETURN_IF(batch_launch(plans[p], best_grid, 8, st));
+        for (int i = 0; i < n; ++i) {
+            Sec &s = S[i];
+            char *v = vecp(i, p), *w = vecp(i, 3);
+            char *vp = first ? nullptr : vecp(i, (p + 2) % 3);
+            XDG_RETURN_IF(s.ops.dot(v, w));
+            XDG_RETURN_IF(s.ops.finalize(0, s.cur_a, s.hist_a, jdev));
+            XDG_RETURN_IF(s.ops.update(w, v, vp, s.cur_a, s.prev_b));
+            XDG_RETURN_IF(s.ops.finalize(1, s.cur_b, s.hist_b, jdev));
+            XDG_RETURN_IF(s.ops.scale(w, vecp(i, (p + 1) % 3), s.cur_b));
+            hipLaunchKernelGGL(k_step_end, dim3(1), dim3(64), 0, st, (int *)nullptr, s.prev_b,
+                               s.cur_b, (int)nvec);
+        }
+        // one counter for all blocks; k_step_end with a null counter only copies beta
+        hipLaunchKernelGGL(k_step_end, dim3(1), dim3(64), 0, st, jdev, S[0].prev_b, S[0].cur_b,
+                           (int)nvec);
+        XDG_TRY_HIP(hipGetLastError());
+        return XDG_OK;
+    };
+    XDG_TRY_HIP(hipStreamSynchronize(st));
+    const auto t0 = std::chrono::steady_clock::now();
+    // step 0 runs eagerly (it has no v_{j-1}); later steps replay graphs
+    XDG_RETURN_IF(enqueue_step(0, true));
+    hipGraphExec_t exec[3] = {nullptr, nullptr, nullptr};
+    hipGraph_t graphs[3] = {nullptr, nullptr, nullptr};
+    int rc = XDG_OK;
+    for (int p = 0; p < 3 && rc == XDG_OK && n_iter > 1; ++p) {
+        XDG_TRY_HIP(hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal));
+        rc = enqueue_step(p, false);
+        hipError_t e = hipStreamEndCapture(st, &graphs[p]);
+        if (rc == XDG_OK && e != hipSuccess) {
+            set_error("graph capture failed: %s", hipGetErrorString(e));
+            rc = XDG_EHIP;
+        }
+        if (rc == XDG_OK) {
+            e = hipGraphInstantiate(&exec[p], graphs[p], nullptr, nullptr, 0);
+            if (e != hipSuccess) {
+                set_error("graph instantiation failed: %s", hipGetErrorString(e));
+                rc = XDG_EHIP;
+            }
+        }
+    }
+    for (int j = 1; j < n_iter && rc == XDG_OK; ++j) {
+        hipError_t e = hipGraphLaunch(exec[j % 3], st);
+        if (e != hipSuccess) {
+            set_error("graph launch failed: %s", hipGetErrorString(e));
+            rc = XDG_EHIP;
+        }
+    }
+    if (rc == XDG_OK) {
+        hipError_t e = hipStreamSynchronize(st);
+        if (e != hipSuccess) {
+            set_error("batched lanczos: %s", hipGetErrorString(e));
+            rc = XDG_EHIP;
+        }
+    }
+    const double total =
+        std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+    for (int p = 0; p < 3; ++p) {
+        if (exec[p]) (void)hipGraphExecDestroy(exec[p]);
+        if (graphs[p]) (void)hipGraphDestroy(graphs[p]);
+    }
+    if (rc == XDG_OK) {
+        std::vector<double> ha((size_t)n_iter * nvec), hb((size_t)n_iter * nvec), a1(n_iter),
+            b1(n_iter), ritz;
+        for (int i = 0; i < n && rc == XDG_OK; ++i) {
+            if (hipMemcpy(ha.data(), S[i].hist_a, sizeof(double) * ha.size(),
+                          hipMemcpyDeviceToHost) != hipSuccess ||
+                hipMemcpy(hb.data(), S[i].hist_b, sizeof(double) * hb.size(),
+                          hipMemcpyDeviceToHost) != hipSuccess) {
+                set_error("batched lanczos: copy of the tridiagonal matrices failed");
+                rc = XDG_EHIP;
+                break;
+            }
+            for (int v = 0; v < nvec; ++v) {
+                int m = n_iter;
+                for (int j = 0; j < n_iter; ++j) {
+                    a1[j] = ha[(size_t)j * nvec + v];
+                    b1[j] = hb[(size_t)j * nvec + v];
+                    if (alpha) alpha[((size_t)i * nvec + v) * n_iter + j] = a1[j];
+                    if (beta) beta[((size_t)i * nvec + v) * n_iter + j] = b1[j];
+                }
+                for (int j = 0; j < n_iter; ++j)
+                    if (b1[j] <= 1e-13 * std::max(1.0, std::fabs(a1[j])) || !std::isfinite(b1[j])) {
+                        m = j + 1;
+                        break;
+                    }
+                tridiag_eigenvalues(m, a1.data(), b1.data(), ritz);
+                evals[(size_t)i * nvec + v] = ritz[0];
+            }
+        }
+    }
+    if (own) (void)hipStreamDestroy(own);
+    g_t_total = total;
+    g_t_apply = 0.0;
+    if (t_total) *t_total = total;
+    if (t_apply) *t_apply = 0.0;
+    return rc;
+}
+
+int last_timing(double *total, double *apply) {
+    if (total) *total = g_t_total;
+    if (apply) *apply = g_t_apply;
+    return XDG_OK;
+}
+
+}  // namespace xdg

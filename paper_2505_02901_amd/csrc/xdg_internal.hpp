@@ -1,0 +1,224 @@
+// Internal declarations of the MI355X library behind include/xdg.h.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <atomic>
+#include <cstdint>
+#include <map>
+#include <memory>
+#include <string>
+#include <tuple>
+#include <vector>
+
+#include "xdg.h"
+
+namespace xdg {
+
+// ---------------------------------------------------------------- errors --
+void set_error(const char *fmt, ...);
+const char *get_error();
+
+#define XDG_TRY_HIP(expr)                                                          \
+    do {                                                                           \
+        hipError_t e_ = (expr);                                                    \
+        if (e_ != hipSuccess) {                                                    \
+            ::xdg::set_error("%s failed: %s (%s:%d)", #expr, hipGetErrorString(e_), \
+                             __FILE__, __LINE__);                                  \
+            return e_ == hipErrorOutOfMemory ? XDG_ENOMEM : XDG_EHIP;              \
+        }                                                                          \
+    } while (0)
+
+#define XDG_RETURN_IF(err)        \
+    do {                          \
+        int r_ = (err);           \
+        if (r_ != XDG_OK) return r_; \
+    } while (0)
+
+// Device allocation that owns its memory.
+struct DevBuf {
+    void *p = nullptr;
+    size_t bytes = 0;
+    DevBuf() = default;
+    DevBuf(const DevBuf &) = delete;
+    DevBuf &operator=(const DevBuf &) = delete;
+    ~DevBuf() { release(); }
+    void release() {
+        if (p) (void)hipFree(p);
+        p = nullptr;
+        bytes = 0;
+    }
+    int alloc(size_t n);                      // XDG_OK / XDG_ENOMEM
+    int upload(const void *host, size_t n);   // alloc + copy
+    template <class T> T *as() const { return static_cast<T *>(p); }
+};
+
+// ------------------------------------------------------- search tables --
+// Sublattice-coding tables (built on the host, uploaded once).
+//   sites are blocks of m bits, block q = bits [q m, (q+1) m); top = n_s - 1.
+//   src[g][a]      : block of t feeding block a of g.t
+//   img[g][a][v]   : m-bit image chunk for block a when the source chunk is v
+//   mintop[k][v]   : min over g with src[g][top] = k of img[g][top][v]
+//   cand_off[k][v] : offsets into cand_list (size n_s*(2^m)+1)
+//   cand_list      : group elements reaching mintop[k][v], ascending
+struct SublatticeTables {
+    int n_s = 0, m = 0;
+    std::vector<uint8_t> src;        // [n_sym][n_s]
+    std::vector<uint16_t> img;       // [n_sym][n_s][2^m]
+    std::vector<uint16_t> mintop;    // [n_s][2^m]
+    std::vector<uint32_t> cand_off;  // [n_s * 2^m + 1]
+    std::vector<uint16_t> cand_list; // [cand_off.back()]
+};
+
+// Generic byte tables: tab[g][c][v] = image bits of byte c of t having value v.
+struct ByteTables {
+    int n_chunks = 0;
+    std::vector<uint64_t> tab;       // [n_sym][n_chunks][256]
+};
+
+// Affine (ring) elements: g(i) = (eps*i + a) mod N.
+struct AffineElem {
+    int32_t a;
+    int32_t eps;
+};
+
+struct Plan {
+    int kind = XDG_SEARCH_U1;
+    SublatticeTables sub;
+    ByteTables bytes;
+    std::vector<AffineElem> aff;
+};
+
+int validate_group(int n_sites, int n_sym, const int32_t *perm, const double *chi);
+int validate_bonds(int n_sites, int n_sym, const int32_t *perm, int n_bonds, const int32_t *sites,
+                   const double *jz, const double *jxy);
+int make_plan(int n_sites, int n_sym, const int32_t *perm, const xdg_basis_opts *opts, Plan *plan,
+              bool build_tables);
+uint64_t binomial(int n, int k);
+
+// ---------------------------------------------------------------- basis --
+struct DeviceSearch {
+    // device copies of the search tables (pointers into DevBufs of the basis)
+    const uint8_t *src = nullptr;
+    const uint16_t *img = nullptr;
+    const uint16_t *mintop = nullptr;
+    const uint32_t *cand_off = nullptr;
+    const uint16_t *cand_list = nullptr;
+    const uint64_t *bytetab = nullptr;
+    const AffineElem *aff = nullptr;
+    int n_s = 0, m = 0, n_chunks = 0;
+    uint32_t lds_sub_bytes = 0;   // bytes of mintop + cand_off + cand_list staged in LDS
+};
+
+struct HashIndex {
+    uint64_t n_lines = 0;   // 64-byte lines
+    int slots = 0;          // 8 (32-bit keys) or 5 (64-bit keys)
+};
+
+}  // namespace xdg
+
+struct xdg_basis_s {
+    std::atomic<int> refs{1};
+    int device = 0;
+    int n_sites = 0, n_up = 0, n_sym = 0;
+    bool wide = false;          // 64-bit state words (n_sites > 32)
+    bool is_complex = false;
+    int64_t dim = 0;
+    std::vector<int32_t> perm;  // [n_sym][n_sites]
+    std::vector<double> chi;    // [n_sym][2]
+    xdg::Plan plan;
+    // device data
+    xdg::DevBuf reps;           // u32/u64 [dim]
+    xdg::DevBuf stab;           // u16 [dim]  |Stab(s)|
+    xdg::DevBuf hash;           // 64-byte lines
+    xdg::HashIndex hidx;
+    xdg::DevBuf lin;            // u32 [2^nlo + 2^nhi] Lin tables (U(1))
+    int lin_nlo = 0, lin_nhi = 0;
+    xdg::DevBuf t_src, t_img, t_mintop, t_candoff, t_candlist, t_bytes, t_aff;
+    xdg::DevBuf chi_d;          // double2 [n_sym]
+    xdg::DevBuf chi_f;          // float2 [n_sym]
+    xdg::DevBuf sqrt_d;         // double [n_sym+1] sqrt(c), then [n_sym+1] 1/sqrt(c)
+    xdg::DevBuf sqrt_f;         // float, same layout
+    xdg::DeviceSearch dsearch;
+};
+
+namespace xdg {
+struct TuneKey {
+    int dtype;
+    int64_t nvec;
+    bool operator<(const TuneKey &o) const {
+        return std::tie(dtype, nvec) < std::tie(o.dtype, o.nvec);
+    }
+};
+struct LaunchCfg {
+    int block = 256;       // threads per workgroup
+    int grid = 0;          // workgroups (persistent grid); 0 = one row per lane
+    int nv = 1;            // vectors per pass (<= nvec)
+};
+}  // namespace xdg
+
+struct xdg_ham_s {
+    xdg_basis_s *basis = nullptr;
+    int n_bonds = 0;
+    std::vector<int32_t> sites;
+    std::vector<double> jz, jxy;
+    xdg::DevBuf bonds_d;        // BondD [n_bonds]
+    xdg::DevBuf bonds_f;        // BondF [n_bonds]
+    int64_t nnz = -1;
+    std::map<xdg::TuneKey, xdg::LaunchCfg> tuned;
+};
+
+namespace xdg {
+
+struct BondD {
+    uint32_t i, j;
+    double jz, h;   // h = jxy / 2
+};
+struct BondF {
+    uint32_t i, j;
+    float jz, h;
+};
+
+int basis_build_device(xdg_basis_s *b);                 // enumerate + index
+int basis_lookup(xdg_basis_s *b, const uint64_t *d_states, int64_t n, int64_t *d_idx,
+                 hipStream_t st);
+int ham_count_nnz(xdg_ham_s *h, int64_t *nnz);
+
+int apply_launch(xdg_ham_s *h, const void *x, void *y, int64_t nvec, int dtype, hipStream_t st,
+                 const LaunchCfg *cfg);
+int apply_tuned(xdg_ham_s *h, const void *x, void *y, int64_t nvec, int dtype, hipStream_t st);
+int apply_batched_launch(int n, xdg_ham_s *const *hams, const void *const *xs, void *const *ys,
+                         int64_t nvec, int dtype, hipStream_t st, uint32_t *d_queue,
+                         int grid, int block);
+// Batched persistent launch plan: device copies of the sector descriptors
+// and the cumulative tile counts; the queue counter is zeroed by a kernel
+// (not a memset) so that the launch can be captured into a graph.
+struct BatchPlan {
+    DevBuf descs, prefix, queue;
+    int n = 0, kind = 0;
+    bool wide = false, single = false, cplx = false;
+    int64_t cols = 0;
+    uint32_t n_tiles = 0, tile_rows = 0;
+    size_t lds = 0;
+    int stage_sub = 1;
+};
+int batch_prepare(int n, xdg_ham_s *const *hams, const void *const *xs, void *const *ys,
+                  int64_t nvec, int dtype, BatchPlan *P);
+int batch_launch(const BatchPlan &P, int grid, int nv_cap, hipStream_t st);
+int lanczos_single(xdg_ham_s *h, const void *v0, int k, double tol, int max_iter, uint64_t seed,
+                   int prec, double *evals, int *n_iter, double *alpha, double *beta,
+                   hipStream_t st, double *t_total, double *t_apply);
+int lanczos_batched(int n, xdg_ham_s *const *hams, const void *const *v0s, int64_t nvec,
+                    int n_iter, uint64_t seed, int prec, double *evals, double *alpha,
+                    double *beta, hipStream_t st, double *t_total, double *t_apply);
+void tridiag_eigenvalues(int m, const double *alpha, const double *beta, std::vector<double> &out);
+
+int random_fill(int64_t n_scalars, uint64_t seed, int kind, bool single, void *out,
+                hipStream_t st);
+int device_cu_count();
+
+size_t dtype_size(int dtype);
+bool dtype_complex(int dtype);
+bool dtype_single(int dtype);
+
+}  // namespace xdg

@@ -1,0 +1,406 @@
+"""ctypes binding of ``include/xdg.h`` (argument marshalling only).
+
+Every function keeps the C name; handles are ``ctypes.c_void_p``; vectors
+are torch tensors on the GPU (or raw device pointers as ints).  Every step
+of the computation runs in ``libxdg.so``; if the library is not built this
+module refuses to load.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+from typing import Optional, Sequence, Tuple
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libxdg.so")
+
+XDG_OK, XDG_EINVAL, XDG_EGROUP, XDG_ECHAR, XDG_ENOTSYM, XDG_ENOMEM, XDG_EHIP, XDG_ENOCONV = (
+    0, -1, -2, -3, -4, -5, -6, -7)
+XDG_F64, XDG_F32, XDG_C128, XDG_C64 = 0, 1, 2, 3
+XDG_SEARCH_AUTO, XDG_SEARCH_U1, XDG_SEARCH_AFFINE, XDG_SEARCH_SUBLATTICE, XDG_SEARCH_TABLE = (
+    0, 1, 2, 3, 4)
+XDG_PREC_F64, XDG_PREC_F32VEC, XDG_PREC_F32VEC_REORTH, XDG_PREC_F64_REORTH = 0, 1, 2, 3
+
+ERROR_NAMES = {0: "XDG_OK", -1: "XDG_EINVAL", -2: "XDG_EGROUP", -3: "XDG_ECHAR",
+               -4: "XDG_ENOTSYM", -5: "XDG_ENOMEM", -6: "XDG_EHIP", -7: "XDG_ENOCONV"}
+
+
+class XdgError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"{ERROR_NAMES.get(code, code)}: {msg}")
+        self.code = code
+
+
+class BasisOpts(C.Structure):
+    _fields_ = [("search", C.c_int), ("n_sublattices", C.c_int), ("reserved", C.c_int * 6)]
+
+
+_lib = None
+
+
+def lib():
+    """The loaded HIP library (raises if it has not been built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is missing: build it with "
+                               "`python -m paper_2505_02901_amd.build` (there is no fallback)")
+        L = C.CDLL(LIB_PATH)
+        P, I, I64, D, U64 = C.c_void_p, C.c_int, C.c_int64, C.c_double, C.c_uint64
+        sig = {
+            "xdg_version": (C.c_char_p, []),
+            "xdg_last_error": (C.c_char_p, []),
+            "xdg_check_group": (I, [I, I, P, P]),
+            "xdg_check_bonds": (I, [I, I, P, I, P, P, P]),
+            "xdg_plan_search": (I, [I, I, P, P, P, P]),
+            "xdg_create_basis": (I, [I, I, I, P, P, P, P]),
+            "xdg_destroy_basis": (None, [P]),
+            "xdg_basis_dim": (I, [P, P]),
+            "xdg_basis_is_complex": (I, [P, P]),
+            "xdg_basis_search_kind": (I, [P, P, P]),
+            "xdg_basis_copy_states": (I, [P, I64, I64, P]),
+            "xdg_basis_copy_stabilisers": (I, [P, I64, I64, P]),
+            "xdg_basis_index": (I, [P, P, I64, P]),
+            "xdg_create_hamiltonian": (I, [P, I, P, P, P, P]),
+            "xdg_destroy_hamiltonian": (None, [P]),
+            "xdg_ham_nnz": (I, [P, P]),
+            "xdg_apply": (I, [P, P, P, I64, I, P]),
+            "xdg_apply_batched": (I, [I, P, P, P, I64, I, P]),
+            "xdg_random_state": (I, [I64, I64, U64, I, I, P, P]),
+            "xdg_lanczos_eigval": (I, [P, P, I, D, I, U64, I, P, P, P, P, P]),
+            "xdg_lanczos_eigval_batched": (I, [I, P, P, I64, I, U64, I, P, P, P, P]),
+            "xdg_last_lanczos_timing": (I, [P, P]),
+        }
+        for name, (res, args) in sig.items():
+            f = getattr(L, name)
+            f.restype = res
+            f.argtypes = args
+        _lib = L
+    return _lib
+
+
+def exported_names():
+    return ["xdg_version", "xdg_last_error", "xdg_check_group", "xdg_check_bonds",
+            "xdg_plan_search", "xdg_create_basis", "xdg_destroy_basis", "xdg_basis_dim",
+            "xdg_basis_is_complex", "xdg_basis_search_kind", "xdg_basis_copy_states",
+            "xdg_basis_copy_stabilisers", "xdg_basis_index", "xdg_create_hamiltonian",
+            "xdg_destroy_hamiltonian", "xdg_ham_nnz", "xdg_apply", "xdg_apply_batched",
+            "xdg_random_state", "xdg_lanczos_eigval", "xdg_lanczos_eigval_batched",
+            "xdg_last_lanczos_timing"]
+
+
+def _check(rc: int, allow=(XDG_OK,)):
+    if rc not in allow:
+        raise XdgError(rc, xdg_last_error())
+    return rc
+
+
+def _arr(a, dtype):
+    if a is None:
+        return None, None
+    a = np.ascontiguousarray(a, dtype=dtype)
+    return a, a.ctypes.data_as(C.c_void_p)
+
+
+def _chi_arr(chi, n_sym):
+    if chi is None:
+        return None, None
+    chi = np.asarray(chi)
+    if np.iscomplexobj(chi) or chi.ndim == 1:
+        c = np.empty((n_sym, 2), np.float64)
+        c[:, 0] = np.real(chi)
+        c[:, 1] = np.imag(chi)
+    else:
+        c = np.asarray(chi, np.float64).reshape(n_sym, 2)
+    return _arr(c, np.float64)
+
+
+def _ptr(t) -> Optional[int]:
+    if t is None:
+        return None
+    if isinstance(t, int):
+        return t
+    return t.data_ptr()
+
+
+def _stream(stream) -> Optional[int]:
+    if stream is None:
+        try:
+            import torch
+            if torch.cuda.is_available():
+                return torch.cuda.current_stream().cuda_stream
+        except Exception:  # pragma: no cover
+            pass
+        return None
+    if isinstance(stream, int):
+        return stream
+    return stream.cuda_stream
+
+
+def _dtype_code(t) -> int:
+    import torch
+    m = {torch.float64: XDG_F64, torch.float32: XDG_F32, torch.complex128: XDG_C128,
+         torch.complex64: XDG_C64}
+    if t.dtype not in m:
+        raise TypeError(f"unsupported dtype {t.dtype}")
+    return m[t.dtype]
+
+
+# ------------------------------------------------------------------ C names --
+
+def xdg_version() -> str:
+    return lib().xdg_version().decode()
+
+
+def xdg_last_error() -> str:
+    return lib().xdg_last_error().decode()
+
+
+def xdg_check_group(n_sites: int, perm, chi=None) -> int:
+    perm, pp = _arr(perm, np.int32)
+    n_sym = 0 if perm is None else perm.shape[0]
+    chi, pc = _chi_arr(chi, n_sym)
+    return lib().xdg_check_group(n_sites, n_sym, pp, pc)
+
+
+def xdg_check_bonds(n_sites: int, perm, sites, jz, jxy) -> int:
+    perm, pp = _arr(perm, np.int32)
+    n_sym = 0 if perm is None else perm.shape[0]
+    sites, ps = _arr(sites, np.int32)
+    jz, pz = _arr(jz, np.float64)
+    jxy, px = _arr(jxy, np.float64)
+    return lib().xdg_check_bonds(n_sites, n_sym, pp, len(jz), ps, pz, px)
+
+
+def xdg_plan_search(n_sites: int, perm, search: int = 0, n_sublattices: int = 0):
+    perm, pp = _arr(perm, np.int32)
+    n_sym = 0 if perm is None else perm.shape[0]
+    o = BasisOpts(search, n_sublattices)
+    k, ns = C.c_int(), C.c_int()
+    _check(lib().xdg_plan_search(n_sites, n_sym, pp, C.byref(o), C.byref(k), C.byref(ns)))
+    return k.value, ns.value
+
+
+def xdg_create_basis(n_sites: int, n_up: int, perm=None, chi=None, search: int = 0,
+                     n_sublattices: int = 0):
+    perm, pp = _arr(perm, np.int32)
+    n_sym = 0 if perm is None else perm.shape[0]
+    chi, pc = _chi_arr(chi, n_sym)
+    o = BasisOpts(search, n_sublattices)
+    h = C.c_void_p()
+    _check(lib().xdg_create_basis(n_sites, n_up, n_sym, pp, pc, C.byref(o), C.byref(h)))
+    return h
+
+
+def xdg_destroy_basis(b) -> None:
+    lib().xdg_destroy_basis(b)
+
+
+def xdg_basis_dim(b) -> int:
+    d = C.c_int64()
+    _check(lib().xdg_basis_dim(b, C.byref(d)))
+    return d.value
+
+
+def xdg_basis_is_complex(b) -> bool:
+    v = C.c_int()
+    _check(lib().xdg_basis_is_complex(b, C.byref(v)))
+    return bool(v.value)
+
+
+def xdg_basis_search_kind(b) -> Tuple[int, int]:
+    k, ns = C.c_int(), C.c_int()
+    _check(lib().xdg_basis_search_kind(b, C.byref(k), C.byref(ns)))
+    return k.value, ns.value
+
+
+def xdg_basis_copy_states(b, begin: int = 0, count: Optional[int] = None) -> np.ndarray:
+    if count is None:
+        count = xdg_basis_dim(b) - begin
+    out = np.empty(max(count, 0), np.uint64)
+    _check(lib().xdg_basis_copy_states(b, begin, count, out.ctypes.data_as(C.c_void_p)))
+    return out
+
+
+def xdg_basis_copy_stabilisers(b, begin: int = 0, count: Optional[int] = None) -> np.ndarray:
+    if count is None:
+        count = xdg_basis_dim(b) - begin
+    out = np.empty(max(count, 0), np.int32)
+    _check(lib().xdg_basis_copy_stabilisers(b, begin, count, out.ctypes.data_as(C.c_void_p)))
+    return out
+
+
+def xdg_basis_index(b, states) -> np.ndarray:
+    s, ps = _arr(np.atleast_1d(np.asarray(states, dtype=np.uint64)), np.uint64)
+    out = np.empty(len(s), np.int64)
+    _check(lib().xdg_basis_index(b, ps, len(s), out.ctypes.data_as(C.c_void_p)))
+    return out
+
+
+def xdg_create_hamiltonian(b, sites, jz, jxy):
+    sites, ps = _arr(sites, np.int32)
+    jz, pz = _arr(jz, np.float64)
+    jxy, px = _arr(jxy, np.float64)
+    h = C.c_void_p()
+    _check(lib().xdg_create_hamiltonian(b, len(jz), ps, pz, px, C.byref(h)))
+    return h
+
+
+def xdg_destroy_hamiltonian(h) -> None:
+    lib().xdg_destroy_hamiltonian(h)
+
+
+def xdg_ham_nnz(h) -> int:
+    n = C.c_int64()
+    _check(lib().xdg_ham_nnz(h, C.byref(n)))
+    return n.value
+
+
+def xdg_apply(h, x, y, nvec: Optional[int] = None, dtype: Optional[int] = None, stream=None):
+    if nvec is None:
+        nvec = 1 if x.dim() == 1 else int(x.shape[1])
+    if dtype is None:
+        dtype = _dtype_code(x)
+    _check(lib().xdg_apply(h, _ptr(x), _ptr(y), nvec, dtype, _stream(stream)))
+
+
+def xdg_apply_batched(hams: Sequence, xs: Sequence, ys: Sequence, nvec: Optional[int] = None,
+                      dtype: Optional[int] = None, stream=None):
+    n = len(hams)
+    if nvec is None:
+        nvec = 1 if xs[0].dim() == 1 else int(xs[0].shape[1])
+    if dtype is None:
+        dtype = _dtype_code(xs[0])
+    H = (C.c_void_p * n)(*[h.value if isinstance(h, C.c_void_p) else h for h in hams])
+    X = (C.c_void_p * n)(*[_ptr(x) for x in xs])
+    Y = (C.c_void_p * n)(*[_ptr(y) for y in ys])
+    _check(lib().xdg_apply_batched(n, H, X, Y, nvec, dtype, _stream(stream)))
+
+
+def xdg_random_state(out, seed: int, kind: int = 1, nvec: Optional[int] = None, stream=None):
+    nvec = nvec or (1 if out.dim() == 1 else int(out.shape[1]))
+    dim = int(out.shape[0])
+    _check(lib().xdg_random_state(dim, nvec, seed, kind, _dtype_code(out), _ptr(out),
+                                  _stream(stream)))
+
+
+def xdg_lanczos_eigval(h, k: int = 1, tol: float = 1e-12, max_iter: int = 300, seed: int = 0,
+                       prec: int = XDG_PREC_F64, v0=None, stream=None):
+    """Returns (status, evals, alpha, beta)."""
+    ev = np.zeros(k, np.float64)
+    al = np.zeros(max_iter, np.float64)
+    be = np.zeros(max_iter, np.float64)
+    nit = C.c_int()
+    rc = lib().xdg_lanczos_eigval(h, _ptr(v0), k, tol, max_iter, seed, prec,
+                                  ev.ctypes.data_as(C.c_void_p), C.byref(nit),
+                                  al.ctypes.data_as(C.c_void_p), be.ctypes.data_as(C.c_void_p),
+                                  _stream(stream))
+    _check(rc, allow=(XDG_OK, XDG_ENOCONV))
+    n = nit.value
+    return rc, ev, al[:n].copy(), be[:n].copy()
+
+
+def xdg_lanczos_eigval_batched(hams: Sequence, nvec: int, n_iter: int, seed: int = 0,
+                               prec: int = XDG_PREC_F32VEC, v0s=None, stream=None):
+    """Returns (evals [n, nvec], alpha [n, nvec, n_iter], beta [...])."""
+    n = len(hams)
+    ev = np.zeros(n * nvec, np.float64)
+    al = np.zeros(n * nvec * n_iter, np.float64)
+    be = np.zeros(n * nvec * n_iter, np.float64)
+    H = (C.c_void_p * n)(*[h.value if isinstance(h, C.c_void_p) else h for h in hams])
+    V = None if v0s is None else (C.c_void_p * n)(*[_ptr(v) for v in v0s])
+    _check(lib().xdg_lanczos_eigval_batched(n, H, V, nvec, n_iter, seed, prec,
+                                            ev.ctypes.data_as(C.c_void_p),
+                                            al.ctypes.data_as(C.c_void_p),
+                                            be.ctypes.data_as(C.c_void_p), _stream(stream)))
+    return ev.reshape(n, nvec), al.reshape(n, nvec, n_iter), be.reshape(n, nvec, n_iter)
+
+
+def xdg_last_lanczos_timing() -> Tuple[float, float]:
+    t, a = C.c_double(), C.c_double()
+    _check(lib().xdg_last_lanczos_timing(C.byref(t), C.byref(a)))
+    return t.value, a.value
+
+
+# ----------------------------------------------------------- thin wrappers --
+
+class Basis:
+    """Owning wrapper of an ``xdg_basis`` handle."""
+
+    def __init__(self, n_sites: int, n_up: int, perm=None, chi=None, search: int = 0,
+                 n_sublattices: int = 0):
+        self.handle = xdg_create_basis(n_sites, n_up, perm, chi, search, n_sublattices)
+        self.n_sites = n_sites
+        self.n_up = n_up
+
+    @classmethod
+    def from_model(cls, m, **kw) -> "Basis":
+        return cls(m.n_sites, m.n_up, m.perm, m.chi, **kw)
+
+    @property
+    def dim(self) -> int:
+        return xdg_basis_dim(self.handle)
+
+    @property
+    def is_complex(self) -> bool:
+        return xdg_basis_is_complex(self.handle)
+
+    @property
+    def search_kind(self) -> Tuple[int, int]:
+        return xdg_basis_search_kind(self.handle)
+
+    def states(self, begin: int = 0, count: Optional[int] = None) -> np.ndarray:
+        return xdg_basis_copy_states(self.handle, begin, count)
+
+    def stabilisers(self, begin: int = 0, count: Optional[int] = None) -> np.ndarray:
+        return xdg_basis_copy_stabilisers(self.handle, begin, count)
+
+    def index(self, states) -> np.ndarray:
+        return xdg_basis_index(self.handle, states)
+
+    def close(self):
+        if getattr(self, "handle", None) is not None and self.handle.value:
+            xdg_destroy_basis(self.handle)
+            self.handle = C.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Hamiltonian:
+    """Owning wrapper of an ``xdg_ham`` handle."""
+
+    def __init__(self, basis: Basis, sites, jz, jxy):
+        self.basis = basis
+        self.handle = xdg_create_hamiltonian(basis.handle, sites, jz, jxy)
+
+    @classmethod
+    def from_model(cls, basis: Basis, m) -> "Hamiltonian":
+        return cls(basis, m.sites, m.jz, m.jxy)
+
+    @property
+    def nnz(self) -> int:
+        return xdg_ham_nnz(self.handle)
+
+    def apply(self, x, y, stream=None):
+        xdg_apply(self.handle, x, y, stream=stream)
+        return y
+
+    def lanczos(self, **kw):
+        return xdg_lanczos_eigval(self.handle, **kw)
+
+    def close(self):
+        if getattr(self, "handle", None) is not None and self.handle.value:
+            xdg_destroy_hamiltonian(self.handle)
+            self.handle = C.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

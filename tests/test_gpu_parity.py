@@ -1,0 +1,266 @@
+"""GPU parity: the HIP path (through the C ABI) against the CPU oracle.
+
+Bases, stabilisers and indices must be bit-exact; y = H x must agree with
+the oracle to 1e-12 relative (max-norm) in FP64 / complex128 and to 2e-6 in
+FP32 / complex64 (FP32 accumulation over at most ~150 terms of O(1) size;
+unit round-off 6e-8).  Sizes span many 256-row tiles and a ragged tail.
+"""
+import numpy as np
+import pytest
+
+import oracle
+import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module")
+def X():
+    import paper_2505_02901_amd as X
+    X.lib()
+    assert torch.cuda.is_available()
+    return X
+
+
+TOL64 = 1e-12
+TOL32 = 2e-6
+
+
+def sector_models():
+    out = [W.chain_model(12), W.chain_model(20), W.chain_model(17, n_up=6)]   # U(1)
+    out += [W.chain_model(12, l=l) for l in range(12)]                          # affine, real+complex
+    out += [W.chain_model(24, l=l) for l in (0, 5, 12)]
+    chi = np.ones(2 * 14, dtype=np.complex128)
+    chi[14:] = -1
+    out.append(W.chain_model(14).with_sector(W.chain_dihedral(14), chi, "dihedral14_odd"))
+    out += [W.torus_model((4, 0), (0, 4), 1.0, 0.5, ir) for ir in ("A1", "A2", "B1", "B2")]
+    out += [W.torus_model((4, 2), (-2, 4), 1.0, 0.0, "A1", reflections=False, n_up=n)
+            for n in (10, 7)]
+    out += [W.torus_model((6, 0), (0, 4), 1.0, 0.3, "A1", rotations=False, name="rect24")]
+    out += [W.torus_model((6, 0), (0, 4), 1.0, 0.3, "B1", rotations=False, name="rect24b")]
+    return out
+
+
+MODELS = sector_models()
+IDS = [f"{i}-{m.name}-n{m.n_up}" for i, m in enumerate(MODELS)]
+_cache = {}
+
+
+def oracle_basis(m):
+    key = id(m)
+    if key not in _cache:
+        _cache[key] = oracle.basis(m)
+    return _cache[key]
+
+
+def gpu_apply(X, H, x, dtype):
+    xt = torch.from_numpy(np.ascontiguousarray(x)).to("cuda", dtype)
+    yt = torch.empty_like(xt)
+    H.apply(xt, yt)
+    torch.cuda.synchronize()
+    return yt.cpu().numpy()
+
+
+def rel_err(a, b):
+    return np.max(np.abs(a - b)) / max(np.max(np.abs(b)), 1e-300)
+
+
+@pytest.mark.parametrize("m", MODELS, ids=IDS)
+def test_basis_bit_exact(X, m):
+    b = X.Basis.from_model(m)
+    want = oracle_basis(m)
+    got = b.states()
+    assert b.dim == len(want)
+    assert np.array_equal(got, want)
+    if m.perm is not None:
+        stab = np.array([oracle.rep(m.n_sites, m.perm, int(s))[2] for s in want[:2000]])
+        assert np.array_equal(b.stabilisers(0, len(stab)), stab)
+    # index: every basis state maps to its position
+    assert np.array_equal(b.index(want), np.arange(len(want)))
+    # and random popcount-n states map to the oracle's answer (-1 if not a rep)
+    rng = np.random.default_rng(7)
+    probes = []
+    for _ in range(3000):
+        bits = rng.choice(m.n_sites, m.n_up, replace=False)
+        probes.append(int(sum(1 << int(q) for q in bits)))
+    probes += [(1 << m.n_sites) - 1, 0, int(want[-1]) + 1]
+    want_idx = np.array([oracle.index(want, s) for s in probes])
+    assert np.array_equal(b.index(probes), want_idx)
+
+
+@pytest.mark.parametrize("m", MODELS, ids=IDS)
+def test_apply_matches_oracle(X, m):
+    b = X.Basis.from_model(m)
+    H = X.Hamiltonian.from_model(b, m)
+    basis = oracle_basis(m)
+    D = len(basis)
+    cplx = m.is_complex
+    for nvec in (1, 3):
+        x = W.random_vector(11 + nvec, D, nvec, kind="uniform", complex_=cplx)
+        y_or = oracle.apply(m, basis, x)
+        if not cplx:
+            assert np.max(np.abs(y_or.imag)) < 1e-12 * max(1, np.max(np.abs(y_or)))
+            y_or = y_or.real
+        dt64 = torch.complex128 if cplx else torch.float64
+        dt32 = torch.complex64 if cplx else torch.float32
+        y64 = gpu_apply(X, H, x, dt64)
+        assert rel_err(y64, y_or) < TOL64, (m.name, nvec)
+        y32 = gpu_apply(X, H, x, dt32)
+        assert rel_err(y32, y_or) < TOL32, (m.name, nvec)
+    if not cplx:
+        # complex vectors on a real block: real and imaginary parts independently
+        x = W.random_vector(5, D, 2, kind="gauss", complex_=True)
+        yc = gpu_apply(X, H, x, torch.complex128)
+        assert rel_err(yc, oracle.apply(m, basis, x)) < TOL64
+
+
+def test_apply_nvec8_and_determinism(X):
+    m = W.chain_model(24, l=7)
+    b = X.Basis.from_model(m)
+    H = X.Hamiltonian.from_model(b, m)
+    basis = oracle_basis(m)
+    x = W.random_vector(3, len(basis), 8, kind="gauss", complex_=True)
+    y1 = gpu_apply(X, H, x, torch.complex64)
+    y2 = gpu_apply(X, H, x, torch.complex64)
+    assert np.array_equal(y1, y2)
+    assert rel_err(y1, oracle.apply(m, basis, x)) < TOL32
+    # single-vector columns give bit-identical results (same per-row order)
+    y_col = gpu_apply(X, H, np.ascontiguousarray(x[:, 3]), torch.complex64)
+    assert np.array_equal(y_col, y1[:, 3])
+
+
+def test_batched_apply_equals_single(X):
+    ms = [W.chain_model(16, l=l) for l in range(16)]
+    bs = [X.Basis.from_model(m) for m in ms]
+    hs = [X.Hamiltonian.from_model(b, m) for b, m in zip(bs, ms)]
+    xs, ys, ref = [], [], []
+    for i, (b, h) in enumerate(zip(bs, hs)):
+        x = torch.from_numpy(W.random_vector(100 + i, b.dim, 4, complex_=True)).to("cuda", torch.complex64)
+        xs.append(x)
+        ys.append(torch.empty_like(x))
+        yr = torch.empty_like(x)
+        h.apply(x, yr)
+        ref.append(yr)
+    X.xdg_apply_batched([h.handle for h in hs], xs, ys)
+    torch.cuda.synchronize()
+    for y, r in zip(ys, ref):
+        assert torch.equal(y, r)
+
+
+def test_random_state_matches_generator(X):
+    for kind, name in ((0, "uniform"), (1, "gauss")):
+        t = torch.empty(1000, 3, dtype=torch.float64, device="cuda")
+        X.xdg_random_state(t, 99, kind)
+        want = W.random_vector(99, 1000, 3, kind=name)
+        got = t.cpu().numpy()
+        if kind == 0:
+            assert np.array_equal(got, want)
+        else:
+            assert np.max(np.abs(got - want)) < 1e-13
+
+
+def test_nnz_count(X):
+    m = W.chain_model(16)
+    b = X.Basis.from_model(m)
+    H = X.Hamiltonian.from_model(b, m)
+    # every row has 16 bonds; off-diagonal terms = bonds with unequal spins
+    basis = oracle_basis(m)
+    T = sum(len(oracle.row_terms(m, int(s))[1]) for s in basis)
+    assert H.nnz == len(basis) + T == 12870 + 109824
+
+
+def test_empty_and_degenerate_blocks(X):
+    # n_up = 0 and n_up = N: one state
+    for n_up in (0, 10):
+        m = W.chain_model(10, n_up=n_up, l=0)
+        b = X.Basis.from_model(m)
+        assert b.dim == 1
+        H = X.Hamiltonian.from_model(b, m)
+        x = np.ones(1)
+        assert abs(gpu_apply(X, H, x, torch.float64)[0] - 10 * 0.25) < 1e-15
+    # an empty sector: n_up = 1 on a ring at k != 0 has dim 1, k = 0 too; take a
+    # stabiliser-incompatible sector: all-up ring at k = 1
+    m = W.chain_model(6, n_up=6, l=1)
+    b = X.Basis.from_model(m)
+    assert b.dim == 0 == len(oracle_basis(m))
+    H = X.Hamiltonian.from_model(b, m)
+    e = torch.empty(0, dtype=torch.complex128, device="cuda")
+    H.apply(e, torch.empty(0, dtype=torch.complex128, device="cuda"))
+
+
+def test_apply_argument_errors(X):
+    m = W.chain_model(8, l=1)
+    b = X.Basis.from_model(m)
+    H = X.Hamiltonian.from_model(b, m)
+    x = torch.zeros(b.dim, dtype=torch.float64, device="cuda")
+    with pytest.raises(X.XdgError):          # real vector on a complex block
+        H.apply(x, torch.zeros_like(x))
+    xc = torch.zeros(b.dim, dtype=torch.complex128, device="cuda")
+    with pytest.raises(X.XdgError):          # x == y
+        X.xdg_apply(H.handle, xc, xc)
+    with pytest.raises(X.XdgError):          # bonds not invariant
+        X.Hamiltonian(b, m.sites[:-1], m.jz[:-1], m.jxy[:-1])
+    with pytest.raises(X.XdgError):
+        X.Basis(8, 9)
+
+
+@pytest.mark.parametrize("prec,tol", [(0, 1e-12), (1, 1e-7)])
+def test_lanczos_chain16_bethe(X, prec, tol):
+    m = W.chain_model(16)
+    b = X.Basis.from_model(m)
+    H = X.Hamiltonian.from_model(b, m)
+    e_bethe = -7.142296360617     # Bethe ansatz, pinned in test_oracle_pins
+    st, ev, al, be = H.lanczos(k=1, tol=1e-13 if prec == 0 else 1e-9, max_iter=300, seed=1,
+                               prec=prec)
+    assert abs(ev[0] - e_bethe) < tol * abs(e_bethe), (ev[0], len(al))
+
+
+def test_lanczos_matches_oracle_sequence(X):
+    m = W.chain_model(20, l=3)
+    basis = oracle_basis(m)
+    b = X.Basis.from_model(m)
+    H = X.Hamiltonian.from_model(b, m)
+    x0 = W.random_vector(21, len(basis), 1, kind="gauss", complex_=True)
+    st_o, ev_o, al_o, be_o = oracle.lanczos(m, basis, x0, k=2, tol=0.0, max_iter=40)
+    v0 = torch.from_numpy(x0).to("cuda", torch.complex128)
+    st, ev, al, be = H.lanczos(k=2, tol=0.0, max_iter=40, prec=0, v0=v0)
+    assert len(al) == len(al_o) == 40
+    # early recurrence coefficients agree to rounding; Ritz values to 1e-12
+    assert np.max(np.abs(al[:10] - al_o[:10])) < 1e-11
+    assert np.max(np.abs(be[:10] - be_o[:10])) < 1e-11
+    assert np.max(np.abs(ev - ev_o)) < 1e-11 * np.max(np.abs(ev_o))
+
+
+def test_lanczos_reorth_and_breakdown(X):
+    m = W.torus_model((4, 2), (-2, 4), 1.0, 0.0, "A1", reflections=False)
+    basis = oracle_basis(m)
+    Hd = oracle.apply(m, basis, np.eye(len(basis), dtype=np.complex128)).real
+    want = np.linalg.eigvalsh(Hd)
+    b = X.Basis.from_model(m)
+    H = X.Hamiltonian.from_model(b, m)
+    for prec in (3, 2):
+        st, ev, al, be = H.lanczos(k=3, tol=1e-14, max_iter=min(len(basis), 120), seed=4,
+                                   prec=prec)
+        tol = 1e-10 if prec == 3 else 1e-5
+        assert np.max(np.abs(ev - want[:3])) < tol, (prec, ev, want[:3])
+    # ferromagnetic state in the fully polarised sector: H v = E v at once,
+    # beta_1 = 0 terminates after one step
+    m2 = W.chain_model(8, n_up=8, l=0)
+    b2 = X.Basis.from_model(m2)
+    H2 = X.Hamiltonian.from_model(b2, m2)
+    st, ev, al, be = H2.lanczos(k=1, tol=1e-12, max_iter=50, seed=3, prec=0)
+    assert st == 0 and len(al) == 1 and abs(ev[0] - 2.0) < 1e-14
+
+
+def test_batched_lanczos_matches_single(X):
+    ms = [W.chain_model(12, l=l) for l in range(12)]
+    bs = [X.Basis.from_model(m) for m in ms]
+    hs = [X.Hamiltonian.from_model(b, m) for b, m in zip(bs, ms)]
+    ev, al, be = X.xdg_lanczos_eigval_batched([h.handle for h in hs], nvec=4, n_iter=60, seed=9,
+                                              prec=1)
+    for i, (m, b) in enumerate(zip(ms, bs)):
+        basis = oracle_basis(m)
+        e0 = np.linalg.eigvalsh(oracle.apply(m, basis, np.eye(len(basis), dtype=complex)))[0]
+        assert np.max(np.abs(ev[i] - e0)) < 1e-6 * max(1, abs(e0)), (i, ev[i], e0)

@@ -1,0 +1,130 @@
+"""Host-side behaviour of the C-ABI library (CPU only: no compute call).
+
+* the shared library loads and exports every function include/xdg.h declares;
+* group / character / bond validation and its error codes
+  (Sec. 3.10.1 group axioms, Sec. 3.10.2 homomorphism, invariance of H);
+* the search-kind planner on the benchmark lattices.
+"""
+import os
+import re
+
+import numpy as np
+import pytest
+
+import workloads as W
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+@pytest.fixture(scope="module")
+def X():
+    import paper_2505_02901_amd as X
+    X.lib()
+    return X
+
+
+def header_functions():
+    txt = open(os.path.join(ROOT, "include", "xdg.h")).read()
+    txt = re.sub(r"/\*.*?\*/", "", txt, flags=re.S)
+    return sorted(set(re.findall(r"\b(xdg_[a-z0-9_]+)\s*\(", txt)))
+
+
+def test_exports_every_declared_symbol(X):
+    names = header_functions()
+    assert len(names) >= 20
+    L = X.lib()
+    for n in names:
+        assert hasattr(L, n), n
+    assert sorted(X.exported_names()) == names
+    assert X.xdg_version().startswith("xdg-mi355x")
+
+
+def test_group_validation_errors(X):
+    m = W.chain_model(8, l=2)
+    assert X.xdg_check_group(8, m.perm, m.chi) == X.XDG_OK
+    assert X.xdg_check_group(8, m.perm, None) == X.XDG_OK
+    # not a bijection
+    p = m.perm.copy()
+    p[3, 0] = p[3, 1]
+    assert X.xdg_check_group(8, p, None) == X.XDG_EINVAL
+    # site out of range
+    p = m.perm.copy()
+    p[2, 4] = 8
+    assert X.xdg_check_group(8, p, None) == X.XDG_EINVAL
+    # no identity
+    assert X.xdg_check_group(8, m.perm[1:], None) == X.XDG_EGROUP
+    # not closed (T^0, T^1 only)
+    assert X.xdg_check_group(8, m.perm[:2], None) == X.XDG_EGROUP
+    # duplicate element
+    assert X.xdg_check_group(8, np.vstack([m.perm, m.perm[3:4]]), None) == X.XDG_EGROUP
+    # missing inverse but closed is impossible for finite sets; a set closed
+    # under products with an inverse removed is not closed either
+    assert X.xdg_check_group(8, np.delete(m.perm, 3, axis=0), None) == X.XDG_EGROUP
+    # characters: |chi| != 1
+    c = m.chi.copy()
+    c[0] = 1.5
+    assert X.xdg_check_group(8, m.perm, c) == X.XDG_ECHAR
+    # characters: homomorphism violated
+    c = m.chi.copy()
+    c[1] = np.conj(c[1])
+    assert X.xdg_check_group(8, m.perm, c) == X.XDG_ECHAR
+    # the k = pi characters printed in Sec. 3.10.2 pass
+    chi = np.array([1.0, -1.0, 1.0, -1.0, 1.0, -1.0, 1.0, -1.0])
+    assert X.xdg_check_group(8, W.chain_translations(8), chi) == X.XDG_OK
+    assert X.xdg_check_group(0, None, None) == X.XDG_EINVAL
+    assert X.xdg_check_group(65, None, None) == X.XDG_EINVAL
+
+
+def test_bond_validation_errors(X):
+    m = W.chain_model(8, l=0)
+    assert X.xdg_check_bonds(8, m.perm, m.sites, m.jz, m.jxy) == X.XDG_OK
+    s = m.sites.copy()
+    s[0, 1] = s[0, 0]
+    assert X.xdg_check_bonds(8, m.perm, s, m.jz, m.jxy) == X.XDG_EINVAL
+    s = m.sites.copy()
+    s[0, 1] = 9
+    assert X.xdg_check_bonds(8, m.perm, s, m.jz, m.jxy) == X.XDG_EINVAL
+    jz = m.jz.copy()
+    jz[2] = 0.5
+    assert X.xdg_check_bonds(8, m.perm, m.sites, jz, m.jxy) == X.XDG_ENOTSYM
+    # open chain is not translation invariant
+    assert X.xdg_check_bonds(8, m.perm, m.sites[:-1], m.jz[:-1], m.jxy[:-1]) == X.XDG_ENOTSYM
+    # reversed bond orientation and duplicated bonds with split couplings are fine
+    s = m.sites[:, ::-1].copy()
+    assert X.xdg_check_bonds(8, m.perm, s, m.jz, m.jxy) == X.XDG_OK
+    s2 = np.vstack([m.sites, m.sites])
+    assert X.xdg_check_bonds(8, m.perm, s2, np.r_[m.jz, m.jz] / 2, np.r_[m.jxy, m.jxy] / 2) == 0
+    # no group: any bond list of distinct in-range sites is fine
+    assert X.xdg_check_bonds(8, None, m.sites[:-1], m.jz[:-1], m.jxy[:-1]) == X.XDG_OK
+
+
+def test_planner_kinds(X):
+    assert X.xdg_plan_search(16, None) == (X.XDG_SEARCH_U1, 0)
+    assert X.xdg_plan_search(32, W.chain_translations(32)) == (X.XDG_SEARCH_AFFINE, 0)
+    assert X.xdg_plan_search(12, W.chain_dihedral(12)) == (X.XDG_SEARCH_AFFINE, 0)
+    c3 = W.workload("square36_j1j2_A1")[0]
+    assert c3.n_sym == 288
+    assert X.xdg_plan_search(36, c3.perm) == (X.XDG_SEARCH_SUBLATTICE, 4)
+    c5 = W.workload("tilted40_xxz")[0]
+    assert c5.n_sym == 160
+    assert X.xdg_plan_search(40, c5.perm) == (X.XDG_SEARCH_SUBLATTICE, 4)
+    # forced kinds
+    assert X.xdg_plan_search(32, W.chain_translations(32), X.XDG_SEARCH_TABLE)[0] == X.XDG_SEARCH_TABLE
+    with pytest.raises(X.XdgError):
+        X.xdg_plan_search(36, c3.perm, X.XDG_SEARCH_AFFINE)
+    with pytest.raises(X.XdgError):
+        X.xdg_plan_search(32, W.chain_translations(32), X.XDG_SEARCH_SUBLATTICE)
+    # a random relabelling destroys the block structure: generic tables
+    rng = np.random.default_rng(0)
+    perm = rng.permutation(36)
+    inv = np.argsort(perm)
+    relab = np.array([perm[g[inv]] for g in c3.perm], dtype=np.int32)
+    assert X.xdg_check_group(36, relab, None) == 0
+    assert X.xdg_plan_search(36, relab)[0] == X.XDG_SEARCH_TABLE
+
+
+def test_benchmark_lattices_are_symmetric(X):
+    for name in ("chain16_u1", "chain32_k0_kpi", "square36_j1j2_A1", "tilted40_xxz"):
+        for m in W.workload(name):
+            assert X.xdg_check_group(m.n_sites, m.perm, m.chi) == 0, name
+            assert X.xdg_check_bonds(m.n_sites, m.perm, m.sites, m.jz, m.jxy) == 0, name
