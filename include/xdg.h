@@ -76,9 +76,14 @@ typedef struct xdg_ham_s *xdg_ham;
 /* Options for xdg_create_basis; pass NULL for defaults (all zero). */
 typedef struct xdg_basis_opts {
     int search;          /* XDG_SEARCH_*; 0 = auto */
-    int n_sublattices;   /* for XDG_SEARCH_SUBLATTICE: 2..5; 0 = detect */
-    int reserved[6];     /* must be zero */
+    int n_sublattices;   /* for XDG_SEARCH_SUBLATTICE: 2..8; 0 = detect */
+    int flags;           /* XDG_FLAG_* bits */
+    int reserved[5];     /* must be zero */
 } xdg_basis_opts;
+
+/* flags: sublattice search done by each lane alone instead of the default
+ * wave-cooperative search (same results; for testing and comparison) */
+#define XDG_FLAG_LANE_SEARCH 1
 
 /* Version string of the library (cf. the version banner, Sec. 2). */
 const char *xdg_version(void);

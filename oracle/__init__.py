@@ -50,6 +50,9 @@ def _load():
         lib.orc_apply.restype = C.c_int
         lib.orc_apply.argtypes = [C.c_int, C.c_int, P, P, C.c_int, P, P, P, P, C.c_int64,
                                   C.c_int64, P, P]
+        lib.orc_apply_rows.restype = C.c_int
+        lib.orc_apply_rows.argtypes = [C.c_int, C.c_int, P, P, C.c_int, P, P, P, P, C.c_int64,
+                                       P, C.c_int64, C.c_int64, P, P]
         lib.orc_tridiag_eigvals.restype = C.c_int
         lib.orc_tridiag_eigvals.argtypes = [C.c_int, P, P, C.c_int, P]
         lib.orc_lanczos.restype = C.c_int
@@ -144,6 +147,23 @@ def apply(m, basis_list: np.ndarray, x: np.ndarray) -> np.ndarray:
                            _p(jxy), _p(b), len(b), nvec, _p(xc), _p(y))
     if rc != 0:
         raise RuntimeError("orc_apply failed")
+    return y[:, 0] if squeeze else y
+
+
+def apply_rows(m, basis_list: np.ndarray, rows: np.ndarray, x: np.ndarray) -> np.ndarray:
+    """(H x)[rows]; x of shape [dim] or [dim, nvec]."""
+    perm, chi, sites, jz, jxy = _model_arrays(m)
+    b = np.ascontiguousarray(basis_list, dtype=np.uint64)
+    r = np.ascontiguousarray(rows, dtype=np.int64)
+    squeeze = x.ndim == 1
+    xc = np.ascontiguousarray(x.reshape(len(b), -1), dtype=np.complex128)
+    nvec = xc.shape[1]
+    y = np.zeros((len(r), nvec), np.complex128)
+    rc = _load().orc_apply_rows(m.n_sites, m.n_sym, _p(perm), _p(chi), len(jz), _p(sites),
+                                _p(jz), _p(jxy), _p(b), len(b), _p(r), len(r), nvec, _p(xc),
+                                _p(y))
+    if rc != 0:
+        raise RuntimeError("orc_apply_rows failed")
     return y[:, 0] if squeeze else y
 
 

@@ -293,6 +293,42 @@ int orc_apply(int n_sites, int n_sym, const int32_t *perm, const double *chi,
     return err ? -1 : 0;
 }
 
+/* y[k] = (H x)[rows[k]] for selected rows only (same arithmetic as
+   orc_apply, row by row); x complex128 [dim][nvec], y [n_rows][nvec]. */
+int orc_apply_rows(int n_sites, int n_sym, const int32_t *perm, const double *chi,
+                   int n_bonds, const int32_t *sites, const double *jz, const double *jxy,
+                   const uint64_t *basis, int64_t dim, const int64_t *rows, int64_t n_rows,
+                   int64_t nvec, const double *x, double *y) {
+    const cplx *xc = (const cplx *)x;
+    cplx *yc = (cplx *)y;
+    int err = 0;
+#pragma omp parallel
+    {
+        uint64_t *tg = (uint64_t *)malloc(sizeof(uint64_t) * (size_t)(n_bonds + 1));
+        double *am = (double *)malloc(sizeof(double) * 2 * (size_t)(n_bonds + 1));
+#pragma omp for schedule(dynamic, 64)
+        for (int64_t k = 0; k < n_rows; ++k) {
+            const int64_t row = rows[k];
+            if (row < 0 || row >= dim) { err = 1; continue; }
+            double d;
+            int nt = orc_row_terms(n_sites, n_sym, perm, chi, n_bonds, sites, jz, jxy,
+                                   basis[row], &d, tg, am, n_bonds + 1);
+            if (nt < 0) { err = 1; continue; }
+            for (int64_t v = 0; v < nvec; ++v) {
+                cplx acc = d * xc[row * nvec + v];
+                for (int q = 0; q < nt; ++q) {
+                    int64_t col = orc_index(basis, dim, tg[q]);
+                    if (col < 0) { err = 1; continue; }
+                    acc += (am[2 * q] + I * am[2 * q + 1]) * xc[col * nvec + v];
+                }
+                yc[k * nvec + v] = acc;
+            }
+        }
+        free(tg); free(am);
+    }
+    return err ? -1 : 0;
+}
+
 /* ------------------------------------------------------------------------ */
 /* Symmetric tridiagonal eigenvalues by Sturm-sequence bisection.            */
 /* T has diagonal a[0..m) and off-diagonal b[0..m-1) (b[i] couples i, i+1).  */

@@ -11,6 +11,13 @@ namespace xdg {
 
 size_t lds_limit();
 
+// dynamic LDS available to the apply kernels: the device limit minus the
+// static shared data (sector descriptor, tile counter)
+static size_t lds_budget() {
+    const size_t stat = sizeof(SectorDesc) + 64;
+    return lds_limit() > stat ? lds_limit() - stat : 0;
+}
+
 size_t dtype_size(int dtype) {
     switch (dtype) {
         case XDG_F64: return 8;
@@ -22,6 +29,9 @@ size_t dtype_size(int dtype) {
 }
 bool dtype_complex(int dtype) { return dtype == XDG_C128 || dtype == XDG_C64; }
 bool dtype_single(int dtype) { return dtype == XDG_F32 || dtype == XDG_C64; }
+
+// persistent apply grid of `mult` 1024-lane equivalents per compute unit
+int apply_grid_for(int mult) { return device_cu_count() * mult * BLOCKS_PER_1024; }
 
 namespace {
 
@@ -53,15 +63,20 @@ SectorDesc make_desc(const xdg_ham_s *h, bool single, const void *x, void *y) {
     d.n_sym = b->n_sym;
     d.n_bonds = h->n_bonds;
     d.aff = b->t_aff.as<AffineElem>();
+    d.ring = b->plan.ring;
+    d.ring_gidx = b->t_ring.as<int16_t>();
     d.bytetab = b->t_bytes.as<uint64_t>();
     d.n_bchunks = b->plan.bytes.n_chunks;
     d.mintop = b->t_mintop.as<uint16_t>();
     d.cand_off = b->t_candoff.as<uint32_t>();
     d.cand_list = b->t_candlist.as<uint16_t>();
     d.src = b->t_src.as<uint8_t>();
-    d.img = b->t_img.as<uint16_t>();
+    d.pid = b->t_pid.as<uint16_t>();
+    d.tperm = b->t_tperm.as<uint16_t>();
     d.n_s = b->plan.sub.n_s;
     d.m = b->plan.sub.m;
+    d.pb = b->plan.sub.pb;
+    d.n_perm = b->plan.sub.n_perm;
     d.n_cand = (uint32_t)b->plan.sub.cand_list.size();
     d.bonds = single ? h->bonds_f.p : h->bonds_d.p;
     d.chi = single ? b->chi_f.p : b->chi_d.p;
@@ -116,9 +131,9 @@ int apply_launch(xdg_ham_s *h, const void *x, void *y, int64_t nvec, int dtype, 
         return XDG_EINVAL;
     }
     LaunchCfg c = cfg ? *cfg : LaunchCfg{};
-    const unsigned block = 256;
+    const unsigned block = APPLY_BLOCK;
     const int64_t need = (b->dim + block - 1) / block;
-    const int64_t gmax = c.grid > 0 ? c.grid : (int64_t)device_cu_count() * 16;
+    const int64_t gmax = c.grid > 0 ? c.grid : (int64_t)apply_grid_for(2);
     const unsigned grid = (unsigned)std::max<int64_t>(1, std::min<int64_t>(need, gmax));
     ApplyArgs A{};
     A.one = make_desc(h, f.single, x, y);
@@ -126,7 +141,7 @@ int apply_launch(xdg_ham_s *h, const void *x, void *y, int64_t nvec, int dtype, 
     size_t lds = f.single ? stage_bytes<float>(A.one, b->plan.kind, 1)
                           : stage_bytes<double>(A.one, b->plan.kind, 1);
     A.stage_sub = 1;
-    if (lds > lds_limit()) {
+    if (lds > lds_budget()) {
         A.stage_sub = 0;
         lds = f.single ? stage_bytes<float>(A.one, b->plan.kind, 0)
                        : stage_bytes<double>(A.one, b->plan.kind, 0);
@@ -152,19 +167,20 @@ int apply_tuned(xdg_ham_s *h, const void *x, void *y, int64_t nvec, int dtype, h
     const xdg_basis_s *b = h->basis;
     Form f;
     XDG_RETURN_IF(form_of(b, dtype, nvec, &f));
-    const int64_t need = (b->dim + 255) / 256;
-    if (b->dim < 4096 * 256) {   // small blocks: one row per lane is already optimal
-        LaunchCfg c{256, (int)std::min<int64_t>(need, 1 << 30), 8};
+    const int64_t need = (b->dim + APPLY_BLOCK - 1) / APPLY_BLOCK;
+    if (b->dim < (int64_t)1024 * APPLY_BLOCK) {   // small blocks: one row per lane
+        LaunchCfg c{APPLY_BLOCK, (int)std::min<int64_t>(need, 1 << 30), 8};
         h->tuned[key] = c;
         return apply_launch(h, x, y, nvec, dtype, st, &c);
     }
     std::vector<LaunchCfg> cands;
     const int cu = device_cu_count();
-    for (int mult : {4, 8, 16, 32}) {
-        cands.push_back({256, cu * mult, 8});
-        if (f.cols > 1) cands.push_back({256, cu * mult, (int)std::max<int64_t>(1, f.cols / 2)});
+    for (int mult : {1, 2, 4, 8}) {
+        const int g = cu * mult * BLOCKS_PER_1024;
+        cands.push_back({APPLY_BLOCK, g, 8});
+        if (f.cols > 1) cands.push_back({APPLY_BLOCK, g, (int)std::max<int64_t>(1, f.cols / 2)});
     }
-    cands.push_back({256, (int)std::min<int64_t>(need, 1 << 30), 8});
+    cands.push_back({APPLY_BLOCK, (int)std::min<int64_t>(need, 1 << 30), 8});
     hipEvent_t e0, e1;
     XDG_TRY_HIP(hipEventCreate(&e0));
     XDG_TRY_HIP(hipEventCreate(&e1));
@@ -208,13 +224,13 @@ int ham_count_nnz(xdg_ham_s *h, int64_t *nnz) {
     A.count = cnt.as<unsigned long long>();
     A.stage_sub = 1;
     size_t lds = stage_bytes<double>(A.one, b->plan.kind, 1);
-    if (lds > lds_limit()) {
+    if (lds > lds_budget()) {
         A.stage_sub = 0;
         lds = stage_bytes<double>(A.one, b->plan.kind, 0);
     }
-    const unsigned block = 256;
+    const unsigned block = APPLY_BLOCK;
     const unsigned grid =
-        (unsigned)std::min<int64_t>((b->dim + block - 1) / block, (int64_t)device_cu_count() * 16);
+        (unsigned)std::min<int64_t>((b->dim + block - 1) / block, (int64_t)apply_grid_for(2));
     int rc;
     switch (b->plan.kind) {
         case K_U1: rc = launch_count_kind<K_U1>(b->wide, A, grid, block, lds, 0); break;
@@ -260,7 +276,7 @@ int batch_prepare(int n, xdg_ham_s *const *hams, const void *const *xs, void *co
     P->single = dtype_single(dtype);
     P->cplx = any_cplx;
     P->cols = (dtype_complex(dtype) && !any_cplx) ? 2 * nvec : nvec;
-    P->tile_rows = 1024;
+    P->tile_rows = 4 * APPLY_BLOCK;
     std::vector<SectorDesc> descs(n);
     std::vector<uint32_t> prefix(n + 1, 0);
     size_t lds_full = 0, lds_part = 0;
@@ -280,7 +296,7 @@ int batch_prepare(int n, xdg_ham_s *const *hams, const void *const *xs, void *co
         lds_part = std::max(lds_part, f0);
     }
     P->n_tiles = prefix[n];
-    P->stage_sub = lds_full <= lds_limit();
+    P->stage_sub = lds_full <= lds_budget();
     P->lds = P->stage_sub ? lds_full : lds_part;
     XDG_RETURN_IF(P->descs.upload(descs.data(), sizeof(SectorDesc) * n));
     XDG_RETURN_IF(P->prefix.upload(prefix.data(), sizeof(uint32_t) * (n + 1)));
@@ -299,13 +315,14 @@ int batch_launch(const BatchPlan &P, int grid, int nv_cap, hipStream_t st) {
     A.queue = P.queue.as<uint32_t>();
     A.nvec = P.cols;
     A.stage_sub = P.stage_sub;
-    const unsigned g = (unsigned)(grid > 0 ? grid : device_cu_count() * 8);
+    const unsigned g = (unsigned)(grid > 0 ? grid : apply_grid_for(2));
     for (int64_t v0 = 0; v0 < P.cols;) {
         const int nv = pick_nv(P.cols - v0, nv_cap > 0 ? nv_cap : 8);
         A.v0 = (int)v0;
         hipLaunchKernelGGL(k_zero_u32, dim3(1), dim3(1), 0, st, A.queue);
         XDG_TRY_HIP(hipGetLastError());
-        XDG_RETURN_IF(launch_dispatch(P.kind, P.wide, P.single, P.cplx, nv, A, g, 256, P.lds, st));
+        XDG_RETURN_IF(
+            launch_dispatch(P.kind, P.wide, P.single, P.cplx, nv, A, g, APPLY_BLOCK, P.lds, st));
         v0 += nv;
     }
     return XDG_OK;

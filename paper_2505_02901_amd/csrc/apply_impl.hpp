@@ -9,11 +9,19 @@
 // to the row, after the diagonal Sum_b Jz_b (+-1/4) x[r].  The row is
 // written once: no atomics, bitwise reproducible for any launch shape.
 // Up to NV vectors of the [dim][nvec] block share each search and lookup.
+// Workgroups are up to 1024 lanes so that the tables staged in LDS (bonds,
+// characters, search tables) are shared by 16 waves.
 #pragma once
 
 #include "device_common.hpp"
 
 namespace xdg {
+
+#ifndef XDG_APPLY_BLOCK
+#define XDG_APPLY_BLOCK 1024
+#endif
+constexpr int APPLY_BLOCK = XDG_APPLY_BLOCK;
+constexpr int BLOCKS_PER_1024 = 1024 / APPLY_BLOCK;   // grid scale for smaller workgroups
 
 template <class T> struct Vec2;
 template <> struct Vec2<float> { using type = float2; };
@@ -43,14 +51,17 @@ struct SectorDesc {
     int nlo;
     int n_sites, n_sym, n_bonds;
     const AffineElem *aff;
+    int ring;                    // 0, 1 (all rotations), 2 (and all reflections)
+    const int16_t *ring_gidx;    // [2 n_sites]
     const uint64_t *bytetab;
     int n_bchunks;
     const uint16_t *mintop;
     const uint32_t *cand_off;
     const uint16_t *cand_list;
     const uint8_t *src;
-    const uint16_t *img;
-    int n_s, m;
+    const uint16_t *pid;
+    const uint16_t *tperm;
+    int n_s, m, pb, n_perm;
     uint32_t n_cand;
     const void *bonds;           // BondD / BondF [n_bonds]
     const void *chi;             // double2 / float2 [n_sym]
@@ -75,6 +86,13 @@ struct ApplyArgs {
 
 __host__ __device__ inline size_t a16(size_t x) { return (x + 15) & ~(size_t)15; }
 
+__host__ __device__ inline size_t sub_table_bytes(const SectorDesc &d) {
+    const size_t NV = (size_t)d.n_s << d.m;
+    return a16(2 * NV) + a16(4 * (NV + 1)) + a16(2 * (size_t)d.n_cand) +
+           a16((size_t)d.n_sym * d.n_s) + a16(2 * (size_t)d.n_sym * d.n_s) +
+           a16(2 * (size_t)d.n_perm * 2 * ((size_t)1 << d.pb));
+}
+
 // LDS bytes needed to stage a sector's tables.
 template <class T>
 __host__ __device__ inline size_t stage_bytes(const SectorDesc &d, int kind, int stage_sub) {
@@ -82,11 +100,8 @@ __host__ __device__ inline size_t stage_bytes(const SectorDesc &d, int kind, int
     if (kind != K_U1) {
         n += a16(sizeof(typename Vec2<T>::type) * d.n_sym);
         n += a16(sizeof(T) * 2 * (d.n_sym + 1));
-        if (kind == K_AFF) n += a16(sizeof(AffineElem) * d.n_sym);
-        if (kind == K_SUB && stage_sub) {
-            const size_t NV = (size_t)d.n_s << d.m;
-            n += a16(2 * NV) + a16(4 * (NV + 1)) + a16(2 * (size_t)d.n_cand);
-        }
+        if (kind == K_AFF) n += a16(sizeof(AffineElem) * d.n_sym) + a16(4 * (size_t)d.n_sites);
+        if (kind == K_SUB && stage_sub) n += sub_table_bytes(d);
     }
     return n;
 }
@@ -98,53 +113,47 @@ struct Staged {
     const T *sq;       // sqrt(c)
     const T *rsq;      // 1/sqrt(c)
     const AffineElem *aff;
+    const int16_t *ring_gidx;
     SubCtx sub;
 };
+
+template <class E>
+__device__ inline E *stage_copy(unsigned char *smem, size_t &off, const E *src, size_t n) {
+    E *dst = reinterpret_cast<E *>(smem + off);
+    off = a16(off + sizeof(E) * n);
+    for (size_t e = threadIdx.x; e < n; e += blockDim.x) dst[e] = src[e];
+    return dst;
+}
 
 template <int KIND, class T>
 __device__ inline void stage(const SectorDesc &d, unsigned char *smem, int stage_sub, Staged<T> &S) {
     using B = typename BondT<T>::type;
     using T2 = typename Vec2<T>::type;
     size_t off = 0;
-    B *lb = reinterpret_cast<B *>(smem + off);
-    off = a16(off + sizeof(B) * d.n_bonds);
-    for (int e = threadIdx.x; e < d.n_bonds; e += blockDim.x)
-        lb[e] = reinterpret_cast<const B *>(d.bonds)[e];
-    S.bonds = lb;
-    S.sub = SubCtx{d.mintop, d.cand_off, d.cand_list, d.src, d.img, d.n_s, d.m};
+    S.bonds = stage_copy(smem, off, reinterpret_cast<const B *>(d.bonds), d.n_bonds);
+    S.sub = SubCtx{d.mintop, d.cand_off, d.cand_list, d.src, d.pid, d.tperm, d.n_s, d.m, d.pb};
     if constexpr (KIND != K_U1) {
-        T2 *lc = reinterpret_cast<T2 *>(smem + off);
-        off = a16(off + sizeof(T2) * d.n_sym);
-        for (int e = threadIdx.x; e < d.n_sym; e += blockDim.x)
-            lc[e] = reinterpret_cast<const T2 *>(d.chi)[e];
-        T *ls = reinterpret_cast<T *>(smem + off);
-        off = a16(off + sizeof(T) * 2 * (d.n_sym + 1));
-        for (int e = threadIdx.x; e < 2 * (d.n_sym + 1); e += blockDim.x)
-            ls[e] = reinterpret_cast<const T *>(d.sqrtt)[e];
-        S.chi = lc;
+        S.chi = stage_copy(smem, off, reinterpret_cast<const T2 *>(d.chi), d.n_sym);
+        const T *ls = stage_copy(smem, off, reinterpret_cast<const T *>(d.sqrtt), 2 * (d.n_sym + 1));
         S.sq = ls;
         S.rsq = ls + d.n_sym + 1;
         if constexpr (KIND == K_AFF) {
-            AffineElem *la = reinterpret_cast<AffineElem *>(smem + off);
-            off = a16(off + sizeof(AffineElem) * d.n_sym);
-            for (int e = threadIdx.x; e < d.n_sym; e += blockDim.x) la[e] = d.aff[e];
-            S.aff = la;
+            S.aff = stage_copy(smem, off, d.aff, d.n_sym);
+            int16_t *lg = reinterpret_cast<int16_t *>(smem + off);
+            off = a16(off + 4 * (size_t)d.n_sites);
+            if (d.ring)
+                for (int e = threadIdx.x; e < 2 * d.n_sites; e += blockDim.x) lg[e] = d.ring_gidx[e];
+            S.ring_gidx = lg;
         }
         if constexpr (KIND == K_SUB) {
             if (stage_sub) {
-                const uint32_t NV = (uint32_t)d.n_s << d.m;
-                uint16_t *lmt = reinterpret_cast<uint16_t *>(smem + off);
-                off = a16(off + 2 * (size_t)NV);
-                uint32_t *lco = reinterpret_cast<uint32_t *>(smem + off);
-                off = a16(off + 4 * ((size_t)NV + 1));
-                uint16_t *lcl = reinterpret_cast<uint16_t *>(smem + off);
-                for (uint32_t e = threadIdx.x; e < NV; e += blockDim.x) lmt[e] = d.mintop[e];
-                for (uint32_t e = threadIdx.x; e <= NV; e += blockDim.x) lco[e] = d.cand_off[e];
-                for (uint32_t e = threadIdx.x; e < d.n_cand; e += blockDim.x)
-                    lcl[e] = d.cand_list[e];
-                S.sub.mintop = lmt;
-                S.sub.cand_off = lco;
-                S.sub.cand_list = lcl;
+                const size_t NV = (size_t)d.n_s << d.m;
+                S.sub.mintop = stage_copy(smem, off, d.mintop, NV);
+                S.sub.cand_off = stage_copy(smem, off, d.cand_off, NV + 1);
+                S.sub.cand_list = stage_copy(smem, off, d.cand_list, d.n_cand);
+                S.sub.src = stage_copy(smem, off, d.src, (size_t)d.n_sym * d.n_s);
+                S.sub.pid = stage_copy(smem, off, d.pid, (size_t)d.n_sym * d.n_s);
+                S.sub.tperm = stage_copy(smem, off, d.tperm, (size_t)d.n_perm * 2 * ((size_t)1 << d.pb));
             }
         }
     }
@@ -163,12 +172,16 @@ __device__ __forceinline__ int64_t locate(const SectorDesc &d, const Staged<T> &
         return (int64_t)d.lin[(1ull << d.nlo) + hi] + (int64_t)d.lin[lo];
     } else {
         W rep;
-        if constexpr (KIND == K_AFF)
-            aff_search<W>(S.aff, d.n_sym, d.n_sites, t, rep, u, cnt);
-        else if constexpr (KIND == K_SUB)
+        if constexpr (KIND == K_AFF) {
+            if (d.ring)
+                ring_search<W>(S.ring_gidx, d.ring, d.n_sites, t, rep, u, cnt);
+            else
+                aff_search<W>(S.aff, d.n_sym, d.n_sites, t, rep, u, cnt);
+        } else if constexpr (KIND == K_SUB) {
             sub_search<W>(S.sub, t, rep, u, cnt);
-        else
+        } else {
             tab_search<W>(d.bytetab, d.n_bchunks, d.n_sym, t, rep, u, cnt);
+        }
         return hash_find<W>(d.hash, d.n_lines, (W)d.empty, rep);
     }
 }
@@ -243,7 +256,7 @@ __device__ __forceinline__ uint32_t count_row(const SectorDesc &d, const Staged<
 }
 
 template <class W, int KIND, class T, bool CPLX, int NV>
-__global__ __launch_bounds__(256) void k_apply(ApplyArgs A) {
+__global__ __launch_bounds__(APPLY_BLOCK) void k_apply(ApplyArgs A) {
     extern __shared__ __align__(16) unsigned char smem[];
     __shared__ uint32_t s_tile;
     __shared__ SectorDesc s_desc;
@@ -287,7 +300,7 @@ __global__ __launch_bounds__(256) void k_apply(ApplyArgs A) {
 }
 
 template <class W, int KIND>
-__global__ __launch_bounds__(256) void k_count(ApplyArgs A) {
+__global__ __launch_bounds__(APPLY_BLOCK) void k_count(ApplyArgs A) {
     extern __shared__ __align__(16) unsigned char smem[];
     __shared__ unsigned long long s_sum;
     Staged<double> S;
@@ -314,10 +327,6 @@ int launch_kind(bool wide, bool single, bool cplx, int nv, const ApplyArgs &A, u
 template <int KIND>
 int launch_count_kind(bool wide, const ApplyArgs &A, unsigned grid, unsigned block, size_t lds,
                       hipStream_t st);
-
-}  // namespace xdg
-
-namespace xdg {
 
 template <class W, int KIND, class T, bool CPLX>
 int launch_nv(int nv, const ApplyArgs &A, unsigned grid, unsigned block, size_t lds,

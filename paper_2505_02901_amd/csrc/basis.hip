@@ -83,8 +83,9 @@ struct EnumArgs {
     const uint32_t *cand_off;
     const uint16_t *cand_list;
     const uint8_t *src;
-    const uint16_t *img;
-    int n_s, m;
+    const uint16_t *pid;
+    const uint16_t *tperm;
+    int n_s, m, pb, n_perm;
     uint32_t n_cand;
     int stage_sub;
 };
@@ -94,7 +95,7 @@ __global__ __launch_bounds__(256) void k_enum(EnumArgs<W> A) {
     extern __shared__ __align__(16) unsigned char smem[];
     const double2 *chi = A.chi;
     const AffineElem *aff = A.aff;
-    SubCtx C{A.mintop, A.cand_off, A.cand_list, A.src, A.img, A.n_s, A.m};
+    SubCtx C{A.mintop, A.cand_off, A.cand_list, A.src, A.pid, A.tperm, A.n_s, A.m, A.pb};
     if constexpr (KIND != K_U1) {
         double2 *lchi = reinterpret_cast<double2 *>(smem);
         size_t off = align16(sizeof(double2) * A.n_sym);
@@ -116,9 +117,25 @@ __global__ __launch_bounds__(256) void k_enum(EnumArgs<W> A) {
                 for (uint32_t e = threadIdx.x; e < NV; e += blockDim.x) lmt[e] = A.mintop[e];
                 for (uint32_t e = threadIdx.x; e <= NV; e += blockDim.x) lco[e] = A.cand_off[e];
                 for (uint32_t e = threadIdx.x; e < A.n_cand; e += blockDim.x) lcl[e] = A.cand_list[e];
+                off = align16(off + 2 * (size_t)A.n_cand);
+                const uint32_t GS = (uint32_t)A.n_sym * A.n_s;
+                uint8_t *lsrc = reinterpret_cast<uint8_t *>(smem + off);
+                off = align16(off + GS);
+                uint16_t *lpid = reinterpret_cast<uint16_t *>(smem + off);
+                off = align16(off + 2 * (size_t)GS);
+                uint16_t *ltp = reinterpret_cast<uint16_t *>(smem + off);
+                const uint32_t TP = (uint32_t)A.n_perm * 2u << A.pb;
+                for (uint32_t e = threadIdx.x; e < GS; e += blockDim.x) {
+                    lsrc[e] = A.src[e];
+                    lpid[e] = A.pid[e];
+                }
+                for (uint32_t e = threadIdx.x; e < TP; e += blockDim.x) ltp[e] = A.tperm[e];
                 C.mintop = lmt;
                 C.cand_off = lco;
                 C.cand_list = lcl;
+                C.src = lsrc;
+                C.pid = lpid;
+                C.tperm = ltp;
             }
         }
         __syncthreads();
@@ -334,9 +351,12 @@ int enumerate(xdg_basis_s *b, DevBuf &binom_d) {
     A.cand_off = b->t_candoff.as<uint32_t>();
     A.cand_list = b->t_candlist.as<uint16_t>();
     A.src = b->t_src.as<uint8_t>();
-    A.img = b->t_img.as<uint16_t>();
+    A.pid = b->t_pid.as<uint16_t>();
+    A.tperm = b->t_tperm.as<uint16_t>();
     A.n_s = b->plan.sub.n_s;
     A.m = b->plan.sub.m;
+    A.pb = b->plan.sub.pb;
+    A.n_perm = b->plan.sub.n_perm;
     A.n_cand = (uint32_t)b->plan.sub.cand_list.size();
 
     const uint64_t lanes_target = (uint64_t)device_cu_count() * 1024;
@@ -351,7 +371,10 @@ int enumerate(xdg_basis_s *b, DevBuf &binom_d) {
         if (kind == K_AFF) lds += align16(sizeof(AffineElem) * b->n_sym);
         if (kind == K_SUB) {
             const size_t NV = (size_t)A.n_s << A.m;
-            size_t need = align16(2 * NV) + align16(4 * (NV + 1)) + align16(2 * (size_t)A.n_cand);
+            const size_t GS = (size_t)A.n_sym * A.n_s;
+            size_t need = align16(2 * NV) + align16(4 * (NV + 1)) + align16(2 * (size_t)A.n_cand) +
+                          align16(GS) + align16(2 * GS) +
+                          align16(2 * ((size_t)A.n_perm * 2 << A.pb));
             if (lds + need <= lds_limit()) {
                 A.stage_sub = 1;
                 lds += need;
@@ -502,11 +525,15 @@ int basis_build_device(xdg_basis_s *b) {
         XDG_RETURN_IF(b->sqrt_d.upload(sq.data(), sq.size() * sizeof(double)));
         XDG_RETURN_IF(b->sqrt_f.upload(sqf.data(), sqf.size() * sizeof(float)));
     }
-    if (P.kind == K_AFF)
+    if (P.kind == K_AFF) {
         XDG_RETURN_IF(b->t_aff.upload(P.aff.data(), P.aff.size() * sizeof(AffineElem)));
+        if (P.ring)
+            XDG_RETURN_IF(b->t_ring.upload(P.ring_gidx.data(), P.ring_gidx.size() * 2));
+    }
     if (P.kind == K_SUB) {
         XDG_RETURN_IF(b->t_src.upload(P.sub.src.data(), P.sub.src.size()));
-        XDG_RETURN_IF(b->t_img.upload(P.sub.img.data(), P.sub.img.size() * 2));
+        XDG_RETURN_IF(b->t_pid.upload(P.sub.pid.data(), P.sub.pid.size() * 2));
+        XDG_RETURN_IF(b->t_tperm.upload(P.sub.tperm.data(), P.sub.tperm.size() * 2));
         XDG_RETURN_IF(b->t_mintop.upload(P.sub.mintop.data(), P.sub.mintop.size() * 2));
         XDG_RETURN_IF(b->t_candoff.upload(P.sub.cand_off.data(), P.sub.cand_off.size() * 4));
         XDG_RETURN_IF(b->t_candlist.upload(P.sub.cand_list.data(),

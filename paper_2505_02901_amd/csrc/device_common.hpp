@@ -124,6 +124,71 @@ __device__ __forceinline__ void aff_search(const AffineElem *aff, int n_sym, int
     }
 }
 
+// ---------------------------------------- search: full ring of rotations --
+// For a group holding every rotation i -> i + a (and optionally every
+// reflection i -> a - i), the image under rotation a is rotr_N(t, a); read
+// from its top bit it is t read downward from site a - 1.  The smallest image
+// therefore begins with a longest run of zeros of t, so only the tops of the
+// maximal zero runs need a full comparison: y_k has bit p set iff sites
+// p, p-1, .., p-k+1 of t are all down, and y_{k+1} = y_k & rotl(z, k).  All
+// minimising rotations are among these candidates, so the first minimising
+// element and the number of minimisers (= |Stab|) come out exact.
+template <class W>
+__device__ __forceinline__ W rotl_n(W t, int k, int N) {
+    return rotr_n<W>(t, (N - k) % N, N);
+}
+
+// Scans the rotations of t; merges into (best, u, cnt) using gidx[a] as the
+// group index of rotation a.
+template <class W>
+__device__ __forceinline__ void ring_scan(W t, int N, const int16_t *gidx, W &best, int &u,
+                                          int &cnt) {
+    const W mask = N == (int)(8 * sizeof(W)) ? ~W(0) : ((W(1) << N) - 1);
+    const W z = ~t & mask;
+    W y;
+    if (z == 0 || z == mask) {
+        y = mask;                      // all rotations give the same image
+    } else {
+        y = z;
+        for (int k = 1; k < N; ++k) {
+            const W y2 = y & rotl_n<W>(z, k, N);
+            if (y2 == 0) break;
+            y = y2;
+        }
+    }
+    while (y) {
+        int p;
+        if constexpr (sizeof(W) == 4)
+            p = __builtin_ctz(y);
+        else
+            p = __builtin_ctzll(y);
+        y &= y - 1;
+        const int a = p + 1 == N ? 0 : p + 1;
+        const W img = rotr_n<W>(t, a, N);
+        const int g = gidx[a];
+        if (img < best) {
+            best = img;
+            u = g;
+            cnt = 1;
+        } else if (img == best) {
+            ++cnt;
+            u = g < u ? g : u;
+        }
+    }
+}
+
+// ring = 1: rotations only; ring = 2: rotations and reflections.
+// gidx[a] (rotation a) and gidx[N + a] (reflection image rotr_N(rev_N(t), a)).
+template <class W>
+__device__ __forceinline__ void ring_search(const int16_t *gidx, int ring, int N, W t, W &best,
+                                            int &u, int &cnt) {
+    best = ~W(0);
+    u = 0x7fffffff;
+    cnt = 0;
+    ring_scan<W>(t, N, gidx, best, u, cnt);
+    if (ring == 2) ring_scan<W>(rev_n<W>(t, N), N, gidx + N, best, u, cnt);
+}
+
 // Representative test for enumeration: false as soon as some image is smaller.
 // On true, stab = |Stab(s)| and (cr, ci) = sum of chi over the stabiliser.
 template <class W>
@@ -155,17 +220,25 @@ __device__ __forceinline__ bool aff_is_rep(const AffineElem *aff, int n_sym, int
 // only for them is the full image assembled, block by block from the top,
 // abandoning an element as soon as its image prefix exceeds the best one.
 struct SubCtx {
-    const uint16_t *mintop;    // [n_s][V]       (LDS)
-    const uint32_t *cand_off;  // [n_s*V + 1]    (LDS)
-    const uint16_t *cand_list; //                (LDS)
-    const uint8_t *src;        // [n_sym][n_s]   (global)
-    const uint16_t *img;       // [n_sym][n_s][V](global)
-    int n_s, m;
+    const uint16_t *mintop;    // [n_s][V]
+    const uint32_t *cand_off;  // [n_s*V + 1]
+    const uint16_t *cand_list;
+    const uint8_t *src;        // [n_sym][n_s]
+    const uint16_t *pid;       // [n_sym][n_s]
+    const uint16_t *tperm;     // [n_perm][2][E]
+    int n_s, m, pb;            // E = 1 << pb
 };
 
 template <class W>
 __device__ __forceinline__ uint32_t chunk_of(W t, int k, int m, uint32_t vmask) {
     return (uint32_t)(t >> (k * m)) & vmask;
+}
+
+// image chunk of source chunk v for block a of element g (two half lookups)
+__device__ __forceinline__ uint32_t sub_img(const SubCtx &C, int g, int a, uint32_t v) {
+    const int E = 1 << C.pb;
+    const uint16_t *tp = C.tperm + (size_t)C.pid[g * C.n_s + a] * 2 * E;
+    return (uint32_t)tp[v & (E - 1)] | tp[E + (v >> C.pb)];
 }
 
 template <class W>
@@ -187,12 +260,11 @@ __device__ __forceinline__ void sub_search(const SubCtx &C, W t, W &best, int &u
         for (uint32_t q = C.cand_off[e]; q < q1; ++q) {
             const int g = C.cand_list[q];
             const uint8_t *sg = C.src + (size_t)g * ns;
-            const uint16_t *ig = C.img + (size_t)g * ns * V;
             W img = (W)mt << (top * m);
             bool lose = false;
             int a = top - 1;
             for (; a >= 0; --a) {
-                img |= (W)ig[a * V + chunk_of<W>(t, sg[a], m, vmask)] << (a * m);
+                img |= (W)sub_img(C, g, a, chunk_of<W>(t, sg[a], m, vmask)) << (a * m);
                 const W hi = img >> (a * m), hb = best >> (a * m);
                 if (hi > hb) {
                     lose = true;
@@ -200,7 +272,7 @@ __device__ __forceinline__ void sub_search(const SubCtx &C, W t, W &best, int &u
                 }
                 if (hi < hb) {
                     for (--a; a >= 0; --a)
-                        img |= (W)ig[a * V + chunk_of<W>(t, sg[a], m, vmask)] << (a * m);
+                        img |= (W)sub_img(C, g, a, chunk_of<W>(t, sg[a], m, vmask)) << (a * m);
                     break;
                 }
             }
@@ -235,11 +307,10 @@ __device__ __forceinline__ bool sub_is_rep(const SubCtx &C, W s, const double2 *
         for (uint32_t q = C.cand_off[e]; q < q1; ++q) {
             const int g = C.cand_list[q];
             const uint8_t *sg = C.src + (size_t)g * ns;
-            const uint16_t *ig = C.img + (size_t)g * ns * V;
             W img = (W)ct << (top * m);
             int cmp = 0;   // -1: image < s, +1: image > s
             for (int a = top - 1; a >= 0; --a) {
-                img |= (W)ig[a * V + chunk_of<W>(s, sg[a], m, vmask)] << (a * m);
+                img |= (W)sub_img(C, g, a, chunk_of<W>(s, sg[a], m, vmask)) << (a * m);
                 const W hi = img >> (a * m), hs = s >> (a * m);
                 if (hi != hs) {
                     cmp = hi < hs ? -1 : 1;

@@ -568,14 +568,14 @@ int lanczos_batched(int n, xdg_ham_s *const *hams, const void *const *v0s, int64
         XDG_RETURN_IF(batch_prepare(n, hv.data(), xs.data(), ys.data(), nvec, dtype, &plans[p]));
     }
     // choose the persistent grid once (outside capture): a few sizes, timed
-    int best_grid = device_cu_count() * 8;
+    int best_grid = apply_grid_for(2);
     {
         hipEvent_t e0, e1;
         XDG_TRY_HIP(hipEventCreate(&e0));
         XDG_TRY_HIP(hipEventCreate(&e1));
         float best = 1e30f;
-        for (int mult : {4, 8, 16}) {
-            const int g = device_cu_count() * mult;
+        for (int mult : {1, 2, 4}) {
+            const int g = apply_grid_for(mult);
             XDG_RETURN_IF(batch_launch(plans[0], g, 8, st));
             XDG_TRY_HIP(hipEventRecord(e0, st));
             XDG_RETURN_IF(batch_launch(plans[0], g, 8, st));

@@ -239,37 +239,63 @@ bool detect_sublattice(int N, int n_sym, const int32_t *perm, int n_s, std::vect
 void build_sublattice(int N, int n_sym, const int32_t *perm, int n_s, SublatticeTables *T) {
     const int m = N / n_s;
     const int V = 1 << m;
+    const int pb = (m + 1) / 2, E = 1 << pb;
     T->n_s = n_s;
     T->m = m;
+    T->pb = pb;
     detect_sublattice(N, n_sym, perm, n_s, &T->src);
-    T->img.assign((size_t)n_sym * n_s * V, 0);
+    // distinct block permutations: image bit w of block a takes source bit
+    // p[a m + w] - k m of block k = src[g][a]
+    std::map<std::vector<int>, int> ids;
+    std::vector<std::vector<int>> perms;
+    T->pid.assign((size_t)n_sym * n_s, 0);
     for (int g = 0; g < n_sym; ++g) {
         const int32_t *p = perm + (size_t)g * N;
         for (int a = 0; a < n_s; ++a) {
-            int k = T->src[(size_t)g * n_s + a];
-            uint16_t *dst = &T->img[((size_t)g * n_s + a) * V];
-            for (int v = 0; v < V; ++v) {
-                uint32_t r = 0;
-                for (int w = 0; w < m; ++w)
-                    if ((v >> (p[a * m + w] - k * m)) & 1) r |= 1u << w;
-                dst[v] = (uint16_t)r;
+            const int k = T->src[(size_t)g * n_s + a];
+            std::vector<int> bw(m);
+            for (int w = 0; w < m; ++w) bw[w] = p[a * m + w] - k * m;
+            auto it = ids.find(bw);
+            if (it == ids.end()) {
+                it = ids.emplace(bw, (int)perms.size()).first;
+                perms.push_back(bw);
             }
+            T->pid[(size_t)g * n_s + a] = (uint16_t)it->second;
         }
     }
+    T->n_perm = (int)perms.size();
+    T->tperm.assign((size_t)T->n_perm * 2 * E, 0);
+    for (int q = 0; q < T->n_perm; ++q) {
+        std::vector<int> dst(m);   // source bit -> image bit
+        for (int w = 0; w < m; ++w) dst[perms[q][w]] = w;
+        for (int h = 0; h < 2; ++h)
+            for (int u = 0; u < E; ++u) {
+                uint32_t r = 0;
+                for (int j = 0; j < pb; ++j) {
+                    const int sb = h * pb + j;
+                    if (sb < m && ((u >> j) & 1)) r |= 1u << dst[sb];
+                }
+                T->tperm[((size_t)q * 2 + h) * E + u] = (uint16_t)r;
+            }
+    }
+    auto image = [&](int g, int a, int v) -> uint32_t {
+        const uint16_t *tp = &T->tperm[(size_t)T->pid[(size_t)g * n_s + a] * 2 * E];
+        return (uint32_t)tp[v & (E - 1)] | tp[E + (v >> pb)];
+    };
     const int top = n_s - 1;
     T->mintop.assign((size_t)n_s * V, 0xFFFF);
     std::vector<std::vector<uint16_t>> lists((size_t)n_s * V);
     for (int g = 0; g < n_sym; ++g) {
         int k = T->src[(size_t)g * n_s + top];
-        const uint16_t *im = &T->img[((size_t)g * n_s + top) * V];
         for (int v = 0; v < V; ++v) {
+            const uint16_t im = (uint16_t)image(g, top, v);
             uint16_t &mt = T->mintop[(size_t)k * V + v];
             auto &L = lists[(size_t)k * V + v];
-            if (im[v] < mt) {
-                mt = im[v];
+            if (im < mt) {
+                mt = im;
                 L.clear();
             }
-            if (im[v] == mt) L.push_back((uint16_t)g);
+            if (im == mt) L.push_back((uint16_t)g);
         }
     }
     T->cand_off.assign((size_t)n_s * V + 1, 0);
@@ -318,7 +344,13 @@ int make_plan(int n_sites, int n_sym, const int32_t *perm, const xdg_basis_opts 
         set_error("unknown search kind %d", want);
         return XDG_EINVAL;
     }
+    const int flags = opts ? opts->flags : 0;
+    if (flags & ~XDG_FLAG_LANE_SEARCH) {
+        set_error("unknown flags 0x%x", flags);
+        return XDG_EINVAL;
+    }
     Plan p;
+    p.flags = flags;
     if (n_sym == 0) {
         if (want != XDG_SEARCH_AUTO && want != XDG_SEARCH_U1) {
             set_error("search kind %d needs a permutation group", want);
@@ -340,6 +372,20 @@ int make_plan(int n_sites, int n_sym, const int32_t *perm, const xdg_basis_opts 
     if (want == XDG_SEARCH_AUTO || want == XDG_SEARCH_AFFINE) {
         if (detect_affine(N, n_sym, perm, &p.aff)) {
             p.kind = XDG_SEARCH_AFFINE;
+            std::vector<int16_t> gi(2 * (size_t)N, -1);
+            int n_rot = 0, n_ref = 0;
+            for (int g = 0; g < n_sym; ++g) {
+                const AffineElem &e = p.aff[g];
+                int16_t &slot = gi[(e.eps > 0 ? 0 : N) + e.a];
+                if (slot < 0) {
+                    slot = (int16_t)g;
+                    (e.eps > 0 ? n_rot : n_ref)++;
+                }
+            }
+            if (n_rot == N && (n_ref == 0 || n_ref == N) && n_sym == n_rot + n_ref && N <= 64) {
+                p.ring = n_ref ? 2 : 1;
+                p.ring_gidx = gi;
+            }
             *plan = std::move(p);
             return XDG_OK;
         }

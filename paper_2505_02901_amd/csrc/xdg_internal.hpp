@@ -57,14 +57,18 @@ struct DevBuf {
 // Sublattice-coding tables (built on the host, uploaded once).
 //   sites are blocks of m bits, block q = bits [q m, (q+1) m); top = n_s - 1.
 //   src[g][a]      : block of t feeding block a of g.t
-//   img[g][a][v]   : m-bit image chunk for block a when the source chunk is v
-//   mintop[k][v]   : min over g with src[g][top] = k of img[g][top][v]
+//   pid[g][a]      : which of the distinct block permutations maps it
+//   tperm[p][h][u] : image bits of the half h (bits [h pb, (h+1) pb)) of a
+//                    source chunk with value u under permutation p; the
+//                    image chunk of v is tperm[p][0][v & lo] | tperm[p][1][v >> pb]
+//   mintop[k][v]   : min over g with src[g][top] = k of the image of v
 //   cand_off[k][v] : offsets into cand_list (size n_s*(2^m)+1)
 //   cand_list      : group elements reaching mintop[k][v], ascending
 struct SublatticeTables {
-    int n_s = 0, m = 0;
+    int n_s = 0, m = 0, pb = 0, n_perm = 0;
     std::vector<uint8_t> src;        // [n_sym][n_s]
-    std::vector<uint16_t> img;       // [n_sym][n_s][2^m]
+    std::vector<uint16_t> pid;       // [n_sym][n_s]
+    std::vector<uint16_t> tperm;     // [n_perm][2][2^pb]
     std::vector<uint16_t> mintop;    // [n_s][2^m]
     std::vector<uint32_t> cand_off;  // [n_s * 2^m + 1]
     std::vector<uint16_t> cand_list; // [cand_off.back()]
@@ -87,6 +91,12 @@ struct Plan {
     SublatticeTables sub;
     ByteTables bytes;
     std::vector<AffineElem> aff;
+    // affine groups holding every rotation (ring = 1) and also every
+    // reflection (ring = 2): group index of rotation a at [a], of the
+    // reflection with image rotr_N(rev_N(t), a) at [N + a]
+    int ring = 0;
+    std::vector<int16_t> ring_gidx;
+    int flags = 0;   // XDG_FLAG_*
 };
 
 int validate_group(int n_sites, int n_sym, const int32_t *perm, const double *chi);
@@ -134,7 +144,7 @@ struct xdg_basis_s {
     xdg::HashIndex hidx;
     xdg::DevBuf lin;            // u32 [2^nlo + 2^nhi] Lin tables (U(1))
     int lin_nlo = 0, lin_nhi = 0;
-    xdg::DevBuf t_src, t_img, t_mintop, t_candoff, t_candlist, t_bytes, t_aff;
+    xdg::DevBuf t_src, t_pid, t_tperm, t_mintop, t_candoff, t_candlist, t_bytes, t_aff, t_ring;
     xdg::DevBuf chi_d;          // double2 [n_sym]
     xdg::DevBuf chi_f;          // float2 [n_sym]
     xdg::DevBuf sqrt_d;         // double [n_sym+1] sqrt(c), then [n_sym+1] 1/sqrt(c)
@@ -216,6 +226,7 @@ void tridiag_eigenvalues(int m, const double *alpha, const double *beta, std::ve
 int random_fill(int64_t n_scalars, uint64_t seed, int kind, bool single, void *out,
                 hipStream_t st);
 int device_cu_count();
+int apply_grid_for(int mult);
 
 size_t dtype_size(int dtype);
 bool dtype_complex(int dtype);

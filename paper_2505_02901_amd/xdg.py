@@ -34,7 +34,11 @@ class XdgError(RuntimeError):
 
 
 class BasisOpts(C.Structure):
-    _fields_ = [("search", C.c_int), ("n_sublattices", C.c_int), ("reserved", C.c_int * 6)]
+    _fields_ = [("search", C.c_int), ("n_sublattices", C.c_int), ("flags", C.c_int),
+                ("reserved", C.c_int * 5)]
+
+
+XDG_FLAG_LANE_SEARCH = 1
 
 
 _lib = None
@@ -184,11 +188,11 @@ def xdg_plan_search(n_sites: int, perm, search: int = 0, n_sublattices: int = 0)
 
 
 def xdg_create_basis(n_sites: int, n_up: int, perm=None, chi=None, search: int = 0,
-                     n_sublattices: int = 0):
+                     n_sublattices: int = 0, flags: int = 0):
     perm, pp = _arr(perm, np.int32)
     n_sym = 0 if perm is None else perm.shape[0]
     chi, pc = _chi_arr(chi, n_sym)
-    o = BasisOpts(search, n_sublattices)
+    o = BasisOpts(search, n_sublattices, flags)
     h = C.c_void_p()
     _check(lib().xdg_create_basis(n_sites, n_up, n_sym, pp, pc, C.byref(o), C.byref(h)))
     return h
@@ -330,8 +334,8 @@ class Basis:
     """Owning wrapper of an ``xdg_basis`` handle."""
 
     def __init__(self, n_sites: int, n_up: int, perm=None, chi=None, search: int = 0,
-                 n_sublattices: int = 0):
-        self.handle = xdg_create_basis(n_sites, n_up, perm, chi, search, n_sublattices)
+                 n_sublattices: int = 0, flags: int = 0):
+        self.handle = xdg_create_basis(n_sites, n_up, perm, chi, search, n_sublattices, flags)
         self.n_sites = n_sites
         self.n_up = n_up
 

@@ -35,11 +35,21 @@ def sector_models():
     chi = np.ones(2 * 14, dtype=np.complex128)
     chi[14:] = -1
     out.append(W.chain_model(14).with_sector(W.chain_dihedral(14), chi, "dihedral14_odd"))
+    # translations by even steps only: affine but not a full ring of rotations
+    even = W.chain_translations(16)[::2]
+    out.append(W.chain_model(16).with_sector(even, np.exp(2j * np.pi * np.arange(8) * 3 / 8),
+                                             "chain16_T2_k3"))
     out += [W.torus_model((4, 0), (0, 4), 1.0, 0.5, ir) for ir in ("A1", "A2", "B1", "B2")]
     out += [W.torus_model((4, 2), (-2, 4), 1.0, 0.0, "A1", reflections=False, n_up=n)
             for n in (10, 7)]
     out += [W.torus_model((6, 0), (0, 4), 1.0, 0.3, "A1", rotations=False, name="rect24")]
     out += [W.torus_model((6, 0), (0, 4), 1.0, 0.3, "B1", rotations=False, name="rect24b")]
+    # 64-bit state words: the benchmark lattices at low filling, long rings
+    out += [W.torus_model((6, 0), (0, 6), 1.0, 0.5, ir, n_up=n, name="square36")
+            for ir, n in (("A1", 3), ("A1", 5), ("B2", 5))]
+    out += [W.torus_model((6, 2), (-2, 6), 1.0, 0.0, "A1", reflections=False, n_up=n,
+                          name="tilted40") for n in (4, 5)]
+    out += [W.chain_model(40, n_up=5, l=3), W.chain_model(34, n_up=4)]
     return out
 
 
@@ -114,6 +124,30 @@ def test_apply_matches_oracle(X, m):
         x = W.random_vector(5, D, 2, kind="gauss", complex_=True)
         yc = gpu_apply(X, H, x, torch.complex128)
         assert rel_err(yc, oracle.apply(m, basis, x)) < TOL64
+
+
+@pytest.mark.parametrize("search,flags", [(4, 0), (3, 1)], ids=["table", "lane-sublattice"])
+def test_apply_other_search_kinds(X, search, flags):
+    # the generic byte-table search and the lane-private sublattice search give
+    # the same basis and bitwise the same y as the default path
+    for m in (W.torus_model((4, 0), (0, 4), 1.0, 0.5, "B1"),
+              W.torus_model((6, 0), (0, 6), 1.0, 0.5, "A1", n_up=5, name="square36"),
+              W.chain_model(16, l=5)):
+        if search == 3 and m.n_sites == 16 and m.perm.shape[0] == 16:
+            continue   # a ring has no block structure in its natural labelling
+        b0 = X.Basis.from_model(m)
+        b1 = X.Basis.from_model(m, search=search, flags=flags)
+        assert b1.search_kind[0] == search
+        assert np.array_equal(b0.states(), b1.states())
+        assert np.array_equal(b0.stabilisers(), b1.stabilisers())
+        h0 = X.Hamiltonian.from_model(b0, m)
+        h1 = X.Hamiltonian.from_model(b1, m)
+        x = W.random_vector(8, b0.dim, 2, kind="gauss", complex_=True)
+        y0 = gpu_apply(X, h0, x, torch.complex128)
+        y1 = gpu_apply(X, h1, x, torch.complex128)
+        assert rel_err(y1, y0) < 1e-14
+        y_or = oracle.apply(m, oracle_basis(m), x)
+        assert rel_err(y1, y_or) < TOL64
 
 
 def test_apply_nvec8_and_determinism(X):
