@@ -81,9 +81,12 @@ typedef struct xdg_basis_opts {
     int reserved[5];     /* must be zero */
 } xdg_basis_opts;
 
-/* flags: sublattice search done by each lane alone instead of the default
- * wave-cooperative search (same results; for testing and comparison) */
-#define XDG_FLAG_LANE_SEARCH 1
+/* flags:
+ * XDG_FLAG_F32_ACCUMULATE: with FP32 / complex-FP32 vectors, compute the
+ *   amplitudes and accumulate each output row in FP32 (default: FP64
+ *   amplitudes and accumulation, one rounding to FP32 when the row is
+ *   stored; the vectors are FP32 in memory either way). */
+#define XDG_FLAG_F32_ACCUMULATE 2
 
 /* Version string of the library (cf. the version banner, Sec. 2). */
 const char *xdg_version(void);

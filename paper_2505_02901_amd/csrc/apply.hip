@@ -35,13 +35,17 @@ int apply_grid_for(int mult) { return device_cu_count() * mult * BLOCKS_PER_1024
 
 namespace {
 
-int launch_dispatch(int kind, bool wide, bool single, bool cplx, int nv, const ApplyArgs &A,
-                    unsigned grid, unsigned block, size_t lds, hipStream_t st) {
+int launch_dispatch(int kind, bool wide, bool single, bool acc64, bool cplx, int nv,
+                    const ApplyArgs &A, unsigned grid, unsigned block, size_t lds, hipStream_t st) {
     switch (kind) {
-        case K_U1: return launch_kind<K_U1>(wide, single, cplx, nv, A, grid, block, lds, st);
-        case K_AFF: return launch_kind<K_AFF>(wide, single, cplx, nv, A, grid, block, lds, st);
-        case K_SUB: return launch_kind<K_SUB>(wide, single, cplx, nv, A, grid, block, lds, st);
-        case K_TAB: return launch_kind<K_TAB>(wide, single, cplx, nv, A, grid, block, lds, st);
+        case K_U1:
+            return launch_kind<K_U1>(wide, single, acc64, cplx, nv, A, grid, block, lds, st);
+        case K_AFF:
+            return launch_kind<K_AFF>(wide, single, acc64, cplx, nv, A, grid, block, lds, st);
+        case K_SUB:
+            return launch_kind<K_SUB>(wide, single, acc64, cplx, nv, A, grid, block, lds, st);
+        case K_TAB:
+            return launch_kind<K_TAB>(wide, single, acc64, cplx, nv, A, grid, block, lds, st);
     }
     set_error("unknown search kind %d", kind);
     return XDG_EINVAL;
@@ -90,6 +94,8 @@ SectorDesc make_desc(const xdg_ham_s *h, bool single, const void *x, void *y) {
 // imaginary parts are independent columns of a [dim][2 nvec] real block.
 struct Form {
     bool single, cplx_kernel;
+    bool acc64;     // FP64 amplitudes and row accumulation
+    bool tsingle;   // FP32 amplitude tables (single && !acc64)
     int64_t cols;   // columns seen by the kernel
 };
 
@@ -108,6 +114,8 @@ int form_of(const xdg_basis_s *b, int dtype, int64_t nvec, Form *f) {
     }
     f->single = dtype_single(dtype);
     f->cplx_kernel = b->is_complex;
+    f->acc64 = !f->single || !(b->plan.flags & XDG_FLAG_F32_ACCUMULATE);
+    f->tsingle = f->single && !f->acc64;
     f->cols = (dtype_complex(dtype) && !b->is_complex) ? 2 * nvec : nvec;
     return XDG_OK;
 }
@@ -136,22 +144,22 @@ int apply_launch(xdg_ham_s *h, const void *x, void *y, int64_t nvec, int dtype, 
     const int64_t gmax = c.grid > 0 ? c.grid : (int64_t)apply_grid_for(2);
     const unsigned grid = (unsigned)std::max<int64_t>(1, std::min<int64_t>(need, gmax));
     ApplyArgs A{};
-    A.one = make_desc(h, f.single, x, y);
+    A.one = make_desc(h, f.tsingle, x, y);
     A.nvec = f.cols;
-    size_t lds = f.single ? stage_bytes<float>(A.one, b->plan.kind, 1)
-                          : stage_bytes<double>(A.one, b->plan.kind, 1);
+    size_t lds = f.tsingle ? stage_bytes<float>(A.one, b->plan.kind, 1)
+                           : stage_bytes<double>(A.one, b->plan.kind, 1);
     A.stage_sub = 1;
     if (lds > lds_budget()) {
         A.stage_sub = 0;
-        lds = f.single ? stage_bytes<float>(A.one, b->plan.kind, 0)
-                       : stage_bytes<double>(A.one, b->plan.kind, 0);
+        lds = f.tsingle ? stage_bytes<float>(A.one, b->plan.kind, 0)
+                        : stage_bytes<double>(A.one, b->plan.kind, 0);
     }
     const int cap = c.nv > 0 ? c.nv : 8;
     for (int64_t v0 = 0; v0 < f.cols;) {
         const int nv = pick_nv(f.cols - v0, cap);
         A.v0 = (int)v0;
-        XDG_RETURN_IF(launch_dispatch(b->plan.kind, b->wide, f.single, f.cplx_kernel, nv, A, grid,
-                                      block, lds, st));
+        XDG_RETURN_IF(launch_dispatch(b->plan.kind, b->wide, f.single, f.acc64, f.cplx_kernel, nv,
+                                      A, grid, block, lds, st));
         v0 += nv;
     }
     return XDG_OK;
@@ -274,6 +282,8 @@ int batch_prepare(int n, xdg_ham_s *const *hams, const void *const *xs, void *co
     P->kind = b0->plan.kind;
     P->wide = b0->wide;
     P->single = dtype_single(dtype);
+    P->acc64 = !P->single || !(b0->plan.flags & XDG_FLAG_F32_ACCUMULATE);
+    const bool tsingle = P->single && !P->acc64;
     P->cplx = any_cplx;
     P->cols = (dtype_complex(dtype) && !any_cplx) ? 2 * nvec : nvec;
     P->tile_rows = 4 * APPLY_BLOCK;
@@ -281,17 +291,17 @@ int batch_prepare(int n, xdg_ham_s *const *hams, const void *const *xs, void *co
     std::vector<uint32_t> prefix(n + 1, 0);
     size_t lds_full = 0, lds_part = 0;
     for (int i = 0; i < n; ++i) {
-        descs[i] = make_desc(hams[i], P->single, xs[i], ys[i]);
+        descs[i] = make_desc(hams[i], tsingle, xs[i], ys[i]);
         const uint64_t tiles = (hams[i]->basis->dim + P->tile_rows - 1) / P->tile_rows;
         if ((uint64_t)prefix[i] + tiles >= 0xFFFFFFFFull) {
             set_error("too many row tiles in the batch");
             return XDG_EINVAL;
         }
         prefix[i + 1] = prefix[i] + (uint32_t)tiles;
-        const size_t f1 = P->single ? stage_bytes<float>(descs[i], P->kind, 1)
-                                    : stage_bytes<double>(descs[i], P->kind, 1);
-        const size_t f0 = P->single ? stage_bytes<float>(descs[i], P->kind, 0)
-                                    : stage_bytes<double>(descs[i], P->kind, 0);
+        const size_t f1 = tsingle ? stage_bytes<float>(descs[i], P->kind, 1)
+                                  : stage_bytes<double>(descs[i], P->kind, 1);
+        const size_t f0 = tsingle ? stage_bytes<float>(descs[i], P->kind, 0)
+                                  : stage_bytes<double>(descs[i], P->kind, 0);
         lds_full = std::max(lds_full, f1);
         lds_part = std::max(lds_part, f0);
     }
@@ -322,7 +332,8 @@ int batch_launch(const BatchPlan &P, int grid, int nv_cap, hipStream_t st) {
         hipLaunchKernelGGL(k_zero_u32, dim3(1), dim3(1), 0, st, A.queue);
         XDG_TRY_HIP(hipGetLastError());
         XDG_RETURN_IF(
-            launch_dispatch(P.kind, P.wide, P.single, P.cplx, nv, A, g, APPLY_BLOCK, P.lds, st));
+            launch_dispatch(P.kind, P.wide, P.single, P.acc64, P.cplx, nv, A, g, APPLY_BLOCK,
+                            P.lds, st));
         v0 += nv;
     }
     return XDG_OK;

@@ -186,37 +186,39 @@ __device__ __forceinline__ int64_t locate(const SectorDesc &d, const Staged<T> &
     }
 }
 
-template <class W, int KIND, class T, bool CPLX, int NV>
-__device__ __forceinline__ void process_row(const SectorDesc &d, const Staged<T> &S, int64_t row,
+// T: storage type of x and y; A: type of the amplitudes and of the per-row
+// accumulation (each output element is rounded to T once, at the store).
+template <class W, int KIND, class T, class A, bool CPLX, int NV>
+__device__ __forceinline__ void process_row(const SectorDesc &d, const Staged<A> &S, int64_t row,
                                             int64_t nvec, int v0) {
-    using B = typename BondT<T>::type;
+    using B = typename BondT<A>::type;
     constexpr int C = CPLX ? 2 : 1;
     const W s = reinterpret_cast<const W *>(d.reps)[row];
     const T *X = reinterpret_cast<const T *>(d.x);
     T *Y = reinterpret_cast<T *>(d.y);
     const int nb = d.n_bonds;
-    T diag = 0;
+    A diag = 0;
     for (int b = 0; b < nb; ++b) {
         const B bd = S.bonds[b];
         const bool eq = ((s >> bd.i) & 1) == ((s >> bd.j) & 1);
-        diag += (eq ? T(0.25) : T(-0.25)) * bd.jz;
+        diag += (eq ? A(0.25) : A(-0.25)) * bd.jz;
     }
-    T acc[NV * C];
+    A acc[NV * C];
     const size_t base = ((size_t)row * nvec + v0) * C;
 #pragma unroll
-    for (int v = 0; v < NV * C; ++v) acc[v] = diag * X[base + v];
-    T rn = T(1);
+    for (int v = 0; v < NV * C; ++v) acc[v] = diag * (A)X[base + v];
+    A rn = A(1);
     if constexpr (KIND != K_U1) rn = S.rsq[d.stab[row]];
     for (int b = 0; b < nb; ++b) {
         const B bd = S.bonds[b];
         if (((s >> bd.i) & 1) == ((s >> bd.j) & 1)) continue;
         const W t = s ^ ((W(1) << bd.i) | (W(1) << bd.j));
         int u, cnt;
-        const int64_t idx = locate<W, KIND, T>(d, S, t, u, cnt);
+        const int64_t idx = locate<W, KIND, A>(d, S, t, u, cnt);
         if (idx < 0) continue;
-        T ar = bd.h, ai = 0;
+        A ar = bd.h, ai = 0;
         if constexpr (KIND != K_U1) {
-            const T f = bd.h * S.sq[cnt] * rn;
+            const A f = bd.h * S.sq[cnt] * rn;
             const auto c = S.chi[u];
             ar = f * c.x;
             if constexpr (CPLX) ai = f * c.y;
@@ -227,16 +229,16 @@ __device__ __forceinline__ void process_row(const SectorDesc &d, const Staged<T>
 #pragma unroll
         for (int v = 0; v < NV; ++v) {
             if constexpr (CPLX) {
-                const T xr = X[xb + 2 * v], xi = X[xb + 2 * v + 1];
-                acc[2 * v] = fmadd<T>(-ai, xi, fmadd<T>(ar, xr, acc[2 * v]));
-                acc[2 * v + 1] = fmadd<T>(ai, xr, fmadd<T>(ar, xi, acc[2 * v + 1]));
+                const A xr = X[xb + 2 * v], xi = X[xb + 2 * v + 1];
+                acc[2 * v] = fmadd<A>(-ai, xi, fmadd<A>(ar, xr, acc[2 * v]));
+                acc[2 * v + 1] = fmadd<A>(ai, xr, fmadd<A>(ar, xi, acc[2 * v + 1]));
             } else {
-                acc[v] = fmadd<T>(ar, X[xb + v], acc[v]);
+                acc[v] = fmadd<A>(ar, (A)X[xb + v], acc[v]);
             }
         }
     }
 #pragma unroll
-    for (int v = 0; v < NV * C; ++v) Y[base + v] = acc[v];
+    for (int v = 0; v < NV * C; ++v) Y[base + v] = (T)acc[v];
 }
 
 // count of the off-diagonal terms of a row that land in the block
@@ -255,19 +257,19 @@ __device__ __forceinline__ uint32_t count_row(const SectorDesc &d, const Staged<
     return n;
 }
 
-template <class W, int KIND, class T, bool CPLX, int NV>
+template <class W, int KIND, class T, class AC, bool CPLX, int NV>
 __global__ __launch_bounds__(APPLY_BLOCK) void k_apply(ApplyArgs A) {
     extern __shared__ __align__(16) unsigned char smem[];
     __shared__ uint32_t s_tile;
     __shared__ SectorDesc s_desc;
-    Staged<T> S;
+    Staged<AC> S;
     if (A.descs == nullptr) {
         const SectorDesc &d = A.one;
-        stage<KIND, T>(d, smem, A.stage_sub, S);
+        stage<KIND, AC>(d, smem, A.stage_sub, S);
         __syncthreads();
         const int64_t stride = (int64_t)gridDim.x * blockDim.x;
         for (int64_t row = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; row < d.dim; row += stride)
-            process_row<W, KIND, T, CPLX, NV>(d, S, row, A.nvec, A.v0);
+            process_row<W, KIND, T, AC, CPLX, NV>(d, S, row, A.nvec, A.v0);
         return;
     }
     // persistent: (sector, row tile) items from one queue
@@ -285,7 +287,7 @@ __global__ __launch_bounds__(APPLY_BLOCK) void k_apply(ApplyArgs A) {
         if (lo != cur) {
             if (threadIdx.x == 0) s_desc = A.descs[lo];
             __syncthreads();
-            stage<KIND, T>(s_desc, smem, A.stage_sub, S);
+            stage<KIND, AC>(s_desc, smem, A.stage_sub, S);
             __syncthreads();
             cur = lo;
         }
@@ -294,7 +296,7 @@ __global__ __launch_bounds__(APPLY_BLOCK) void k_apply(ApplyArgs A) {
         int64_t r1 = r0 + A.tile_rows;
         r1 = r1 < d.dim ? r1 : d.dim;
         for (int64_t row = r0 + threadIdx.x; row < r1; row += blockDim.x)
-            process_row<W, KIND, T, CPLX, NV>(d, S, row, A.nvec, A.v0);
+            process_row<W, KIND, T, AC, CPLX, NV>(d, S, row, A.nvec, A.v0);
         __syncthreads();
     }
 }
@@ -319,24 +321,26 @@ __global__ __launch_bounds__(APPLY_BLOCK) void k_count(ApplyArgs A) {
 
 static __global__ void k_zero_u32(uint32_t *p) { *p = 0; }
 
-// Host launcher for one search kind (instantiated in one translation unit per kind).
+// Host launcher for one search kind (instantiated in one translation unit per
+// kind).  `single`: FP32 vectors; `acc64`: FP64 amplitudes and accumulation
+// (always for FP64 vectors).
 template <int KIND>
-int launch_kind(bool wide, bool single, bool cplx, int nv, const ApplyArgs &A, unsigned grid,
-                unsigned block, size_t lds, hipStream_t st);
+int launch_kind(bool wide, bool single, bool acc64, bool cplx, int nv, const ApplyArgs &A,
+                unsigned grid, unsigned block, size_t lds, hipStream_t st);
 
 template <int KIND>
 int launch_count_kind(bool wide, const ApplyArgs &A, unsigned grid, unsigned block, size_t lds,
                       hipStream_t st);
 
-template <class W, int KIND, class T, bool CPLX>
+template <class W, int KIND, class T, class AC, bool CPLX>
 int launch_nv(int nv, const ApplyArgs &A, unsigned grid, unsigned block, size_t lds,
               hipStream_t st) {
     void (*f)(ApplyArgs) = nullptr;
     switch (nv) {
-        case 1: f = k_apply<W, KIND, T, CPLX, 1>; break;
-        case 2: f = k_apply<W, KIND, T, CPLX, 2>; break;
-        case 4: f = k_apply<W, KIND, T, CPLX, 4>; break;
-        case 8: f = k_apply<W, KIND, T, CPLX, 8>; break;
+        case 1: f = k_apply<W, KIND, T, AC, CPLX, 1>; break;
+        case 2: f = k_apply<W, KIND, T, AC, CPLX, 2>; break;
+        case 4: f = k_apply<W, KIND, T, AC, CPLX, 4>; break;
+        case 8: f = k_apply<W, KIND, T, AC, CPLX, 8>; break;
         default:
             set_error("vectors per pass %d not in {1, 2, 4, 8}", nv);
             return XDG_EINVAL;
@@ -349,32 +353,30 @@ int launch_nv(int nv, const ApplyArgs &A, unsigned grid, unsigned block, size_t 
     return XDG_OK;
 }
 
+template <class W, int KIND, bool CPLX>
+int launch_prec(bool single, bool acc64, int nv, const ApplyArgs &A, unsigned grid,
+                unsigned block, size_t lds, hipStream_t st) {
+    if (!single) return launch_nv<W, KIND, double, double, CPLX>(nv, A, grid, block, lds, st);
+    if (acc64) return launch_nv<W, KIND, float, double, CPLX>(nv, A, grid, block, lds, st);
+    return launch_nv<W, KIND, float, float, CPLX>(nv, A, grid, block, lds, st);
+}
+
 template <int KIND>
-int launch_kind_impl(bool wide, bool single, bool cplx, int nv, const ApplyArgs &A, unsigned grid,
-                     unsigned block, size_t lds, hipStream_t st) {
+int launch_kind_impl(bool wide, bool single, bool acc64, bool cplx, int nv, const ApplyArgs &A,
+                     unsigned grid, unsigned block, size_t lds, hipStream_t st) {
     if constexpr (KIND == K_U1) {
         if (cplx) {
             set_error("complex kernel requested for a U(1) block");
             return XDG_EINVAL;
         }
-        if (wide)
-            return single ? launch_nv<uint64_t, KIND, float, false>(nv, A, grid, block, lds, st)
-                          : launch_nv<uint64_t, KIND, double, false>(nv, A, grid, block, lds, st);
-        return single ? launch_nv<uint32_t, KIND, float, false>(nv, A, grid, block, lds, st)
-                      : launch_nv<uint32_t, KIND, double, false>(nv, A, grid, block, lds, st);
+        return wide ? launch_prec<uint64_t, KIND, false>(single, acc64, nv, A, grid, block, lds, st)
+                    : launch_prec<uint32_t, KIND, false>(single, acc64, nv, A, grid, block, lds, st);
     } else {
-        if (wide) {
-            if (cplx)
-                return single ? launch_nv<uint64_t, KIND, float, true>(nv, A, grid, block, lds, st)
-                              : launch_nv<uint64_t, KIND, double, true>(nv, A, grid, block, lds, st);
-            return single ? launch_nv<uint64_t, KIND, float, false>(nv, A, grid, block, lds, st)
-                          : launch_nv<uint64_t, KIND, double, false>(nv, A, grid, block, lds, st);
-        }
-        if (cplx)
-            return single ? launch_nv<uint32_t, KIND, float, true>(nv, A, grid, block, lds, st)
-                          : launch_nv<uint32_t, KIND, double, true>(nv, A, grid, block, lds, st);
-        return single ? launch_nv<uint32_t, KIND, float, false>(nv, A, grid, block, lds, st)
-                      : launch_nv<uint32_t, KIND, double, false>(nv, A, grid, block, lds, st);
+        if (wide)
+            return cplx ? launch_prec<uint64_t, KIND, true>(single, acc64, nv, A, grid, block, lds, st)
+                        : launch_prec<uint64_t, KIND, false>(single, acc64, nv, A, grid, block, lds, st);
+        return cplx ? launch_prec<uint32_t, KIND, true>(single, acc64, nv, A, grid, block, lds, st)
+                    : launch_prec<uint32_t, KIND, false>(single, acc64, nv, A, grid, block, lds, st);
     }
 }
 

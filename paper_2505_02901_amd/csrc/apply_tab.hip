@@ -4,9 +4,9 @@
 namespace xdg {
 
 template <>
-int launch_kind<K_TAB>(bool wide, bool single, bool cplx, int nv, const ApplyArgs &A, unsigned grid,
-                    unsigned block, size_t lds, hipStream_t st) {
-    return launch_kind_impl<K_TAB>(wide, single, cplx, nv, A, grid, block, lds, st);
+int launch_kind<K_TAB>(bool wide, bool single, bool acc64, bool cplx, int nv, const ApplyArgs &A,
+                    unsigned grid, unsigned block, size_t lds, hipStream_t st) {
+    return launch_kind_impl<K_TAB>(wide, single, acc64, cplx, nv, A, grid, block, lds, st);
 }
 
 template <>

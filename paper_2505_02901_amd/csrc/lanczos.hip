@@ -13,6 +13,8 @@
 #include <algorithm>
 #include <chrono>
 #include <cmath>
+#include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <vector>
 
@@ -240,6 +242,16 @@ struct VecOps {
 
 thread_local double g_t_total = 0.0, g_t_apply = 0.0;
 
+// XDG_LANCZOS_PROGRESS=n: print a line to stderr every n iterations (0 = off)
+int progress_every() {
+    static int every = -1;
+    if (every < 0) {
+        const char *e = getenv("XDG_LANCZOS_PROGRESS");
+        every = e ? std::max(0, atoi(e)) : 0;
+    }
+    return every;
+}
+
 }  // namespace
 
 // Eigenvalues of the symmetric tridiagonal matrix (alpha on the diagonal,
@@ -422,6 +434,10 @@ int lanczos_single(xdg_ham_s *h, const void *v0, int k, double tol, int max_iter
         hipLaunchKernelGGL(k_step_end, dim3(1), dim3(64), 0, st, jdev, prev_beta, cur_beta, 1);
         XDG_TRY_HIP(hipGetLastError());
         m = j + 1;
+        if (progress_every() && m % progress_every() == 0) {
+            XDG_TRY_HIP(hipStreamSynchronize(st));
+            fprintf(stderr, "[xdg] lanczos iteration %d / %d\n", m, max_iter);
+        }
         const bool check = tol > 0.0 || m == max_iter || (m % 16) == 0;
         if (check) {
             XDG_TRY_HIP(hipMemcpyAsync(ha.data(), hist_a, sizeof(double) * m,
@@ -567,9 +583,16 @@ int lanczos_batched(int n, xdg_ham_s *const *hams, const void *const *v0s, int64
         }
         XDG_RETURN_IF(batch_prepare(n, hv.data(), xs.data(), ys.data(), nvec, dtype, &plans[p]));
     }
-    // choose the persistent grid once (outside capture): a few sizes, timed
+    // choose the persistent grid once per set of blocks (outside capture):
+    // a few sizes, timed; remembered for later calls on the same blocks
+    static std::map<std::vector<const void *>, int> grid_cache;
+    std::vector<const void *> gkey(hams, hams + n);
+    gkey.push_back(reinterpret_cast<const void *>((intptr_t)(nvec * 8 + dtype)));
     int best_grid = apply_grid_for(2);
-    {
+    auto cached = grid_cache.find(gkey);
+    if (cached != grid_cache.end()) {
+        best_grid = cached->second;
+    } else {
         hipEvent_t e0, e1;
         XDG_TRY_HIP(hipEventCreate(&e0));
         XDG_TRY_HIP(hipEventCreate(&e1));
@@ -590,6 +613,7 @@ int lanczos_batched(int n, xdg_ham_s *const *hams, const void *const *v0s, int64
         }
         (void)hipEventDestroy(e0);
         (void)hipEventDestroy(e1);
+        grid_cache[gkey] = best_grid;
     }
     auto enqueue_step = [&](int p, bool first) -> int {
         XDG_RETURN_IF(batch_launch(plans[p], best_grid, 8, st));
@@ -639,6 +663,10 @@ int lanczos_batched(int n, xdg_ham_s *const *hams, const void *const *v0s, int64
         if (e != hipSuccess) {
             set_error("graph launch failed: %s", hipGetErrorString(e));
             rc = XDG_EHIP;
+        }
+        if (rc == XDG_OK && progress_every() && (j + 1) % progress_every() == 0) {
+            (void)hipStreamSynchronize(st);
+            fprintf(stderr, "[xdg] batched lanczos iteration %d / %d\n", j + 1, n_iter);
         }
     }
     if (rc == XDG_OK) {

@@ -206,7 +206,7 @@ int apply_batched_launch(int n, xdg_ham_s *const *hams, const void *const *xs, v
 struct BatchPlan {
     DevBuf descs, prefix, queue;
     int n = 0, kind = 0;
-    bool wide = false, single = false, cplx = false;
+    bool wide = false, single = false, cplx = false, acc64 = true;
     int64_t cols = 0;
     uint32_t n_tiles = 0, tile_rows = 0;
     size_t lds = 0;

@@ -38,7 +38,7 @@ class BasisOpts(C.Structure):
                 ("reserved", C.c_int * 5)]
 
 
-XDG_FLAG_LANE_SEARCH = 1
+XDG_FLAG_F32_ACCUMULATE = 2
 
 
 _lib = None
