@@ -42,6 +42,9 @@ def _load():
         lib.orc_rep.argtypes = [C.c_int, C.c_int, P, C.c_uint64, P, P]
         lib.orc_basis.restype = C.c_int64
         lib.orc_basis.argtypes = [C.c_int, C.c_int, C.c_int, P, P, P, C.c_int64]
+        lib.orc_basis_range.restype = C.c_int64
+        lib.orc_basis_range.argtypes = [C.c_int, C.c_int, C.c_int, P, P, C.c_uint64, C.c_uint64,
+                                        P, C.c_int64]
         lib.orc_index.restype = C.c_int64
         lib.orc_index.argtypes = [P, C.c_int64, C.c_uint64]
         lib.orc_row_terms.restype = C.c_int
@@ -114,6 +117,29 @@ def basis(m) -> np.ndarray:
     d2 = lib.orc_basis(m.n_sites, m.n_up, n_sym, _p(perm), _p(chi), _p(out), d)
     assert d2 == d
     return out[:d]
+
+
+def basis_range(m, lo: int, hi: int, cap: int = 1 << 22) -> np.ndarray:
+    """Basis states s with lo <= s <= hi, ascending."""
+    perm, chi, *_ = _model_arrays(m)
+    n_sym = m.n_sym
+    if chi is None and n_sym:
+        chi = np.zeros((n_sym, 2))
+        chi[:, 0] = 1.0
+    out = np.empty(cap, dtype=np.uint64)
+    n = _load().orc_basis_range(m.n_sites, m.n_up, n_sym, _p(perm), _p(chi), lo, hi, _p(out), cap)
+    if n < 0:
+        raise ValueError(f"orc_basis_range failed ({n})")
+    return out[:n].copy()
+
+
+def stabiliser_character_sum(m, s: int) -> complex:
+    """sum of chi over the elements fixing s (zero for orbits without a symmetric state)."""
+    tot = 0j
+    for g, c in zip(m.perm, m.chi):
+        if act(m.n_sites, g, s) == s:
+            tot += c
+    return tot
 
 
 def index(basis_list: np.ndarray, s: int) -> int:

@@ -203,6 +203,33 @@ int64_t orc_basis(int n_sites, int n_up, int n_sym, const int32_t *perm,
     return dim;
 }
 
+/* The basis states lying in [lo, hi] (ascending), by the same sweep as
+   orc_basis restricted to that range.  Returns their number, or -2 if cap is
+   too small. */
+int64_t orc_basis_range(int n_sites, int n_up, int n_sym, const int32_t *perm,
+                        const double *chi, uint64_t lo, uint64_t hi, uint64_t *out, int64_t cap) {
+    if (n_sites < 1 || n_sites > 64 || n_up < 1 || n_up > n_sites || lo > hi) return -1;
+    const uint64_t top = n_sites == 64 ? UINT64_MAX : (((uint64_t)1 << n_sites) - 1);
+    /* smallest popcount-n_up integer >= lo (plain upward scan) */
+    uint64_t s = lo;
+    const uint64_t first = n_up == 64 ? UINT64_MAX : (((uint64_t)1 << n_up) - 1);
+    if (s < first) s = first;
+    while (popcount64(s) != n_up && s < top) ++s;
+    if (popcount64(s) != n_up) return 0;
+    int64_t n = 0;
+    while (s <= hi && s <= top) {
+        int keep = n_sym == 0 || in_sym_basis(n_sites, n_sym, perm, chi, s);
+        if (keep) {
+            if (n >= cap) return -2;
+            out[n++] = s;
+        }
+        uint64_t nx = next_same_popcount(s);
+        if (nx <= s) break;
+        s = nx;
+    }
+    return n;
+}
+
 /* position of s in the ascending basis list, -1 if absent */
 int64_t orc_index(const uint64_t *basis, int64_t dim, uint64_t s) {
     int64_t lo = 0, hi = dim;

@@ -1,0 +1,204 @@
+"""GPU parity at the benchmark sizes (C1-C5), in the launch configuration the
+benchmark times (single-vector apply through the tuned launch, FP32 and FP64).
+
+The oracle cannot enumerate the large sectors whole, so it checks what it can
+compute one by one, and properties that hold at any size check the rest:
+
+* dimension = projection-operator trace formula (independent of both);
+* the GPU basis is strictly ascending, and on windows of the state space it
+  equals the oracle's brute-force enumeration of that window bit for bit;
+* sampled GPU states are representatives of compatible orbits; sampled
+  random states are found (or not) exactly as the oracle says;
+* sampled columns H e_r: the nonzeros, mapped to states through the GPU basis,
+  equal the oracle's row r (Hermitian conjugate), to 1e-12 (FP64) / 2e-6 (FP32);
+* Hermiticity <w, Hx> = conj <x, Hw>, the ferromagnetic bound lambda_max =
+  sum J / 4 in the trivial sector, batched = single launches bitwise.
+"""
+import numpy as np
+import pytest
+
+import oracle
+import workloads as W
+from test_oracle_pins import dimension_formula
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module")
+def X():
+    import paper_2505_02901_amd as X
+    X.lib()
+    return X
+
+
+_built = {}
+
+
+def built(X, name, i=0):
+    key = (name, i)
+    if key not in _built:
+        _built.clear()
+        torch.cuda.empty_cache()
+        m = W.workload(name)[i]
+        b = X.Basis.from_model(m)
+        _built[key] = (m, b, X.Hamiltonian.from_model(b, m))
+    return _built[key]
+
+
+def random_states(m, n, seed):
+    rng = np.random.default_rng(seed)
+    out = []
+    for _ in range(n):
+        bits = rng.choice(m.n_sites, m.n_up, replace=False)
+        out.append(int(sum(1 << int(q) for q in bits)))
+    return out
+
+
+def check_membership(X, m, b, seed, n_members=3000, n_random=3000):
+    D = b.dim
+    rng = np.random.default_rng(seed)
+    pos = np.sort(rng.choice(D, size=min(D, n_members), replace=False))
+    for p in pos[::max(1, len(pos) // 200)]:
+        s = int(b.states(int(p), 1)[0])
+        r, _, _ = oracle.rep(m.n_sites, m.perm, s)
+        assert r == s
+        assert abs(oracle.stabiliser_character_sum(m, s)) > 0.5
+    probes = random_states(m, n_random, seed + 1)
+    reps = []
+    for t in probes:
+        r, _, _ = oracle.rep(m.n_sites, m.perm, t)
+        reps.append(r)
+    idx = b.index(reps)
+    for r, i in zip(reps, idx):
+        compatible = abs(oracle.stabiliser_character_sum(m, r)) > 0.5
+        if compatible:
+            assert i >= 0 and int(b.states(int(i), 1)[0]) == r
+        else:
+            assert i == -1
+    # non-representatives are never found
+    nonrep = [t for t, r in zip(probes, reps) if t != r][:500]
+    assert np.all(b.index(nonrep) == -1)
+
+
+def check_windows(m, b, seed, n_windows=3, width=1500):
+    D = b.dim
+    rng = np.random.default_rng(seed)
+    for p in rng.integers(0, max(1, D - width), n_windows):
+        got = b.states(int(p), min(width, D - int(p)))
+        assert np.all(np.diff(got.astype(np.int64) if m.n_sites < 63 else got) > 0)
+        want = oracle.basis_range(m, int(got[0]), int(got[-1]))
+        assert np.array_equal(got, want)
+
+
+def check_columns(X, m, b, H, seed, n_cols, dtypes):
+    """y = H e_r for oracle-chosen representatives r."""
+    cands = [oracle.rep(m.n_sites, m.perm, t)[0] if m.perm is not None else t
+             for t in random_states(m, 50, seed)]
+    cols = []
+    for r in cands:
+        if m.perm is None or abs(oracle.stabiliser_character_sum(m, r)) > 0.5:
+            cols.append(r)
+        if len(cols) == n_cols:
+            break
+    cplx = b.is_complex
+    for r in cols:
+        j = int(b.index([r])[0])
+        assert j >= 0 and int(b.states(j, 1)[0]) == r
+        d, targets, amps = oracle.row_terms(m, r)
+        want = {}
+        want[r] = want.get(r, 0) + d
+        for s, a in zip(targets, amps):
+            want[int(s)] = want.get(int(s), 0) + a
+        for dt, tol in dtypes:
+            dt = {torch.float64: torch.complex128, torch.float32: torch.complex64}[dt] if cplx else dt
+            x = torch.zeros(b.dim, dtype=dt, device="cuda")
+            x[j] = 1
+            y = torch.empty_like(x)
+            H.apply(x, y)
+            torch.cuda.synchronize()
+            nz = torch.nonzero(y).flatten().cpu().numpy()
+            vals = y[torch.from_numpy(nz).cuda()].cpu().numpy() if len(nz) else np.zeros(0)
+            states = np.array([int(b.states(int(i), 1)[0]) for i in nz], dtype=np.uint64)
+            got = {int(s): v for s, v in zip(states, vals)}
+            nonzero_want = {s: v for s, v in want.items() if abs(v) > 1e-14}
+            assert set(got) == set(nonzero_want), (r, dt)
+            scale = max(abs(v) for v in nonzero_want.values())
+            for s, v in nonzero_want.items():
+                # y[i] = H[i, r] = conj(H[r, i])
+                assert abs(got[s] - np.conj(v)) <= tol * scale, (r, s, got[s], v)
+
+
+def test_c1_full_oracle_parity(X):
+    m = W.workload("chain16_u1")[0]
+    b = X.Basis.from_model(m)
+    H = X.Hamiltonian.from_model(b, m)
+    basis = oracle.basis(m)
+    assert np.array_equal(b.states(), basis)
+    x = W.random_vector(1, len(basis), kind="uniform")
+    y_or = oracle.apply(m, basis, x).real
+    for dt, tol in ((torch.float64, 1e-12), (torch.float32, 2e-6)):
+        xt = torch.from_numpy(x).to("cuda", dt)
+        yt = torch.empty_like(xt)
+        H.apply(xt, yt)
+        torch.cuda.synchronize()
+        y = yt.cpu().numpy()
+        assert np.max(np.abs(y - y_or)) < tol * np.max(np.abs(y_or))
+    assert H.nnz == 122694
+
+
+@pytest.mark.parametrize("i", [0, 1], ids=["k0", "kpi"])
+def test_c2_fullsize(X, i):
+    m, b, H = built(X, "chain32_k0_kpi", i)
+    assert b.dim == dimension_formula(m) == 18784170
+    check_windows(m, b, 10 + i)
+    check_membership(X, m, b, 20 + i)
+    check_columns(X, m, b, H, 30 + i, 4, [(torch.float64, 1e-12), (torch.float32, 2e-6)])
+
+
+def test_c3_fullsize(X):
+    m, b, H = built(X, "square36_j1j2_A1")
+    assert b.dim == dimension_formula(m) == 31566122
+    check_windows(m, b, 40, n_windows=2, width=600)
+    check_membership(X, m, b, 41, n_members=1000, n_random=1000)
+    check_columns(X, m, b, H, 42, 3, [(torch.float64, 1e-12), (torch.float32, 2e-6)])
+    # Hermiticity at full size
+    x = torch.randn(b.dim, dtype=torch.float64, device="cuda")
+    w = torch.randn(b.dim, dtype=torch.float64, device="cuda")
+    hx, hw = torch.empty_like(x), torch.empty_like(w)
+    H.apply(x, hx)
+    H.apply(w, hw)
+    lhs, rhs = torch.dot(w, hx).item(), torch.dot(x, hw).item()
+    assert abs(lhs - rhs) < 1e-10 * abs(lhs)
+    del x, w, hx, hw
+
+
+def test_c3_ferromagnetic_bound(X):
+    m, b, _ = built(X, "square36_j1j2_A1")
+    Hn = X.Hamiltonian(b, m.sites, -m.jz, -m.jxy)
+    st, ev, al, be = Hn.lanczos(k=1, tol=1e-13, max_iter=300, seed=5, prec=0)
+    assert abs(-ev[0] - m.jz.sum() / 4.0) < 1e-9
+    assert m.jz.sum() / 4.0 == 27.0
+
+
+def test_c4_batched_equals_single_fullsize(X):
+    ms = [W.workload("chain32_allk")[l] for l in (0, 5, 16)]
+    bs = [X.Basis.from_model(m) for m in ms]
+    hs = [X.Hamiltonian.from_model(b, m) for b, m in zip(bs, ms)]
+    xs = [torch.randn(b.dim, 2, dtype=torch.complex64, device="cuda") for b in bs]
+    ys = [torch.empty_like(x) for x in xs]
+    X.xdg_apply_batched([h.handle for h in hs], xs, ys)
+    for h, x, y in zip(hs, xs, ys):
+        r = torch.empty_like(x)
+        h.apply(x, r)
+        torch.cuda.synchronize()
+        assert torch.equal(r, y)
+    assert [b.dim for b in bs] == [dimension_formula(m) for m in ms]
+
+
+def test_c5_fullsize(X):
+    m, b, H = built(X, "tilted40_xxz")
+    assert b.dim == dimension_formula(m) == 861602748
+    check_windows(m, b, 50, n_windows=2, width=400)
+    check_membership(X, m, b, 51, n_members=600, n_random=600)
+    check_columns(X, m, b, H, 52, 2, [(torch.float64, 1e-12)])

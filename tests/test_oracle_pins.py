@@ -293,6 +293,18 @@ def test_basis_against_brute_force(oracle_lib):
             range(len(want)))
 
 
+def test_basis_range_is_a_window_of_the_basis(oracle_lib):
+    rng = np.random.default_rng(3)
+    for m in (W.chain_model(14, l=3), W.torus_model((4, 0), (0, 4), 1.0, 0.5, "B1"),
+              W.chain_model(12)):
+        full = oracle_lib.basis(m)
+        for _ in range(5):
+            lo, hi = sorted(int(v) for v in rng.integers(0, 1 << m.n_sites, 2))
+            want = full[(full >= lo) & (full <= hi)]
+            assert np.array_equal(oracle_lib.basis_range(m, lo, hi), want)
+        assert np.array_equal(oracle_lib.basis_range(m, 0, (1 << m.n_sites) - 1), full)
+
+
 @pytest.mark.slow
 def test_table1_block_sizes(oracle_lib):
     g = load_gold("table1_block_sizes.json")
