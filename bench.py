@@ -41,7 +41,7 @@ HBM_PEAK_GBS = 8000.0
 E0_ITERS = {"chain16_u1": 300, "chain32_k0_kpi": 200, "square36_j1j2_A1": 200,
             "chain32_allk": 100, "tilted40_xxz": 100}
 DEFAULT_STEPS = {"chain16_u1": 200, "chain32_k0_kpi": 40, "square36_j1j2_A1": 10,
-                 "chain32_allk": 5, "tilted40_xxz": 3}
+                 "chain32_allk": 20, "tilted40_xxz": 3}
 
 
 def log(*a):
@@ -182,6 +182,7 @@ class Ctx:
         e1.record(st)
         e1.synchronize()
         sec = e0.elapsed_time(e1) * 1e-3 / reps
+        del x, y
         m = self.models[0]
         sym = m.perm is not None
         word = 8 if m.n_sites > 32 else 4
@@ -189,7 +190,6 @@ class Ctx:
         alg = alg_bytes(d, n, word, vb, nvec, sym)
         khash = source_hash()
         achieved = alg / sec / 1e9
-        del x, y
         torch.cuda.empty_cache()
         return {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": achieved / HBM_PEAK_GBS,
@@ -268,8 +268,66 @@ def run_batched(c: Ctx):
     }
 
 
+def counters_run(args):
+    """Workload for the counter runs: three applies of the first sector (FP32,
+    one vector), the last of which is summarised, then a plain 1 GiB device
+    copy whose FETCH_SIZE / WRITE_SIZE calibrate the counters."""
+    import torch
+    import paper_2505_02901_amd as X
+    import workloads as W
+    m = W.workload(args.workload)[0]
+    b = X.Basis.from_model(m)
+    h = X.Hamiltonian.from_model(b, m)
+    dt = torch.complex64 if b.is_complex else torch.float32
+    x = torch.randn(b.dim, dtype=dt, device="cuda")
+    y = torch.empty_like(x)
+    for _ in range(3):
+        h.apply(x, y)
+    torch.cuda.synchronize()
+    a = torch.empty(256 << 20, dtype=torch.float32, device="cuda")
+    c = torch.empty_like(a)
+    c.copy_(a)
+    torch.cuda.synchronize()
+    print(json.dumps({"workload": args.workload, "dim": b.dim, "nnz": h.nnz,
+                      "copy_bytes": a.numel() * 4}))
+
+
+def summarize_counters(args):
+    """profiles/traffic_<workload>.json from the CSVs of the FETCH_SIZE and
+    WRITE_SIZE runs (last apply dispatch of each; counts in KiB, scaled by the
+    copy calibration)."""
+    import csv
+    import glob
+
+    def read(d, counter):
+        f = glob.glob(os.path.join(d, "**", "*counter_collection.csv"), recursive=True)[0]
+        rows = [r for r in csv.DictReader(open(f)) if r["Counter_Name"] == counter]
+        app = [r for r in rows if "k_apply" in r["Kernel_Name"]][-1]
+        cp = [r for r in rows if "copyBuffer" in r["Kernel_Name"] or "copy" in r["Kernel_Name"]]
+        cp = max(cp, key=lambda r: float(r["Counter_Value"]))
+        return float(app["Counter_Value"]), float(cp["Counter_Value"]), app["Kernel_Name"]
+
+    fetch, fetch_cp, kname = read(args.summarize_counters[0], "FETCH_SIZE")
+    write, write_cp, _ = read(args.summarize_counters[1], "WRITE_SIZE")
+    copy_bytes = 256 << 22
+    f_scale = copy_bytes / (fetch_cp * 1024.0)
+    w_scale = copy_bytes / (write_cp * 1024.0)
+    traffic = fetch * 1024.0 * f_scale + write * 1024.0 * w_scale
+    out = {"workload": args.workload, "kernel": kname, "source_hash": source_hash(),
+           "fetch_kib": fetch, "write_kib": write, "copy_fetch_kib": fetch_cp,
+           "copy_write_kib": write_cp, "fetch_scale": f_scale, "write_scale": w_scale,
+           "traffic_bytes_per_launch": traffic}
+    p = os.path.join(ROOT, "profiles", f"traffic_{args.workload}.json")
+    with open(p, "w") as f:
+        json.dump(out, f, indent=1)
+    print(json.dumps(out))
+
+
 def main():
     ap = argparse.ArgumentParser()
+    ap.add_argument("--counters", action="store_true",
+                    help="run the profiled apply + calibration copy (under rocprofv3 --pmc)")
+    ap.add_argument("--summarize-counters", nargs=2, metavar=("FETCH_DIR", "WRITE_DIR"))
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=None)
     ap.add_argument("--warmup", type=int, default=None)
@@ -278,6 +336,9 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--e0-iters", type=int, default=None)
     args = ap.parse_args()
+    if args.summarize_counters:
+        summarize_counters(args)
+        return
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU: this build has no multi-GPU path "
               "(run with --gpus 1)", file=sys.stderr)
@@ -289,6 +350,9 @@ def main():
     import torch
     assert torch.cuda.is_available(), "bench needs a GPU"
     torch.cuda.set_device(0)
+    if args.counters:
+        counters_run(args)
+        return
     c = Ctx(args)
     X = c.X
     log(f"workload {args.workload}: dims {c.dims[:4]}{'...' if len(c.dims) > 4 else ''} "

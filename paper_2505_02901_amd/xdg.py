@@ -178,10 +178,11 @@ def xdg_check_bonds(n_sites: int, perm, sites, jz, jxy) -> int:
     return lib().xdg_check_bonds(n_sites, n_sym, pp, len(jz), ps, pz, px)
 
 
-def xdg_plan_search(n_sites: int, perm, search: int = 0, n_sublattices: int = 0):
+def xdg_plan_search(n_sites: int, perm, search: int = 0, n_sublattices: int = 0,
+                    flags: int = 0):
     perm, pp = _arr(perm, np.int32)
     n_sym = 0 if perm is None else perm.shape[0]
-    o = BasisOpts(search, n_sublattices)
+    o = BasisOpts(search, n_sublattices, flags)
     k, ns = C.c_int(), C.c_int()
     _check(lib().xdg_plan_search(n_sites, n_sym, pp, C.byref(o), C.byref(k), C.byref(ns)))
     return k.value, ns.value
