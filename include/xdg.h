@@ -87,6 +87,24 @@ typedef struct xdg_basis_opts {
  *   amplitudes and accumulation, one rounding to FP32 when the row is
  *   stored; the vectors are FP32 in memory either way). */
 #define XDG_FLAG_F32_ACCUMULATE 2
+/* XDG_FLAG_HASH_INDEX: index a symmetric block with the hash table even when
+ *   the rank bitmap (below) would fit. */
+#define XDG_FLAG_HASH_INDEX 4
+
+/* Index of a block (Sec. 5.2: state -> position in the ascending basis):
+ * XDG_INDEX_LIN   no permutation group: Lin's two tables;
+ * XDG_INDEX_HASH  open addressing over 64-byte lines of (state, position);
+ * XDG_INDEX_RANK  rank bitmap: one (u32 count, u32 bits) pair per 32
+ *                 consecutive colex ranks among the states with n_up up
+ *                 spins, up to the rank of the largest representative; the
+ *                 position of s is the count of its word plus the set bits
+ *                 below s's bit.  Colex rank preserves numeric order, so the
+ *                 lookups of neighbouring rows touch neighbouring words.
+ *                 Chosen when it takes at most 4x the hash table's memory
+ *                 plus 64 MiB, unless XDG_FLAG_HASH_INDEX is set. */
+#define XDG_INDEX_LIN  1
+#define XDG_INDEX_HASH 2
+#define XDG_INDEX_RANK 3
 
 /* Version string of the library (cf. the version banner, Sec. 2). */
 const char *xdg_version(void);
@@ -139,6 +157,9 @@ int xdg_basis_is_complex(xdg_basis b, int *is_complex);
 
 /* Search kind in use and its number of sublattices (0 unless sublattice). */
 int xdg_basis_search_kind(xdg_basis b, int *kind, int *n_sublattices);
+
+/* Index kind in use (XDG_INDEX_*) and its device memory in bytes. */
+int xdg_basis_index_kind(xdg_basis b, int *kind, int64_t *bytes);
 
 /* Copy basis states [begin, begin + count) (ascending representatives) to
  * host memory (iteration over a block, Sec. 3.1 / 3.11). */

@@ -63,6 +63,12 @@ SectorDesc make_desc(const xdg_ham_s *h, bool single, const void *x, void *y) {
                       : (b->n_up == b->n_sites ? 0ull : 0xFFFFFFFFull);
     d.lin = b->lin.as<uint32_t>();
     d.nlo = b->lin_nlo;
+    d.rwords = b->n_rwords ? b->rwords.as<uint2>() : nullptr;
+    d.n_rwords = b->n_rwords;
+    d.rtab = b->rtab.as<uint64_t>();
+    d.rcb = b->rank_cb;
+    d.rnc = b->rank_nc;
+    d.rnb = b->n_up + 1;
     d.n_sites = b->n_sites;
     d.n_sym = b->n_sym;
     d.n_bonds = h->n_bonds;

@@ -47,6 +47,10 @@ struct SectorDesc {
     const void *hash;
     uint64_t n_lines;
     uint64_t empty;
+    const uint2 *rwords;         // rank index (null: hash)
+    uint64_t n_rwords;
+    const uint64_t *rtab;        // colex chunk tables [rnc][rnb][2^rcb]
+    int rcb, rnc, rnb;
     const uint32_t *lin;         // Lin tables (U(1))
     int nlo;
     int n_sites, n_sym, n_bonds;
@@ -93,6 +97,10 @@ __host__ __device__ inline size_t sub_table_bytes(const SectorDesc &d) {
            a16(2 * (size_t)d.n_perm * 2 * ((size_t)1 << d.pb));
 }
 
+__host__ __device__ inline size_t rank_table_len(const SectorDesc &d) {
+    return d.rwords ? ((size_t)d.rnc * d.rnb) << d.rcb : 0;
+}
+
 // LDS bytes needed to stage a sector's tables.
 template <class T>
 __host__ __device__ inline size_t stage_bytes(const SectorDesc &d, int kind, int stage_sub) {
@@ -100,6 +108,7 @@ __host__ __device__ inline size_t stage_bytes(const SectorDesc &d, int kind, int
     if (kind != K_U1) {
         n += a16(sizeof(typename Vec2<T>::type) * d.n_sym);
         n += a16(sizeof(T) * 2 * (d.n_sym + 1));
+        n += a16(8 * rank_table_len(d));
         if (kind == K_AFF) n += a16(sizeof(AffineElem) * d.n_sym) + a16(4 * (size_t)d.n_sites);
         if (kind == K_SUB && stage_sub) n += sub_table_bytes(d);
     }
@@ -114,6 +123,7 @@ struct Staged {
     const T *rsq;      // 1/sqrt(c)
     const AffineElem *aff;
     const int16_t *ring_gidx;
+    const uint64_t *rtab;
     SubCtx sub;
 };
 
@@ -137,6 +147,7 @@ __device__ inline void stage(const SectorDesc &d, unsigned char *smem, int stage
         const T *ls = stage_copy(smem, off, reinterpret_cast<const T *>(d.sqrtt), 2 * (d.n_sym + 1));
         S.sq = ls;
         S.rsq = ls + d.n_sym + 1;
+        S.rtab = d.rwords ? stage_copy(smem, off, d.rtab, rank_table_len(d)) : nullptr;
         if constexpr (KIND == K_AFF) {
             S.aff = stage_copy(smem, off, d.aff, d.n_sym);
             int16_t *lg = reinterpret_cast<int16_t *>(smem + off);
@@ -182,6 +193,8 @@ __device__ __forceinline__ int64_t locate(const SectorDesc &d, const Staged<T> &
         } else {
             tab_search<W>(d.bytetab, d.n_bchunks, d.n_sym, t, rep, u, cnt);
         }
+        if (d.rwords)
+            return rank_find(d.rwords, d.n_rwords, colex_rank<W>(S.rtab, d.rcb, d.rnc, d.rnb, rep));
         return hash_find<W>(d.hash, d.n_lines, (W)d.empty, rep);
     }
 }

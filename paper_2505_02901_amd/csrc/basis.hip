@@ -264,12 +264,34 @@ __global__ __launch_bounds__(256) void k_hash_insert(const W *reps, uint64_t dim
     }
 }
 
+// ------------------------------------------------------------------- rank --
+// Sets the bit of every basis state; the first state of each word (the reps
+// are ascending and the colex rank preserves their order) writes its index
+// as the word's count.
+template <class W>
+__global__ __launch_bounds__(256) void k_rank_build(const W *reps, uint64_t dim, const uint64_t *T,
+                                                    int cb, int nc, int nb, uint2 *words) {
+    const uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= dim) return;
+    const uint64_t r = colex_rank<W>(T, cb, nc, nb, reps[i]);
+    const uint64_t w = r >> 5;
+    atomicOr(&words[w].y, 1u << (uint32_t)(r & 31));
+    if (i == 0 || (colex_rank<W>(T, cb, nc, nb, reps[i - 1]) >> 5) != w) words[w].x = (uint32_t)i;
+}
+
 // index of arbitrary states (-1 when absent)
+struct RankArgs {
+    const uint2 *words;
+    uint64_t n_words;   // 0: no rank index
+    const uint64_t *tab;
+    int cb, nc, nb;
+};
+
 template <class W>
 __global__ __launch_bounds__(256) void k_lookup(const uint64_t *states, int64_t n, int64_t *out,
                                                 int N, int n_up, int u1, const uint32_t *lin,
                                                 int nlo, const void *table, uint64_t n_lines,
-                                                W empty) {
+                                                W empty, RankArgs R) {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
     const uint64_t s = states[i];
@@ -279,6 +301,8 @@ __global__ __launch_bounds__(256) void k_lookup(const uint64_t *states, int64_t 
         if (u1) {
             const uint64_t lo = s & ((1ull << nlo) - 1), hi = s >> nlo;
             r = (int64_t)lin[(1ull << nlo) + hi] + (int64_t)lin[lo];
+        } else if (R.n_words) {
+            r = rank_find(R.words, R.n_words, colex_rank<W>(R.tab, R.cb, R.nc, R.nb, (W)s));
         } else if (n_lines) {
             r = hash_find<W>(table, n_lines, empty, (W)s);
         }
@@ -471,6 +495,71 @@ int build_hash(xdg_basis_s *b) {
     return XDG_OK;
 }
 
+// Chunk tables of the colex rank: T[k][below][v] = sum over the set bits of
+// v, the i-th (from the bottom) at site p = k cb + q, of C(p, below + i);
+// sites beyond N contribute nothing.  cb is the widest chunk whose tables
+// stay within 32 KiB (they are staged in LDS by the apply kernels).
+void rank_tables(int N, int n_up, int &cb, int &nc, std::vector<uint64_t> &T) {
+    const int nb = n_up + 1;
+    for (cb = 8; cb > 1; --cb) {
+        nc = (N + cb - 1) / cb;
+        if ((((size_t)nc * nb) << cb) * 8 <= 32768) break;
+    }
+    nc = (N + cb - 1) / cb;
+    T.assign(((size_t)nc * nb) << cb, 0);
+    for (int k = 0; k < nc; ++k)
+        for (int below = 0; below < nb; ++below)
+            for (uint32_t v = 0; v < (1u << cb); ++v) {
+                uint64_t r = 0;
+                int c = below;
+                for (int q = 0; q < cb; ++q) {
+                    if (!((v >> q) & 1)) continue;
+                    ++c;
+                    const int p = k * cb + q;
+                    if (p < N) r += binomial(p, c);
+                }
+                T[(((size_t)k * nb + below) << cb) | v] = r;
+            }
+}
+
+uint64_t colex_rank_host(uint64_t s) {
+    uint64_t r = 0;
+    int c = 0;
+    for (int p = 0; p < 64; ++p)
+        if ((s >> p) & 1) r += binomial(p, ++c);
+    return r;
+}
+
+// Rank index when it fits (see XDG_INDEX_RANK); returns XDG_OK with
+// b->n_rwords = 0 when the hash index should be used instead.
+template <class W>
+int build_rank(xdg_basis_s *b) {
+    const uint64_t dim = (uint64_t)b->dim;
+    if (b->plan.flags & XDG_FLAG_HASH_INDEX) return XDG_OK;
+    uint64_t last = 0;
+    XDG_TRY_HIP(hipMemcpy(&last, b->reps.as<W>() + (dim - 1), sizeof(W), hipMemcpyDeviceToHost));
+    const uint64_t n_words = (colex_rank_host(last) >> 5) + 1;
+    const int slots = sizeof(W) == 4 ? 8 : 5;
+    const double hash_bytes = 64.0 * std::ceil((double)dim / (slots * 0.5));
+    if ((double)n_words * 8.0 > 4.0 * hash_bytes + 64.0 * (1 << 20)) return XDG_OK;
+    std::vector<uint64_t> T;
+    int cb = 0, nc = 0;
+    rank_tables(b->n_sites, b->n_up, cb, nc, T);
+    XDG_RETURN_IF(b->rtab.upload(T.data(), T.size() * 8));
+    XDG_RETURN_IF(b->rwords.alloc(8 * n_words));
+    XDG_TRY_HIP(hipMemset(b->rwords.p, 0, 8 * n_words));
+    const int block = 256;
+    hipLaunchKernelGGL(k_rank_build<W>, dim3((unsigned)((dim + block - 1) / block)), dim3(block), 0,
+                       0, b->reps.as<W>(), dim, b->rtab.as<uint64_t>(), cb, nc, b->n_up + 1,
+                       b->rwords.as<uint2>());
+    XDG_TRY_HIP(hipGetLastError());
+    XDG_TRY_HIP(hipDeviceSynchronize());
+    b->n_rwords = n_words;
+    b->rank_cb = cb;
+    b->rank_nc = nc;
+    return XDG_OK;
+}
+
 int build_lin(xdg_basis_s *b) {
     // index(s) = L_hi[hi] + L_lo[lo]: L_lo = colex rank of lo among the
     // lo' with the same popcount, L_hi[hi] = number of basis states whose
@@ -551,9 +640,11 @@ int basis_build_device(xdg_basis_s *b) {
         XDG_RETURN_IF(build_lin(b));
     } else if (b->dim > 0) {
         if (b->wide) {
-            XDG_RETURN_IF(build_hash<uint64_t>(b));
+            XDG_RETURN_IF(build_rank<uint64_t>(b));
+            if (!b->n_rwords) XDG_RETURN_IF(build_hash<uint64_t>(b));
         } else {
-            XDG_RETURN_IF(build_hash<uint32_t>(b));
+            XDG_RETURN_IF(build_rank<uint32_t>(b));
+            if (!b->n_rwords) XDG_RETURN_IF(build_hash<uint32_t>(b));
         }
     }
     return XDG_OK;
@@ -565,16 +656,18 @@ int basis_lookup(xdg_basis_s *b, const uint64_t *d_states, int64_t n, int64_t *d
     const int block = 256;
     const unsigned grid = (unsigned)((n + block - 1) / block);
     const int u1 = b->plan.kind == K_U1;
+    const RankArgs R{b->rwords.as<uint2>(), b->n_rwords, b->rtab.as<uint64_t>(), b->rank_cb,
+                     b->rank_nc, b->n_up + 1};
     if (b->wide) {
         const uint64_t empty = b->n_up == b->n_sites ? 0ull : ~0ull;
         hipLaunchKernelGGL(k_lookup<uint64_t>, dim3(grid), dim3(block), 0, st, d_states, n, d_idx,
                            b->n_sites, b->n_up, u1, b->lin.as<uint32_t>(), b->lin_nlo, b->hash.p,
-                           b->dim > 0 ? b->hidx.n_lines : 0, empty);
+                           b->dim > 0 ? b->hidx.n_lines : 0, empty, R);
     } else {
         const uint32_t empty = b->n_up == b->n_sites ? 0u : ~0u;
         hipLaunchKernelGGL(k_lookup<uint32_t>, dim3(grid), dim3(block), 0, st, d_states, n, d_idx,
                            b->n_sites, b->n_up, u1, b->lin.as<uint32_t>(), b->lin_nlo, b->hash.p,
-                           b->dim > 0 ? b->hidx.n_lines : 0, empty);
+                           b->dim > 0 ? b->hidx.n_lines : 0, empty, R);
     }
     XDG_TRY_HIP(hipGetLastError());
     return XDG_OK;

@@ -143,6 +143,22 @@ int xdg_basis_search_kind(xdg_basis b, int *kind, int *n_sublattices) {
     return XDG_OK;
 }
 
+int xdg_basis_index_kind(xdg_basis b, int *kind, int64_t *bytes) {
+    if (!b) {
+        set_error("null basis");
+        return XDG_EINVAL;
+    }
+    int k = XDG_INDEX_LIN;
+    size_t n = b->lin.bytes;
+    if (b->plan.kind != XDG_SEARCH_U1) {
+        k = b->n_rwords ? XDG_INDEX_RANK : XDG_INDEX_HASH;
+        n = b->n_rwords ? b->rwords.bytes + b->rtab.bytes : b->hash.bytes;
+    }
+    if (kind) *kind = k;
+    if (bytes) *bytes = (int64_t)n;
+    return XDG_OK;
+}
+
 int xdg_basis_copy_states(xdg_basis b, int64_t begin, int64_t count, uint64_t *host_out) {
     return guarded([&]() -> int {
         if (!b || (count > 0 && !host_out) || begin < 0 || count < 0 || begin + count > b->dim) {

@@ -37,6 +37,36 @@ __device__ __forceinline__ W rev_n(W t, int N) {
         return __builtin_bitreverse64(t) >> (64 - N);
 }
 
+// ------------------------------------------------------------- rank index --
+// Colex rank of a state among the states of its popcount: the i-th set bit
+// (from the bottom, i = 1, 2, ...) at site p contributes C(p, i).  It is
+// summed per chunk of cb sites from tables T[k][below][v] (below = set bits
+// under chunk k, v = the chunk's bits), so a rank costs nc table reads.
+template <class W>
+__device__ __forceinline__ uint64_t colex_rank(const uint64_t *T, int cb, int nc, int nb, W s) {
+    uint64_t r = 0;
+    uint32_t below = 0;
+    const uint32_t mask = (1u << cb) - 1;
+    for (int k = 0; k < nc; ++k) {
+        const uint32_t v = (uint32_t)((uint64_t)s >> (k * cb)) & mask;
+        r += T[(((uint32_t)k * nb + below) << cb) | v];
+        below += __popc(v);
+    }
+    return r;
+}
+
+// Position of the state of colex rank r, or -1: words[r / 32] holds the
+// number of basis states of smaller rank (valid in words holding a state)
+// and one bit per rank.
+__device__ __forceinline__ int64_t rank_find(const uint2 *words, uint64_t n_words, uint64_t r) {
+    const uint64_t w = r >> 5;
+    if (w >= n_words) return -1;
+    const uint2 e = words[w];
+    const uint32_t b = (uint32_t)r & 31u;
+    if (!((e.y >> b) & 1u)) return -1;
+    return (int64_t)e.x + __popc(e.y & ((1u << b) - 1u));
+}
+
 // ------------------------------------------------------------- hash index --
 // Open addressing over 64-byte lines; a lookup reads one line in the common
 // case.  A line holds 8 (key u32, value u32) or 5 (key u64, value u32) pairs.

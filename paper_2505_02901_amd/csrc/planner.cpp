@@ -345,7 +345,7 @@ int make_plan(int n_sites, int n_sym, const int32_t *perm, const xdg_basis_opts 
         return XDG_EINVAL;
     }
     const int flags = opts ? opts->flags : 0;
-    if (flags & ~XDG_FLAG_F32_ACCUMULATE) {
+    if (flags & ~(XDG_FLAG_F32_ACCUMULATE | XDG_FLAG_HASH_INDEX)) {
         set_error("unknown flags 0x%x", flags);
         return XDG_EINVAL;
     }

@@ -143,6 +143,12 @@ struct xdg_basis_s {
     xdg::DevBuf hash;           // 64-byte lines
     xdg::HashIndex hidx;
     xdg::DevBuf lin;            // u32 [2^nlo + 2^nhi] Lin tables (U(1))
+    // rank index (symmetric blocks): uint2 {count, bits} per 32 colex ranks,
+    // and the chunk tables of the colex rank (u64 [nc][n_up + 1][2^cb])
+    xdg::DevBuf rwords;
+    uint64_t n_rwords = 0;      // 0: the hash index is used
+    xdg::DevBuf rtab;
+    int rank_cb = 0, rank_nc = 0;
     int lin_nlo = 0, lin_nhi = 0;
     xdg::DevBuf t_src, t_pid, t_tperm, t_mintop, t_candoff, t_candlist, t_bytes, t_aff, t_ring;
     xdg::DevBuf chi_d;          // double2 [n_sym]

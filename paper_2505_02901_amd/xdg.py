@@ -39,6 +39,8 @@ class BasisOpts(C.Structure):
 
 
 XDG_FLAG_F32_ACCUMULATE = 2
+XDG_FLAG_HASH_INDEX = 4
+XDG_INDEX_LIN, XDG_INDEX_HASH, XDG_INDEX_RANK = 1, 2, 3
 
 
 _lib = None
@@ -64,6 +66,7 @@ def lib():
             "xdg_basis_dim": (I, [P, P]),
             "xdg_basis_is_complex": (I, [P, P]),
             "xdg_basis_search_kind": (I, [P, P, P]),
+            "xdg_basis_index_kind": (I, [P, P, P]),
             "xdg_basis_copy_states": (I, [P, I64, I64, P]),
             "xdg_basis_copy_stabilisers": (I, [P, I64, I64, P]),
             "xdg_basis_index": (I, [P, P, I64, P]),
@@ -88,7 +91,8 @@ def lib():
 def exported_names():
     return ["xdg_version", "xdg_last_error", "xdg_check_group", "xdg_check_bonds",
             "xdg_plan_search", "xdg_create_basis", "xdg_destroy_basis", "xdg_basis_dim",
-            "xdg_basis_is_complex", "xdg_basis_search_kind", "xdg_basis_copy_states",
+            "xdg_basis_is_complex", "xdg_basis_search_kind", "xdg_basis_index_kind",
+            "xdg_basis_copy_states",
             "xdg_basis_copy_stabilisers", "xdg_basis_index", "xdg_create_hamiltonian",
             "xdg_destroy_hamiltonian", "xdg_ham_nnz", "xdg_apply", "xdg_apply_batched",
             "xdg_random_state", "xdg_lanczos_eigval", "xdg_lanczos_eigval_batched",
@@ -219,6 +223,13 @@ def xdg_basis_search_kind(b) -> Tuple[int, int]:
     k, ns = C.c_int(), C.c_int()
     _check(lib().xdg_basis_search_kind(b, C.byref(k), C.byref(ns)))
     return k.value, ns.value
+
+
+def xdg_basis_index_kind(b) -> Tuple[int, int]:
+    """(XDG_INDEX_* kind, device bytes of the index)."""
+    k, n = C.c_int(), C.c_int64()
+    _check(lib().xdg_basis_index_kind(b, C.byref(k), C.byref(n)))
+    return k.value, n.value
 
 
 def xdg_basis_copy_states(b, begin: int = 0, count: Optional[int] = None) -> np.ndarray:
@@ -355,6 +366,10 @@ class Basis:
     @property
     def search_kind(self) -> Tuple[int, int]:
         return xdg_basis_search_kind(self.handle)
+
+    @property
+    def index_kind(self) -> Tuple[int, int]:
+        return xdg_basis_index_kind(self.handle)
 
     def states(self, begin: int = 0, count: Optional[int] = None) -> np.ndarray:
         return xdg_basis_copy_states(self.handle, begin, count)

@@ -59,7 +59,9 @@ _cache = {}
 
 
 def oracle_basis(m):
-    key = id(m)
+    # keyed by content: ids of freed temporary models are reused
+    key = (m.n_sites, m.n_up, None if m.perm is None else m.perm.tobytes(),
+           None if m.chi is None else np.asarray(m.chi).tobytes())
     if key not in _cache:
         _cache[key] = oracle.basis(m)
     return _cache[key]
@@ -77,9 +79,28 @@ def rel_err(a, b):
     return np.max(np.abs(a - b)) / max(np.max(np.abs(b)), 1e-300)
 
 
+INDEXES = ["rank", "hash"]
+
+
+def make_basis(X, m, index):
+    """Basis with the default index (the rank bitmap for these small sectors)
+    or with the hash index forced; U(1) blocks always use Lin's tables."""
+    b = X.Basis.from_model(m, flags=X.XDG_FLAG_HASH_INDEX if index == "hash" else 0)
+    kind, nbytes = b.index_kind
+    if m.perm is None:
+        assert kind == X.XDG_INDEX_LIN
+    else:
+        assert kind == (X.XDG_INDEX_HASH if index == "hash" else X.XDG_INDEX_RANK)
+    assert nbytes > 0
+    return b
+
+
+@pytest.mark.parametrize("index", INDEXES)
 @pytest.mark.parametrize("m", MODELS, ids=IDS)
-def test_basis_bit_exact(X, m):
-    b = X.Basis.from_model(m)
+def test_basis_bit_exact(X, m, index):
+    if m.perm is None and index == "hash":
+        pytest.skip("U(1) blocks have one index")
+    b = make_basis(X, m, index)
     want = oracle_basis(m)
     got = b.states()
     assert b.dim == len(want)
@@ -96,13 +117,26 @@ def test_basis_bit_exact(X, m):
         bits = rng.choice(m.n_sites, m.n_up, replace=False)
         probes.append(int(sum(1 << int(q) for q in bits)))
     probes += [(1 << m.n_sites) - 1, 0, int(want[-1]) + 1]
+    # same popcount beyond the last representative (past the end of a rank
+    # bitmap): the next state in numeric order and the largest one
+    last = int(want[-1])
+    if 0 < m.n_up < m.n_sites:
+        low = last & -last
+        ripple = last + low
+        nxt = (((ripple ^ last) >> 2) // low) | ripple
+        if nxt < (1 << m.n_sites):
+            probes.append(nxt)
+        probes.append(((1 << m.n_up) - 1) << (m.n_sites - m.n_up))
     want_idx = np.array([oracle.index(want, s) for s in probes])
     assert np.array_equal(b.index(probes), want_idx)
 
 
+@pytest.mark.parametrize("index", INDEXES)
 @pytest.mark.parametrize("m", MODELS, ids=IDS)
-def test_apply_matches_oracle(X, m):
-    b = X.Basis.from_model(m)
+def test_apply_matches_oracle(X, m, index):
+    if m.perm is None and index == "hash":
+        pytest.skip("U(1) blocks have one index")
+    b = make_basis(X, m, index)
     H = X.Hamiltonian.from_model(b, m)
     basis = oracle_basis(m)
     D = len(basis)

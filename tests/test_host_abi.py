@@ -121,11 +121,11 @@ def test_planner_kinds(X):
     relab = np.array([perm[g[inv]] for g in c3.perm], dtype=np.int32)
     assert X.xdg_check_group(36, relab, None) == 0
     assert X.xdg_plan_search(36, relab)[0] == X.XDG_SEARCH_TABLE
-    # option flags: the defined bit passes, any other bit is refused
+    # option flags: the defined bits pass, any other bit is refused
     t16 = W.chain_translations(16)
-    acc = X.XDG_FLAG_F32_ACCUMULATE
+    acc = X.XDG_FLAG_F32_ACCUMULATE | X.XDG_FLAG_HASH_INDEX
     assert X.xdg_plan_search(16, t16, flags=acc) == (X.XDG_SEARCH_AFFINE, 0)
-    for bad in (1, 4, 64, acc | 16):
+    for bad in (1, 8, 64, acc | 16):
         with pytest.raises(X.XdgError):
             X.xdg_plan_search(16, t16, flags=bad)
 
