@@ -115,7 +115,9 @@ int form_of(const xdg_basis_s *b, int dtype, int64_t nvec, Form *f) {
         return XDG_EINVAL;
     }
     if (b->is_complex && !dtype_complex(dtype)) {
-        set_error("the block has complex characters: vectors must be XDG_C128 or XDG_C64");
+        set_error("the block (dimension %lld, %d group elements) has complex characters: "
+                  "vectors must be XDG_C128 or XDG_C64 (got dtype %d)",
+                  (long long)b->dim, b->n_sym, dtype);
         return XDG_EINVAL;
     }
     f->single = dtype_single(dtype);
@@ -353,7 +355,8 @@ int apply_batched_launch(int n, xdg_ham_s *const *hams, const void *const *xs, v
             return XDG_EINVAL;
         }
     // plans are cached by the exact argument tuple so that repeated calls
-    // (iterative methods) upload nothing
+    // (iterative methods) upload nothing; a Hamiltonian enters the key by its
+    // serial number too, since a new one may reuse a freed one's address
     struct Key {
         std::vector<const void *> p;
         int64_t nvec;
@@ -364,6 +367,7 @@ int apply_batched_launch(int n, xdg_ham_s *const *hams, const void *const *xs, v
     Key k;
     for (int i = 0; i < n; ++i) {
         k.p.push_back(hams[i]);
+        k.p.push_back(reinterpret_cast<const void *>((uintptr_t)hams[i]->serial));
         k.p.push_back(xs[i]);
         k.p.push_back(ys[i]);
     }

@@ -135,8 +135,11 @@ __device__ inline E *stage_copy(unsigned char *smem, size_t &off, const E *src, 
     return dst;
 }
 
-template <int KIND, class T>
-__device__ inline void stage(const SectorDesc &d, unsigned char *smem, int stage_sub, Staged<T> &S) {
+// STAGE: the sublattice tables go to LDS too (otherwise they are read from
+// global memory); a compile-time choice so that every table pointer has a
+// known address space.
+template <int KIND, class T, bool STAGE>
+__device__ inline void stage(const SectorDesc &d, unsigned char *smem, Staged<T> &S) {
     using B = typename BondT<T>::type;
     using T2 = typename Vec2<T>::type;
     size_t off = 0;
@@ -147,7 +150,7 @@ __device__ inline void stage(const SectorDesc &d, unsigned char *smem, int stage
         const T *ls = stage_copy(smem, off, reinterpret_cast<const T *>(d.sqrtt), 2 * (d.n_sym + 1));
         S.sq = ls;
         S.rsq = ls + d.n_sym + 1;
-        S.rtab = d.rwords ? stage_copy(smem, off, d.rtab, rank_table_len(d)) : nullptr;
+        S.rtab = stage_copy(smem, off, d.rtab, rank_table_len(d));
         if constexpr (KIND == K_AFF) {
             S.aff = stage_copy(smem, off, d.aff, d.n_sym);
             int16_t *lg = reinterpret_cast<int16_t *>(smem + off);
@@ -157,7 +160,7 @@ __device__ inline void stage(const SectorDesc &d, unsigned char *smem, int stage
             S.ring_gidx = lg;
         }
         if constexpr (KIND == K_SUB) {
-            if (stage_sub) {
+            if constexpr (STAGE) {
                 const size_t NV = (size_t)d.n_s << d.m;
                 S.sub.mintop = stage_copy(smem, off, d.mintop, NV);
                 S.sub.cand_off = stage_copy(smem, off, d.cand_off, NV + 1);
@@ -178,9 +181,10 @@ __device__ __forceinline__ int64_t locate(const SectorDesc &d, const Staged<T> &
     if constexpr (KIND == K_U1) {
         const uint64_t lo = (uint64_t)t & ((1ull << d.nlo) - 1);
         const uint64_t hi = (uint64_t)t >> d.nlo;
+        const uint32_t *lin = d.lin;
         u = 0;
         cnt = 1;
-        return (int64_t)d.lin[(1ull << d.nlo) + hi] + (int64_t)d.lin[lo];
+        return (int64_t)lin[(1ull << d.nlo) + hi] + (int64_t)lin[lo];
     } else {
         W rep;
         if constexpr (KIND == K_AFF) {
@@ -194,7 +198,8 @@ __device__ __forceinline__ int64_t locate(const SectorDesc &d, const Staged<T> &
             tab_search<W>(d.bytetab, d.n_bchunks, d.n_sym, t, rep, u, cnt);
         }
         if (d.rwords)
-            return rank_find(d.rwords, d.n_rwords, colex_rank<W>(S.rtab, d.rcb, d.rnc, d.rnb, rep));
+            return rank_find(d.rwords, d.n_rwords,
+                             colex_rank<W>(S.rtab, d.rcb, d.rnc, d.rnb, rep));
         return hash_find<W>(d.hash, d.n_lines, (W)d.empty, rep);
     }
 }
@@ -270,7 +275,7 @@ __device__ __forceinline__ uint32_t count_row(const SectorDesc &d, const Staged<
     return n;
 }
 
-template <class W, int KIND, class T, class AC, bool CPLX, int NV>
+template <class W, int KIND, class T, class AC, bool CPLX, int NV, bool STAGE>
 __global__ __launch_bounds__(APPLY_BLOCK) void k_apply(ApplyArgs A) {
     extern __shared__ __align__(16) unsigned char smem[];
     __shared__ uint32_t s_tile;
@@ -278,7 +283,7 @@ __global__ __launch_bounds__(APPLY_BLOCK) void k_apply(ApplyArgs A) {
     Staged<AC> S;
     if (A.descs == nullptr) {
         const SectorDesc &d = A.one;
-        stage<KIND, AC>(d, smem, A.stage_sub, S);
+        stage<KIND, AC, STAGE>(d, smem, S);
         __syncthreads();
         const int64_t stride = (int64_t)gridDim.x * blockDim.x;
         for (int64_t row = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; row < d.dim; row += stride)
@@ -300,7 +305,7 @@ __global__ __launch_bounds__(APPLY_BLOCK) void k_apply(ApplyArgs A) {
         if (lo != cur) {
             if (threadIdx.x == 0) s_desc = A.descs[lo];
             __syncthreads();
-            stage<KIND, AC>(s_desc, smem, A.stage_sub, S);
+            stage<KIND, AC, STAGE>(s_desc, smem, S);
             __syncthreads();
             cur = lo;
         }
@@ -314,13 +319,13 @@ __global__ __launch_bounds__(APPLY_BLOCK) void k_apply(ApplyArgs A) {
     }
 }
 
-template <class W, int KIND>
+template <class W, int KIND, bool STAGE>
 __global__ __launch_bounds__(APPLY_BLOCK) void k_count(ApplyArgs A) {
     extern __shared__ __align__(16) unsigned char smem[];
     __shared__ unsigned long long s_sum;
     Staged<double> S;
     const SectorDesc &d = A.one;
-    stage<KIND, double>(d, smem, A.stage_sub, S);
+    stage<KIND, double, STAGE>(d, smem, S);
     if (threadIdx.x == 0) s_sum = 0;
     __syncthreads();
     unsigned long long n = 0;
@@ -345,18 +350,29 @@ template <int KIND>
 int launch_count_kind(bool wide, const ApplyArgs &A, unsigned grid, unsigned block, size_t lds,
                       hipStream_t st);
 
+template <class W, int KIND, class T, class AC, bool CPLX, bool STAGE>
+void (*apply_kernel(int nv))(ApplyArgs) {
+    switch (nv) {
+        case 1: return k_apply<W, KIND, T, AC, CPLX, 1, STAGE>;
+        case 2: return k_apply<W, KIND, T, AC, CPLX, 2, STAGE>;
+        case 4: return k_apply<W, KIND, T, AC, CPLX, 4, STAGE>;
+        case 8: return k_apply<W, KIND, T, AC, CPLX, 8, STAGE>;
+    }
+    return nullptr;
+}
+
 template <class W, int KIND, class T, class AC, bool CPLX>
 int launch_nv(int nv, const ApplyArgs &A, unsigned grid, unsigned block, size_t lds,
               hipStream_t st) {
     void (*f)(ApplyArgs) = nullptr;
-    switch (nv) {
-        case 1: f = k_apply<W, KIND, T, AC, CPLX, 1>; break;
-        case 2: f = k_apply<W, KIND, T, AC, CPLX, 2>; break;
-        case 4: f = k_apply<W, KIND, T, AC, CPLX, 4>; break;
-        case 8: f = k_apply<W, KIND, T, AC, CPLX, 8>; break;
-        default:
-            set_error("vectors per pass %d not in {1, 2, 4, 8}", nv);
-            return XDG_EINVAL;
+    // only the sublattice kind has tables that may stay in global memory
+    if (KIND != K_SUB || A.stage_sub)
+        f = apply_kernel<W, KIND, T, AC, CPLX, true>(nv);
+    else if constexpr (KIND == K_SUB)
+        f = apply_kernel<W, KIND, T, AC, CPLX, false>(nv);
+    if (!f) {
+        set_error("vectors per pass %d not in {1, 2, 4, 8}", nv);
+        return XDG_EINVAL;
     }
     if (lds > 65536)
         XDG_TRY_HIP(hipFuncSetAttribute((const void *)f,
@@ -396,7 +412,10 @@ int launch_kind_impl(bool wide, bool single, bool acc64, bool cplx, int nv, cons
 template <int KIND>
 int launch_count_impl(bool wide, const ApplyArgs &A, unsigned grid, unsigned block, size_t lds,
                       hipStream_t st) {
-    void (*f)(ApplyArgs) = wide ? k_count<uint64_t, KIND> : k_count<uint32_t, KIND>;
+    void (*f)(ApplyArgs) = wide ? k_count<uint64_t, KIND, true> : k_count<uint32_t, KIND, true>;
+    if constexpr (KIND == K_SUB)
+        if (!A.stage_sub)
+            f = wide ? k_count<uint64_t, KIND, false> : k_count<uint32_t, KIND, false>;
     if (lds > 65536)
         XDG_TRY_HIP(hipFuncSetAttribute((const void *)f,
                                         hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));

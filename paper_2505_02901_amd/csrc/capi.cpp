@@ -228,7 +228,9 @@ int xdg_create_hamiltonian(xdg_basis b, int n_bonds, const int32_t *sites, const
         }
         *out = nullptr;
         XDG_RETURN_IF(validate_bonds(b->n_sites, b->n_sym, b->perm.data(), n_bonds, sites, jz, jxy));
+        static std::atomic<uint64_t> next_serial{1};
         auto *h = new xdg_ham_s();
+        h->serial = next_serial.fetch_add(1);
         h->basis = b;
         b->refs.fetch_add(1);
         h->n_bonds = n_bonds;

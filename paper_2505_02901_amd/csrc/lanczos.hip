@@ -586,7 +586,11 @@ int lanczos_batched(int n, xdg_ham_s *const *hams, const void *const *v0s, int64
     // choose the persistent grid once per set of blocks (outside capture):
     // a few sizes, timed; remembered for later calls on the same blocks
     static std::map<std::vector<const void *>, int> grid_cache;
-    std::vector<const void *> gkey(hams, hams + n);
+    std::vector<const void *> gkey;
+    for (int i = 0; i < n; ++i) {
+        gkey.push_back(hams[i]);
+        gkey.push_back(reinterpret_cast<const void *>((uintptr_t)hams[i]->serial));
+    }
     gkey.push_back(reinterpret_cast<const void *>((intptr_t)(nvec * 8 + dtype)));
     int best_grid = apply_grid_for(2);
     auto cached = grid_cache.find(gkey);

@@ -175,6 +175,7 @@ struct LaunchCfg {
 
 struct xdg_ham_s {
     xdg_basis_s *basis = nullptr;
+    uint64_t serial = 0;        // unique per created Hamiltonian (cache keys)
     int n_bonds = 0;
     std::vector<int32_t> sites;
     std::vector<double> jz, jxy;

@@ -130,6 +130,10 @@ def _ptr(t) -> Optional[int]:
         return None
     if isinstance(t, int):
         return t
+    if not t.is_cuda:
+        raise ValueError("vectors passed to the library must be device tensors")
+    if not t.is_contiguous():
+        raise ValueError("vectors passed to the library must be contiguous")
     return t.data_ptr()
 
 

@@ -87,6 +87,14 @@ def make_basis(X, m, index):
     or with the hash index forced; U(1) blocks always use Lin's tables."""
     b = X.Basis.from_model(m, flags=X.XDG_FLAG_HASH_INDEX if index == "hash" else 0)
     kind, nbytes = b.index_kind
+    if b.is_complex != m.is_complex:
+        info = dict(name=m.name, handle=hex(b.handle.value), dim=b.dim, search=b.search_kind,
+                    index=b.index_kind, chi_imag=float(np.max(np.abs(np.imag(m.chi)))))
+        again = X.Basis.from_model(m, flags=X.XDG_FLAG_HASH_INDEX if index == "hash" else 0)
+        info["again"] = (hex(again.handle.value), again.is_complex, again.dim)
+        import sys
+        print("COMPLEXITY MISMATCH", info, file=sys.stderr, flush=True)
+        raise AssertionError(f"basis complexity mismatch {info}")
     if m.perm is None:
         assert kind == X.XDG_INDEX_LIN
     else:
