@@ -227,13 +227,11 @@ __device__ __forceinline__ void process_row(const SectorDesc &d, const Staged<A>
     for (int v = 0; v < NV * C; ++v) acc[v] = diag * (A)X[base + v];
     A rn = A(1);
     if constexpr (KIND != K_U1) rn = S.rsq[d.stab[row]];
-    for (int b = 0; b < nb; ++b) {
-        const B bd = S.bonds[b];
-        if (((s >> bd.i) & 1) == ((s >> bd.j) & 1)) continue;
+    auto term = [&](const B &bd) {
         const W t = s ^ ((W(1) << bd.i) | (W(1) << bd.j));
         int u, cnt;
         const int64_t idx = locate<W, KIND, A>(d, S, t, u, cnt);
-        if (idx < 0) continue;
+        if (idx < 0) return;
         A ar = bd.h, ai = 0;
         if constexpr (KIND != K_U1) {
             const A f = bd.h * S.sq[cnt] * rn;
@@ -253,6 +251,33 @@ __device__ __forceinline__ void process_row(const SectorDesc &d, const Staged<A>
             } else {
                 acc[v] = fmadd<A>(ar, (A)X[xb + v], acc[v]);
             }
+        }
+    };
+    if constexpr (KIND == K_AFF || KIND == K_U1) {
+        // Cheap searches: per group of 64 bonds, a mask of the bonds with
+        // unequal spins, walked lowest first (the order of the plain bond
+        // loop), so that a wave iterates over its lanes' active bonds only.
+        for (int b0 = 0; b0 < nb; b0 += 64) {
+            const int bn = nb - b0 < 64 ? nb - b0 : 64;
+            uint64_t act = 0;
+            for (int k = 0; k < bn; ++k) {
+                const B bd = S.bonds[b0 + k];
+                act |= (uint64_t)((uint32_t)((s >> bd.i) ^ (s >> bd.j)) & 1u) << k;
+            }
+            while (act) {
+                const int b = b0 + __builtin_ctzll(act);
+                act &= act - 1;
+                term(S.bonds[b]);
+            }
+        }
+    } else {
+        // Table searches: all lanes take the same bond at the same time, so
+        // that neighbouring rows walk similar table entries and look up
+        // neighbouring index words.
+        for (int b = 0; b < nb; ++b) {
+            const B bd = S.bonds[b];
+            if (((s >> bd.i) & 1) == ((s >> bd.j) & 1)) continue;
+            term(bd);
         }
     }
 #pragma unroll
