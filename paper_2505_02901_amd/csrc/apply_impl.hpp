@@ -62,8 +62,8 @@ struct SectorDesc {
     const uint16_t *mintop;
     const uint32_t *cand_off;
     const uint16_t *cand_list;
-    const uint8_t *src;
-    const uint16_t *pid;
+    const uint8_t *srcoff;
+    const uint32_t *tpoff;
     const uint16_t *tperm;
     int n_s, m, pb, n_perm;
     uint32_t n_cand;
@@ -93,7 +93,7 @@ __host__ __device__ inline size_t a16(size_t x) { return (x + 15) & ~(size_t)15;
 __host__ __device__ inline size_t sub_table_bytes(const SectorDesc &d) {
     const size_t NV = (size_t)d.n_s << d.m;
     return a16(2 * NV) + a16(4 * (NV + 1)) + a16(2 * (size_t)d.n_cand) +
-           a16((size_t)d.n_sym * d.n_s) + a16(2 * (size_t)d.n_sym * d.n_s) +
+           a16((size_t)d.n_sym * d.n_s) + a16(4 * (size_t)d.n_sym * d.n_s) +
            a16(2 * (size_t)d.n_perm * 2 * ((size_t)1 << d.pb));
 }
 
@@ -144,7 +144,7 @@ __device__ inline void stage(const SectorDesc &d, unsigned char *smem, Staged<T>
     using T2 = typename Vec2<T>::type;
     size_t off = 0;
     S.bonds = stage_copy(smem, off, reinterpret_cast<const B *>(d.bonds), d.n_bonds);
-    S.sub = SubCtx{d.mintop, d.cand_off, d.cand_list, d.src, d.pid, d.tperm, d.n_s, d.m, d.pb};
+    S.sub = SubCtx{d.mintop, d.cand_off, d.cand_list, d.srcoff, d.tpoff, d.tperm, d.n_s, d.m, d.pb};
     if constexpr (KIND != K_U1) {
         S.chi = stage_copy(smem, off, reinterpret_cast<const T2 *>(d.chi), d.n_sym);
         const T *ls = stage_copy(smem, off, reinterpret_cast<const T *>(d.sqrtt), 2 * (d.n_sym + 1));
@@ -165,8 +165,8 @@ __device__ inline void stage(const SectorDesc &d, unsigned char *smem, Staged<T>
                 S.sub.mintop = stage_copy(smem, off, d.mintop, NV);
                 S.sub.cand_off = stage_copy(smem, off, d.cand_off, NV + 1);
                 S.sub.cand_list = stage_copy(smem, off, d.cand_list, d.n_cand);
-                S.sub.src = stage_copy(smem, off, d.src, (size_t)d.n_sym * d.n_s);
-                S.sub.pid = stage_copy(smem, off, d.pid, (size_t)d.n_sym * d.n_s);
+                S.sub.srcoff = stage_copy(smem, off, d.srcoff, (size_t)d.n_sym * d.n_s);
+                S.sub.tpoff = stage_copy(smem, off, d.tpoff, (size_t)d.n_sym * d.n_s);
                 S.sub.tperm = stage_copy(smem, off, d.tperm, (size_t)d.n_perm * 2 * ((size_t)1 << d.pb));
             }
         }
@@ -193,7 +193,10 @@ __device__ __forceinline__ int64_t locate(const SectorDesc &d, const Staged<T> &
             else
                 aff_search<W>(S.aff, d.n_sym, d.n_sites, t, rep, u, cnt);
         } else if constexpr (KIND == K_SUB) {
-            sub_search<W>(S.sub, t, rep, u, cnt);
+            if (d.n_s == 4)
+                sub_search<W, 4>(S.sub, t, rep, u, cnt);
+            else
+                sub_search<W, 0>(S.sub, t, rep, u, cnt);
         } else {
             tab_search<W>(d.bytetab, d.n_bchunks, d.n_sym, t, rep, u, cnt);
         }

@@ -253,8 +253,8 @@ struct SubCtx {
     const uint16_t *mintop;    // [n_s][V]
     const uint32_t *cand_off;  // [n_s*V + 1]
     const uint16_t *cand_list;
-    const uint8_t *src;        // [n_sym][n_s]
-    const uint16_t *pid;       // [n_sym][n_s]
+    const uint8_t *srcoff;     // [n_sym][n_s] first bit of the block of t feeding block a
+    const uint32_t *tpoff;     // [n_sym][n_s] offset in tperm of that block's tables
     const uint16_t *tperm;     // [n_perm][2][E]
     int n_s, m, pb;            // E = 1 << pb
 };
@@ -264,18 +264,25 @@ __device__ __forceinline__ uint32_t chunk_of(W t, int k, int m, uint32_t vmask) 
     return (uint32_t)(t >> (k * m)) & vmask;
 }
 
-// image chunk of source chunk v for block a of element g (two half lookups)
-__device__ __forceinline__ uint32_t sub_img(const SubCtx &C, int g, int a, uint32_t v) {
-    const int E = 1 << C.pb;
-    const uint16_t *tp = C.tperm + (size_t)C.pid[g * C.n_s + a] * 2 * E;
-    return (uint32_t)tp[v & (E - 1)] | tp[E + (v >> C.pb)];
+// image bits of block a of g.t (two half-chunk lookups)
+template <class W>
+__device__ __forceinline__ uint32_t sub_block(const SubCtx &C, const uint8_t *so,
+                                              const uint32_t *to, int a, W t, uint32_t vmask) {
+    const uint32_t v = (uint32_t)(t >> so[a]) & vmask;
+    const uint16_t *tp = C.tperm + to[a];
+    const uint32_t lo = (1u << C.pb) - 1;
+    return (uint32_t)tp[v & lo] | tp[lo + 1 + (v >> C.pb)];
 }
 
-template <class W>
+// NS > 0: the number of blocks is a compile-time constant (loops unrolled);
+// NS = 0: taken from C.n_s.
+template <class W, int NS>
 __device__ __forceinline__ void sub_search(const SubCtx &C, W t, W &best, int &u, int &cnt) {
-    const int m = C.m, ns = C.n_s, top = ns - 1;
+    const int m = C.m;
+    const int ns = NS > 0 ? NS : C.n_s, top = ns - 1;
     const uint32_t V = 1u << m, vmask = V - 1;
     uint32_t mt = 0xFFFFu;
+#pragma unroll
     for (int k = 0; k < ns; ++k) {
         const uint32_t v = C.mintop[k * V + chunk_of<W>(t, k, m, vmask)];
         mt = v < mt ? v : mt;
@@ -283,27 +290,30 @@ __device__ __forceinline__ void sub_search(const SubCtx &C, W t, W &best, int &u
     best = ~W(0);
     u = 0x7fffffff;
     cnt = 0;
+#pragma unroll
     for (int k = 0; k < ns; ++k) {
         const uint32_t e = k * V + chunk_of<W>(t, k, m, vmask);
         if (C.mintop[e] != mt) continue;
         const uint32_t q1 = C.cand_off[e + 1];
         for (uint32_t q = C.cand_off[e]; q < q1; ++q) {
             const int g = C.cand_list[q];
-            const uint8_t *sg = C.src + (size_t)g * ns;
+            const uint8_t *so = C.srcoff + g * ns;
+            const uint32_t *to = C.tpoff + g * ns;
+            // blocks from the top down; while the image agrees with the best
+            // one so far, each block is compared with the best one's block
             W img = (W)mt << (top * m);
-            bool lose = false;
-            int a = top - 1;
-            for (; a >= 0; --a) {
-                img |= (W)sub_img(C, g, a, chunk_of<W>(t, sg[a], m, vmask)) << (a * m);
-                const W hi = img >> (a * m), hb = best >> (a * m);
-                if (hi > hb) {
-                    lose = true;
-                    break;
-                }
-                if (hi < hb) {
-                    for (--a; a >= 0; --a)
-                        img |= (W)sub_img(C, g, a, chunk_of<W>(t, sg[a], m, vmask)) << (a * m);
-                    break;
+            bool eq = true, lose = false;
+#pragma unroll
+            for (int a = top - 1; a >= 0; --a) {
+                const uint32_t v = sub_block<W>(C, so, to, a, t, vmask);
+                img |= (W)v << (a * m);
+                if (eq) {
+                    const uint32_t bb = (uint32_t)(best >> (a * m)) & vmask;
+                    if (v > bb) {
+                        lose = true;
+                        break;
+                    }
+                    eq = v == bb;
                 }
             }
             if (lose) continue;
@@ -336,14 +346,14 @@ __device__ __forceinline__ bool sub_is_rep(const SubCtx &C, W s, const double2 *
         const uint32_t q1 = C.cand_off[e + 1];
         for (uint32_t q = C.cand_off[e]; q < q1; ++q) {
             const int g = C.cand_list[q];
-            const uint8_t *sg = C.src + (size_t)g * ns;
-            W img = (W)ct << (top * m);
+            const uint8_t *so = C.srcoff + g * ns;
+            const uint32_t *to = C.tpoff + g * ns;
             int cmp = 0;   // -1: image < s, +1: image > s
             for (int a = top - 1; a >= 0; --a) {
-                img |= (W)sub_img(C, g, a, chunk_of<W>(s, sg[a], m, vmask)) << (a * m);
-                const W hi = img >> (a * m), hs = s >> (a * m);
-                if (hi != hs) {
-                    cmp = hi < hs ? -1 : 1;
+                const uint32_t v = sub_block<W>(C, so, to, a, s, vmask);
+                const uint32_t sv = chunk_of<W>(s, a, m, vmask);
+                if (v != sv) {
+                    cmp = v < sv ? -1 : 1;
                     break;
                 }
             }

@@ -150,6 +150,8 @@ struct xdg_basis_s {
     xdg::DevBuf rtab;
     int rank_cb = 0, rank_nc = 0;
     int lin_nlo = 0, lin_nhi = 0;
+    // sublattice tables on the device: t_src = u8 first bit of the source block
+    // [n_sym][n_s], t_pid = u32 offset of its permutation tables in t_tperm
     xdg::DevBuf t_src, t_pid, t_tperm, t_mintop, t_candoff, t_candlist, t_bytes, t_aff, t_ring;
     xdg::DevBuf chi_d;          // double2 [n_sym]
     xdg::DevBuf chi_f;          // float2 [n_sym]
