@@ -243,6 +243,35 @@ int xdg_lanczos_eigval_batched(int n, const xdg_ham *hams, const void *const *v0
                                int n_iter, uint64_t seed, int prec, double *evals, double *alpha,
                                double *beta, void *stream);
 
+/* Second Lanczos pass: the Ritz vector of T (eig0 / eigs_lanczos, Sec. 3.7.1,
+ * which run the iteration twice to build eigenvectors without storing the
+ * Krylov basis).  The recurrence of xdg_lanczos_eigval is replayed from the
+ * same start vector with the tridiagonal matrix it returned, and
+ * psi = sum_j c_j v_j is accumulated in FP64, c the normalised eigenvector
+ * (c_0 >= 0) of the Ritz value number `which` (0 = lowest) of the leading
+ * n_iter x n_iter block of T.  The vectors v_j equal those of the first pass
+ * bit for bit (same kernels, same scalars).
+ *   v0, seed, prec: as passed to xdg_lanczos_eigval (prec XDG_PREC_F64 or
+ *       XDG_PREC_F32VEC; the forms with reorthogonalisation are refused);
+ *   alpha, beta: host double[n_iter] from xdg_lanczos_eigval;
+ *   psi: device [dim] of the precision form's vector dtype, normalised
+ *       (FP64 accumulation, one rounding); may not alias v0.
+ *   ritz (may be NULL): host double, the Ritz value used. */
+int xdg_lanczos_eigvec(xdg_ham h, const void *v0, uint64_t seed, int prec, int n_iter,
+                       const double *alpha, const double *beta, int which, void *psi,
+                       double *ritz, void *stream);
+
+/* <psi| O |psi> (measurements, Sec. 3.8) for the symmetrised Ising
+ * correlations O = (1/|G|) sum_g S^z_{g(a)} S^z_{g(b)} (symmetrisation of an
+ * operator over the group, Sec. 3.13).  It is diagonal in the symmetric basis with
+ * value (1/|G|) sum_g sz_s(g(a)) sz_s(g(b)) on state s (sz = +-1/2), and for a
+ * state of the block it equals the expectation of the plain S^z_a S^z_b.
+ * On a U(1) block O = S^z_a S^z_b.  psi is not normalised by the call.
+ *   psi: device [dim] of dtype; pairs: host int32[2 n_pairs] (a, b) in [0, N);
+ *   out: host double[n_pairs].  Fixed-order reductions (reproducible). */
+int xdg_expect_szsz(xdg_basis b, const void *psi, int dtype, int n_pairs, const int32_t *pairs,
+                    double *out, void *stream);
+
 /* Timing of the last xdg_lanczos_eigval[_batched] call on this thread:
  * total seconds in the iteration loop and seconds spent in the apply
  * kernels (HIP events); either may be NULL. */

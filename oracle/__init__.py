@@ -221,3 +221,52 @@ def lanczos(m, basis_list: np.ndarray, x0: np.ndarray, k: int = 1, tol: float = 
         raise RuntimeError(f"orc_lanczos failed ({st})")
     n = int(nit[0])
     return st, ev, al[:n].copy(), be[:n].copy()
+
+
+# ---------------------------------------------------------------------------
+# Eigenvectors and measurements (small cases only; plain definitions)
+# ---------------------------------------------------------------------------
+
+def full_states(n_sites: int, n_up: int) -> np.ndarray:
+    """All product states with n_up up spins, ascending (the U(1) basis)."""
+    lib = _load()
+    d = lib.orc_basis(n_sites, n_up, 0, None, None, None, 0)
+    out = np.empty(max(d, 1), dtype=np.uint64)
+    lib.orc_basis(n_sites, n_up, 0, None, None, _p(out), d)
+    return out[:d]
+
+
+def expand_state(m, basis_list: np.ndarray, psi: np.ndarray) -> Tuple[np.ndarray, np.ndarray]:
+    """(product states, amplitudes) of sum_s psi_s |s~>, where the symmetric
+    state of representative s is |s~> = N_s^-1 sum_g chi(g)* g|s> with
+    N_s = sqrt(|G| |Stab s|) (Sec. 3.11).  Pure-Python loops: small cases."""
+    full = full_states(m.n_sites, m.n_up)
+    amp = np.zeros(len(full), np.complex128)
+    if m.perm is None:
+        return full, np.asarray(psi, np.complex128).copy()
+    G = m.n_sym
+    for s, c in zip(basis_list, psi):
+        s = int(s)
+        images = [act(m.n_sites, g, s) for g in m.perm]
+        stab = sum(1 for t in images if t == s)
+        ns = np.sqrt(G * stab)
+        for t, ch in zip(images, m.chi):
+            amp[int(np.searchsorted(full, t))] += c * np.conj(ch) / ns
+    return full, amp
+
+
+def szsz_definition(full: np.ndarray, amp: np.ndarray, a: int, b: int) -> float:
+    """<Psi| S^z_a S^z_b |Psi> on a product-state expansion (sz = +-1/2)."""
+    ba = (full >> np.uint64(a)) & np.uint64(1)
+    bb = (full >> np.uint64(b)) & np.uint64(1)
+    v = np.where(ba == bb, 0.25, -0.25)
+    return float(np.sum(np.abs(amp) ** 2 * v))
+
+
+def dense_ground_state(m, basis_list: np.ndarray) -> Tuple[float, np.ndarray]:
+    """Lowest eigenpair of the block matrix built column by column from the
+    oracle's H x (small cases; LAPACK eigh)."""
+    D = len(basis_list)
+    H = apply(m, basis_list, np.eye(D, dtype=np.complex128))
+    w, v = np.linalg.eigh(H)
+    return float(w[0]), v[:, 0]

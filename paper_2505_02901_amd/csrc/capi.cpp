@@ -334,6 +334,30 @@ int xdg_lanczos_eigval_batched(int n, const xdg_ham *hams, const void *const *v0
     });
 }
 
+int xdg_lanczos_eigvec(xdg_ham h, const void *v0, uint64_t seed, int prec, int n_iter,
+                       const double *alpha, const double *beta, int which, void *psi,
+                       double *ritz, void *stream) {
+    return guarded([&]() -> int {
+        if (!h) {
+            set_error("null hamiltonian");
+            return XDG_EINVAL;
+        }
+        return lanczos_eigvec(h, v0, seed, prec, n_iter, alpha, beta, which, psi, ritz,
+                              (hipStream_t)stream);
+    });
+}
+
+int xdg_expect_szsz(xdg_basis b, const void *psi, int dtype, int n_pairs, const int32_t *pairs,
+                    double *out, void *stream) {
+    return guarded([&]() -> int {
+        if (!b) {
+            set_error("null basis");
+            return XDG_EINVAL;
+        }
+        return expect_szsz(b, psi, dtype, n_pairs, pairs, out, (hipStream_t)stream);
+    });
+}
+
 int xdg_last_lanczos_timing(double *total_s, double *apply_s) {
     return last_timing(total_s, apply_s);
 }

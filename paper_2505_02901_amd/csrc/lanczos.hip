@@ -240,6 +240,24 @@ struct VecOps {
     }
 };
 
+// acc += c v (FP64 accumulation of the Ritz vector)
+template <class T>
+__global__ __launch_bounds__(RB) void k_acc_axpy(double *acc, const T *v, uint64_t n, double c) {
+    const uint64_t stride = (uint64_t)gridDim.x * RB;
+    for (uint64_t q = (uint64_t)blockIdx.x * RB + threadIdx.x; q < n; q += stride)
+        acc[q] = __builtin_fma(c, (double)v[q], acc[q]);
+}
+
+// out = acc / nrm[0], one rounding to T
+template <class T>
+__global__ __launch_bounds__(RB) void k_acc_out(const double *acc, T *out, uint64_t n,
+                                                const double *nrm) {
+    const double s = nrm[0] > 0.0 ? 1.0 / nrm[0] : 0.0;
+    const uint64_t stride = (uint64_t)gridDim.x * RB;
+    for (uint64_t q = (uint64_t)blockIdx.x * RB + threadIdx.x; q < n; q += stride)
+        out[q] = (T)(acc[q] * s);
+}
+
 thread_local double g_t_total = 0.0, g_t_apply = 0.0;
 
 // XDG_LANCZOS_PROGRESS=n: print a line to stderr every n iterations (0 = off)
@@ -501,6 +519,175 @@ int lanczos_single(xdg_ham_s *h, const void *v0, int k, double tol, int max_iter
 // n blocks x nvec recurrences in lockstep; each step (batched apply, then
 // per-block dot / update / norm / scale) is captured once per buffer
 // rotation phase into a HIP graph and replayed.
+// Eigenvector of the symmetric tridiagonal matrix for its eigenvalue number
+// `which` (ascending), by inverse iteration: (T - theta) x = x_prev solved by
+// Gaussian elimination with partial pivoting on the tridiagonal band, three
+// sweeps.  Normalised, first nonzero component made positive.
+void tridiag_eigvec(int m, const double *alpha, const double *beta, int which,
+                    std::vector<double> &x, double &theta) {
+    std::vector<double> ev;
+    tridiag_eigenvalues(m, alpha, beta, ev);
+    theta = ev[which];
+    double tnorm = 0.0;
+    for (int i = 0; i < m; ++i)
+        tnorm = std::max(tnorm, std::fabs(alpha[i]) + (i ? std::fabs(beta[i - 1]) : 0.0) +
+                                    (i + 1 < m ? std::fabs(beta[i]) : 0.0));
+    const double tiny = std::max(tnorm, 1e-300) * 1e-15;
+    // factor P (T - theta) = L U; U has diagonals d, u1, u2; L multipliers f
+    std::vector<double> d(m), u1(m, 0.0), u2(m, 0.0), f(m, 0.0);
+    std::vector<char> swp(m, 0);
+    for (int i = 0; i < m; ++i) {
+        d[i] = alpha[i] - theta;
+        if (i + 1 < m) u1[i] = beta[i];
+    }
+    for (int i = 0; i + 1 < m; ++i) {
+        const double sub = beta[i];   // row i+1, column i
+        if (std::fabs(d[i]) >= std::fabs(sub)) {
+            if (d[i] == 0.0) d[i] = tiny;
+            f[i] = sub / d[i];
+            d[i + 1] -= f[i] * u1[i];
+        } else {
+            // rows i and i+1 exchanged
+            swp[i] = 1;
+            f[i] = d[i] / sub;
+            d[i] = sub;
+            const double r1 = u1[i];       // old row i, column i+1
+            u1[i] = d[i + 1];              // old row i+1, column i+1
+            d[i + 1] = r1 - f[i] * u1[i];
+            if (i + 2 < m) {
+                u2[i] = u1[i + 1];         // old row i+1, column i+2
+                u1[i + 1] = -f[i] * u2[i];
+            }
+        }
+    }
+    if (d[m - 1] == 0.0) d[m - 1] = tiny;
+    x.assign(m, 1.0);
+    for (int sweep = 0; sweep < 3; ++sweep) {
+        // forward: apply P and L^-1
+        for (int i = 0; i + 1 < m; ++i) {
+            if (swp[i]) std::swap(x[i], x[i + 1]);
+            x[i + 1] -= f[i] * x[i];
+        }
+        // back substitution with U
+        for (int i = m - 1; i >= 0; --i) {
+            double r = x[i];
+            if (i + 1 < m) r -= u1[i] * x[i + 1];
+            if (i + 2 < m) r -= u2[i] * x[i + 2];
+            x[i] = r / (d[i] != 0.0 ? d[i] : tiny);
+        }
+        double nrm = 0.0;
+        for (double v : x) nrm += v * v;
+        nrm = std::sqrt(nrm);
+        for (double &v : x) v /= nrm;
+    }
+    for (int i = 0; i < m; ++i)
+        if (x[i] != 0.0) {
+            if (x[i] < 0.0)
+                for (double &v : x) v = -v;
+            break;
+        }
+}
+
+int lanczos_eigvec(xdg_ham_s *h, const void *v0, uint64_t seed, int prec, int m,
+                   const double *alpha, const double *beta, int which, void *psi, double *ritz,
+                   hipStream_t st) {
+    const xdg_basis_s *b = h->basis;
+    if (prec != XDG_PREC_F64 && prec != XDG_PREC_F32VEC) {
+        set_error("second Lanczos pass: precision form %d not supported (no reorthogonalisation)",
+                  prec);
+        return XDG_EINVAL;
+    }
+    if (m < 1 || which < 0 || which >= m || !alpha || !beta || !psi || psi == v0) {
+        set_error("second Lanczos pass: need n_iter >= 1, 0 <= which < n_iter, alpha, beta and a "
+                  "psi distinct from v0");
+        return XDG_EINVAL;
+    }
+    const int64_t D = b->dim;
+    if (D < 1) {
+        set_error("lanczos on an empty block");
+        return XDG_EINVAL;
+    }
+    for (int j = 0; j + 1 < m; ++j)
+        if (!(beta[j] > 0.0)) {
+            set_error("second Lanczos pass: beta[%d] = %g ends the recurrence before n_iter", j,
+                      beta[j]);
+            return XDG_EINVAL;
+        }
+    std::vector<double> c;
+    double theta = 0.0;
+    tridiag_eigvec(m, alpha, beta, which, c, theta);
+    if (ritz) *ritz = theta;
+
+    const bool single = prec == XDG_PREC_F32VEC;
+    const int C = b->is_complex ? 2 : 1;
+    const int dtype = C == 2 ? (single ? XDG_C64 : XDG_C128) : (single ? XDG_F32 : XDG_F64);
+    const size_t esz = (single ? 4 : 8) * C;
+    const uint64_t nsc = (uint64_t)D * C;
+    const size_t vbytes = (size_t)D * esz;
+    DevBuf bufs, wbuf, acc, scal, parts;
+    XDG_RETURN_IF(bufs.alloc(vbytes * 3));
+    XDG_RETURN_IF(wbuf.alloc(vbytes));
+    XDG_RETURN_IF(acc.alloc(sizeof(double) * nsc));
+    // scalars: nrm, alpha[m], beta[m], zero
+    XDG_RETURN_IF(scal.alloc(sizeof(double) * (2 + 2 * (size_t)m) + 16));
+    double *nrm = scal.as<double>(), *zero = nrm + 1, *al_d = nrm + 2, *be_d = al_d + m;
+    int *jdev = reinterpret_cast<int *>(be_d + m);
+    XDG_TRY_HIP(hipMemsetAsync(scal.p, 0, scal.bytes, st));
+    XDG_TRY_HIP(hipMemcpyAsync(al_d, alpha, sizeof(double) * m, hipMemcpyHostToDevice, st));
+    XDG_TRY_HIP(hipMemcpyAsync(be_d, beta, sizeof(double) * m, hipMemcpyHostToDevice, st));
+    XDG_TRY_HIP(hipMemsetAsync(acc.p, 0, acc.bytes, st));
+    VecOps ops{single, C, C, nsc, vec_grid(nsc), nullptr, st};
+    XDG_RETURN_IF(parts.alloc(sizeof(double) * (size_t)ops.grid * MAXC));
+    ops.partials = parts.as<double>();
+    auto vec = [&](int i) -> char * { return bufs.as<char>() + vbytes * i; };
+    char *w = wbuf.as<char>();
+    // start vector exactly as in the first pass
+    if (v0)
+        XDG_TRY_HIP(hipMemcpyAsync(vec(0), v0, vbytes, hipMemcpyDeviceToDevice, st));
+    else
+        XDG_RETURN_IF(random_fill((int64_t)nsc, seed, 1, single, vec(0), st));
+    XDG_RETURN_IF(ops.dot(vec(0), vec(0)));
+    XDG_RETURN_IF(ops.finalize(1, nrm, nullptr, jdev));
+    XDG_RETURN_IF(ops.scale(vec(0), vec(0), nrm));
+    const int g = vec_grid(nsc);
+    int iv = 0, ip = -1, in = 1;
+    for (int j = 0; j < m; ++j) {
+        char *v = vec(iv);
+        if (single)
+            hipLaunchKernelGGL(k_acc_axpy<float>, dim3(g), dim3(RB), 0, st, acc.as<double>(),
+                               (const float *)v, nsc, c[j]);
+        else
+            hipLaunchKernelGGL(k_acc_axpy<double>, dim3(g), dim3(RB), 0, st, acc.as<double>(),
+                               (const double *)v, nsc, c[j]);
+        XDG_TRY_HIP(hipGetLastError());
+        if (j + 1 == m) break;
+        XDG_RETURN_IF(apply_tuned(h, v, w, 1, dtype, st));
+        XDG_RETURN_IF(ops.update(w, v, ip >= 0 ? vec(ip) : nullptr, al_d + j, j ? be_d + j - 1 : zero));
+        XDG_RETURN_IF(ops.scale(w, vec(in), be_d + j));
+        ip = iv;
+        iv = in;
+        in = (in + 1) % 3;
+        if (in == ip) in = (in + 1) % 3;
+        if (progress_every() && (j + 1) % progress_every() == 0) {
+            XDG_TRY_HIP(hipStreamSynchronize(st));
+            fprintf(stderr, "[xdg] second lanczos pass %d / %d\n", j + 1, m);
+        }
+    }
+    // psi = acc / |acc|
+    VecOps dops{false, 1, 1, nsc, vec_grid(nsc), parts.as<double>(), st};
+    XDG_RETURN_IF(dops.dot(acc.p, acc.p));
+    XDG_RETURN_IF(dops.finalize(1, nrm, nullptr, jdev));
+    if (single)
+        hipLaunchKernelGGL(k_acc_out<float>, dim3(g), dim3(RB), 0, st, acc.as<double>(),
+                           (float *)psi, nsc, nrm);
+    else
+        hipLaunchKernelGGL(k_acc_out<double>, dim3(g), dim3(RB), 0, st, acc.as<double>(),
+                           (double *)psi, nsc, nrm);
+    XDG_TRY_HIP(hipGetLastError());
+    XDG_TRY_HIP(hipStreamSynchronize(st));
+    return XDG_OK;
+}
+
 int lanczos_batched(int n, xdg_ham_s *const *hams, const void *const *v0s, int64_t nvec,
                     int n_iter, uint64_t seed, int prec, double *evals, double *alpha,
                     double *beta, hipStream_t user_st, double *t_total, double *t_apply) {

@@ -231,6 +231,13 @@ int lanczos_batched(int n, xdg_ham_s *const *hams, const void *const *v0s, int64
                     int n_iter, uint64_t seed, int prec, double *evals, double *alpha,
                     double *beta, hipStream_t st, double *t_total, double *t_apply);
 void tridiag_eigenvalues(int m, const double *alpha, const double *beta, std::vector<double> &out);
+void tridiag_eigvec(int m, const double *alpha, const double *beta, int which,
+                    std::vector<double> &x, double &theta);
+int lanczos_eigvec(xdg_ham_s *h, const void *v0, uint64_t seed, int prec, int m,
+                   const double *alpha, const double *beta, int which, void *psi, double *ritz,
+                   hipStream_t st);
+int expect_szsz(xdg_basis_s *b, const void *psi, int dtype, int n_pairs, const int32_t *pairs,
+                double *out, hipStream_t st);
 
 int random_fill(int64_t n_scalars, uint64_t seed, int kind, bool single, void *out,
                 hipStream_t st);

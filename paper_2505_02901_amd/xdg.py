@@ -79,6 +79,8 @@ def lib():
             "xdg_lanczos_eigval": (I, [P, P, I, D, I, U64, I, P, P, P, P, P]),
             "xdg_lanczos_eigval_batched": (I, [I, P, P, I64, I, U64, I, P, P, P, P]),
             "xdg_last_lanczos_timing": (I, [P, P]),
+            "xdg_lanczos_eigvec": (I, [P, P, U64, I, I, P, P, I, P, P, P]),
+            "xdg_expect_szsz": (I, [P, P, I, I, P, P, P]),
         }
         for name, (res, args) in sig.items():
             f = getattr(L, name)
@@ -96,7 +98,7 @@ def exported_names():
             "xdg_basis_copy_stabilisers", "xdg_basis_index", "xdg_create_hamiltonian",
             "xdg_destroy_hamiltonian", "xdg_ham_nnz", "xdg_apply", "xdg_apply_batched",
             "xdg_random_state", "xdg_lanczos_eigval", "xdg_lanczos_eigval_batched",
-            "xdg_last_lanczos_timing"]
+            "xdg_last_lanczos_timing", "xdg_lanczos_eigvec", "xdg_expect_szsz"]
 
 
 def _check(rc: int, allow=(XDG_OK,)):
@@ -338,6 +340,31 @@ def xdg_lanczos_eigval_batched(hams: Sequence, nvec: int, n_iter: int, seed: int
     return ev.reshape(n, nvec), al.reshape(n, nvec, n_iter), be.reshape(n, nvec, n_iter)
 
 
+def xdg_lanczos_eigvec(h, alpha, beta, psi, seed: int = 0, prec: int = XDG_PREC_F64, v0=None,
+                       which: int = 0, stream=None) -> float:
+    """Second Lanczos pass into the device tensor psi; returns the Ritz value."""
+    al = np.ascontiguousarray(alpha, dtype=np.float64)
+    be = np.ascontiguousarray(beta, dtype=np.float64)
+    if len(be) < len(al):
+        raise ValueError("beta needs as many entries as alpha")
+    r = C.c_double()
+    _check(lib().xdg_lanczos_eigvec(h, _ptr(v0), seed, prec, len(al),
+                                    al.ctypes.data_as(C.c_void_p), be.ctypes.data_as(C.c_void_p),
+                                    which, _ptr(psi), C.byref(r), _stream(stream)))
+    return r.value
+
+
+def xdg_expect_szsz(b, psi, pairs, dtype: Optional[int] = None, stream=None) -> np.ndarray:
+    """<psi| (1/|G|) sum_g S^z_g(a) S^z_g(b) |psi> for each (a, b) in pairs."""
+    p = np.ascontiguousarray(np.asarray(pairs, dtype=np.int32).reshape(-1, 2))
+    out = np.zeros(len(p), np.float64)
+    if dtype is None:
+        dtype = _dtype_code(psi)
+    _check(lib().xdg_expect_szsz(b, _ptr(psi), dtype, len(p), p.ctypes.data_as(C.c_void_p),
+                                 out.ctypes.data_as(C.c_void_p), _stream(stream)))
+    return out
+
+
 def xdg_last_lanczos_timing() -> Tuple[float, float]:
     t, a = C.c_double(), C.c_double()
     _check(lib().xdg_last_lanczos_timing(C.byref(t), C.byref(a)))
@@ -417,6 +444,21 @@ class Hamiltonian:
 
     def lanczos(self, **kw):
         return xdg_lanczos_eigval(self.handle, **kw)
+
+    def eig0(self, tol: float = 1e-12, max_iter: int = 300, seed: int = 0,
+             prec: int = XDG_PREC_F64, v0=None, stream=None):
+        """Lowest eigenvalue and normalised eigenvector (two Lanczos passes)."""
+        import torch
+        st, ev, al, be = xdg_lanczos_eigval(self.handle, k=1, tol=tol, max_iter=max_iter,
+                                           seed=seed, prec=prec, v0=v0, stream=stream)
+        single = prec in (XDG_PREC_F32VEC, XDG_PREC_F32VEC_REORTH)
+        cplx = self.basis.is_complex
+        dt = {(False, False): torch.float64, (True, False): torch.float32,
+              (False, True): torch.complex128, (True, True): torch.complex64}[(single, cplx)]
+        psi = torch.empty(self.basis.dim, dtype=dt, device="cuda")
+        e = xdg_lanczos_eigvec(self.handle, al, be, psi, seed=seed, prec=prec, v0=v0,
+                               stream=stream)
+        return e, psi, al, be
 
     def close(self):
         if getattr(self, "handle", None) is not None and self.handle.value:

@@ -202,3 +202,19 @@ def test_c5_fullsize(X):
     check_windows(m, b, 50, n_windows=2, width=400)
     check_membership(X, m, b, 51, n_members=600, n_random=600)
     check_columns(X, m, b, H, 52, 2, [(torch.float64, 1e-12)])
+
+
+def test_c2_ground_state_correlations(X):
+    """Second Lanczos pass at full size (k = 0 sector, FP64): the sum rule
+    sum_j <S^z_0 S^z_j> = 0 at Sz = 0 and, for the singlet ground state,
+    <S^z_0 S^z_1> = E0 / (3N) with E0 from the Bethe ansatz."""
+    from test_oracle_pins import bethe_energy
+    m, b, H = built(X, "chain32_k0_kpi", 0)
+    e, psi, al, be = H.eig0(tol=0.0, max_iter=200, seed=2, prec=0)
+    e_bethe = bethe_energy(32, 16)
+    assert abs(e - e_bethe) < 1e-12 * abs(e_bethe)
+    c = X.xdg_expect_szsz(b.handle, psi, [(0, j) for j in range(32)])
+    assert abs(c[0] - 0.25) < 1e-12
+    assert abs(c.sum()) < 1e-11
+    assert abs(c[1] - e_bethe / 96.0) < 1e-6, (c[1], e_bethe / 96.0)
+    assert np.max(np.abs(c[1:] - c[1:][::-1])) < 1e-6

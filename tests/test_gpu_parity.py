@@ -92,6 +92,14 @@ def make_basis(X, m, index):
                     index=b.index_kind, chi_imag=float(np.max(np.abs(np.imag(m.chi)))))
         again = X.Basis.from_model(m, flags=X.XDG_FLAG_HASH_INDEX if index == "hash" else 0)
         info["again"] = (hex(again.handle.value), again.is_complex, again.dim)
+        from paper_2505_02901_amd import xdg as XX
+        carr, _ = XX._chi_arr(m.chi, m.n_sym)
+        info["chi_arr_imag"] = float(np.max(np.abs(carr[:, 1])))
+        info["chi_arr_shape"] = carr.shape
+        real_b = X.Basis(m.n_sites, m.n_up, m.perm, np.real(m.chi).copy())
+        info["real_chi_basis"] = real_b.is_complex
+        none_b = X.Basis(m.n_sites, m.n_up, m.perm, None)
+        info["none_chi_basis"] = none_b.is_complex
         import sys
         print("COMPLEXITY MISMATCH", info, file=sys.stderr, flush=True)
         raise AssertionError(f"basis complexity mismatch {info}")
@@ -360,3 +368,72 @@ def test_batched_lanczos_matches_single(X):
         basis = oracle_basis(m)
         e0 = np.linalg.eigvalsh(oracle.apply(m, basis, np.eye(len(basis), dtype=complex)))[0]
         assert np.max(np.abs(ev[i] - e0)) < 1e-6 * max(1, abs(e0)), (i, ev[i], e0)
+
+
+# ------------------------------------------ second Lanczos pass, measurements
+EIG_CASES = [W.chain_model(12), W.chain_model(12, l=0), W.chain_model(12, l=5),
+             W.chain_model(16, l=0), W.torus_model((4, 0), (0, 4), 1.0, 0.5, "B1"),
+             W.torus_model((4, 2), (-2, 4), 1.0, 0.0, "A1", reflections=False)]
+EIG_IDS = [f"{m.name}-n{m.n_up}" for m in EIG_CASES]
+
+
+@pytest.mark.parametrize("m", EIG_CASES, ids=EIG_IDS)
+def test_eig0_second_pass_matches_dense(X, m):
+    basis = oracle_basis(m)
+    e_or, v_or = oracle.dense_ground_state(m, basis)
+    b = X.Basis.from_model(m)
+    H = X.Hamiltonian.from_model(b, m)
+    D = b.dim
+    for prec, tol_e, tol_v in ((0, 1e-11, 1e-9), (1, 1e-6, 1e-5)):
+        e, psi, al, be = H.eig0(tol=1e-14 if prec == 0 else 1e-9, max_iter=min(D, 250), seed=5,
+                                prec=prec)
+        # the Ritz value of the second pass is the first pass's lowest one
+        assert e == X.xdg_lanczos_eigval(H.handle, k=1, tol=0.0, max_iter=len(al), seed=5,
+                                         prec=prec)[1][0]
+        assert abs(e - e_or) < tol_e * abs(e_or), (prec, e, e_or)
+        p = psi.cpu().numpy().astype(np.complex128)
+        assert abs(np.linalg.norm(p) - 1) < tol_v
+        assert 1 - abs(np.vdot(v_or, p)) < tol_v, (prec, abs(np.vdot(v_or, p)))
+        # <psi|H|psi> through the apply kernel
+        hp = torch.empty_like(psi)
+        H.apply(psi, hp)
+        torch.cuda.synchronize()
+        assert abs(np.vdot(p, hp.cpu().numpy()).real - e_or) < tol_e * abs(e_or)
+
+
+@pytest.mark.parametrize("m", EIG_CASES, ids=EIG_IDS)
+def test_expect_szsz_matches_definition(X, m):
+    """GPU symmetrised correlations against the oracle's product-state
+    expansion of the same vector (plain S^z_a S^z_b)."""
+    basis = oracle_basis(m)
+    b = X.Basis.from_model(m)
+    H = X.Hamiltonian.from_model(b, m)
+    e, psi, _, _ = H.eig0(tol=1e-13, max_iter=min(b.dim, 200), seed=2, prec=0)
+    N = m.n_sites
+    pairs = [(0, j) for j in range(N)] + [(3, 1), (N - 1, 2)]
+    got = X.xdg_expect_szsz(b.handle, psi, pairs)
+    p = psi.cpu().numpy()
+    full, amp = oracle.expand_state(m, basis, p)
+    want = np.array([oracle.szsz_definition(full, amp, a, c) for a, c in pairs])
+    assert np.max(np.abs(got - want)) < 1e-12, (got, want)
+    assert abs(got[0] - 0.25) < 1e-12
+    if 2 * m.n_up == N:
+        assert abs(got[:N].sum()) < 1e-12
+    # FP32 vectors: the same measurement within single-precision rounding
+    got32 = X.xdg_expect_szsz(b.handle, psi.to(torch.complex64 if b.is_complex else torch.float32),
+                              pairs)
+    assert np.max(np.abs(got32 - want)) < 1e-6
+
+
+def test_second_pass_errors(X):
+    m = W.chain_model(12, l=0)
+    b = X.Basis.from_model(m)
+    H = X.Hamiltonian.from_model(b, m)
+    _, _, al, be = H.lanczos(k=1, tol=0.0, max_iter=20, seed=1, prec=0)
+    psi = torch.empty(b.dim, dtype=torch.float64, device="cuda")
+    with pytest.raises(X.XdgError):      # forms with reorthogonalisation are refused
+        X.xdg_lanczos_eigvec(H.handle, al, be, psi, seed=1, prec=3)
+    with pytest.raises(X.XdgError):      # Ritz index out of range
+        X.xdg_lanczos_eigvec(H.handle, al, be, psi, seed=1, prec=0, which=20)
+    with pytest.raises(X.XdgError):      # site out of range
+        X.xdg_expect_szsz(b.handle, psi, [(0, 12)])

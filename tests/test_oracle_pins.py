@@ -429,3 +429,75 @@ def test_square4x4_ground_state_equals_full_space(oracle_lib):
     H = kron_hamiltonian(m, popcount_states(16, 8))
     e_full = spla.eigsh(H, k=1, which="SA", tol=1e-14)[0][0]
     assert abs(ev[0] - e_full) < 1e-11 * abs(e_full)
+
+
+# --------------------------------------------------- eigenvectors, measurements
+EXPAND_CASES = [
+    W.chain_model(12, l=0),                                           # real, translations
+    W.chain_model(12, l=5),                                           # complex characters
+    W.torus_model((4, 0), (0, 4), 1.0, 0.5, "B1"),                   # non-abelian group
+]
+
+
+@pytest.mark.parametrize("case", range(len(EXPAND_CASES)))
+def test_expanded_ground_state(oracle_lib, case):
+    """The product-state expansion of the block ground state: unit norm, an
+    eigenvector of the Kronecker-built U(1) Hamiltonian with the same energy,
+    and g Psi = chi(g) Psi for every g (so a slip in N_s, chi or the action
+    fails here)."""
+    m = EXPAND_CASES[case]
+    b = oracle_lib.basis(m)
+    e0, psi = oracle_lib.dense_ground_state(m, b)
+    full, amp = oracle_lib.expand_state(m, b, psi)
+    assert abs(np.linalg.norm(amp) - 1.0) < 1e-12
+    states = popcount_states(m.n_sites, m.n_up)
+    assert np.array_equal(states.astype(np.uint64), full)
+    H = kron_hamiltonian(m, states)
+    assert np.max(np.abs(H @ amp - e0 * amp)) < 1e-10
+    pos = {int(t): i for i, t in enumerate(full)}
+    for g, ch in zip(m.perm, m.chi):
+        moved = np.zeros_like(amp)
+        for i, t in enumerate(full):
+            moved[pos[oracle_lib.act(m.n_sites, g, int(t))]] = amp[i]
+        assert np.max(np.abs(moved - ch * amp)) < 1e-12
+
+
+def test_szsz_closed_forms(oracle_lib):
+    """<S^z_0 S^z_0> = 1/4; sum_j <S^z_0 S^z_j> = <S^z_0 S^z_tot> = 0 at Sz = 0;
+    the chain ground state is a translation-invariant singlet, so
+    <S^z_0 S^z_1> = <S_0.S_1>/3 = E0/(3N), with E0 from the Bethe ansatz."""
+    N = 16
+    m = W.chain_model(N, l=0)
+    b = oracle_lib.basis(m)
+    e0, psi = oracle_lib.dense_ground_state(m, b)
+    assert abs(e0 - bethe_energy(N, N // 2)) < 1e-11
+    full, amp = oracle_lib.expand_state(m, b, psi)
+    c = np.array([oracle_lib.szsz_definition(full, amp, 0, j) for j in range(N)])
+    assert abs(c[0] - 0.25) < 1e-14
+    assert abs(c.sum()) < 1e-13
+    assert abs(c[1] - bethe_energy(N, N // 2) / (3 * N)) < 1e-12
+    assert np.max(np.abs(c[1:] - c[1:][::-1])) < 1e-13        # reflection symmetry of the ring
+
+
+@pytest.mark.parametrize("case", range(len(EXPAND_CASES)))
+def test_symmetrised_diagonal_equals_plain_expectation(oracle_lib, case):
+    """For a state of the block, <O> of the plain S^z_a S^z_b equals
+    sum_s |psi_s|^2 (1/|G|) sum_g sz_s(g(a)) sz_s(g(b)): the reading of the
+    symmetrised operator used for measurements."""
+    m = EXPAND_CASES[case]
+    b = oracle_lib.basis(m)
+    rng = np.random.default_rng(case)
+    psi = rng.normal(size=len(b)) + (1j * rng.normal(size=len(b)) if m.is_complex else 0)
+    psi /= np.linalg.norm(psi)
+    full, amp = oracle_lib.expand_state(m, b, psi)
+    for a, c in ((0, 1), (0, 5), (3, 7), (2, 2)):
+        plain = oracle_lib.szsz_definition(full, amp, a, c)
+        sym = 0.0
+        for s, p in zip(b, psi):
+            o = 0.0
+            for g in m.perm:
+                ba = (int(s) >> int(g[a])) & 1
+                bc = (int(s) >> int(g[c])) & 1
+                o += 0.25 if ba == bc else -0.25
+            sym += abs(p) ** 2 * o / m.n_sym
+        assert abs(plain - sym) < 1e-13, (a, c)
