@@ -256,7 +256,7 @@ int ham_count_nnz(xdg_ham_s *h, int64_t *nnz) {
     }
     XDG_RETURN_IF(rc);
     unsigned long long c = 0;
-    XDG_TRY_HIP(hipMemcpy(&c, cnt.p, sizeof c, hipMemcpyDeviceToHost));
+    XDG_RETURN_IF(copy_d2h(&c, cnt.p, sizeof c, nullptr));
     h->nnz = b->dim + (int64_t)c;
     *nnz = h->nnz;
     return XDG_OK;

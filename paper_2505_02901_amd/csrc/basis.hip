@@ -30,7 +30,65 @@ int DevBuf::alloc(size_t n) {
 
 int DevBuf::upload(const void *host, size_t n) {
     XDG_RETURN_IF(alloc(n));
-    if (n) XDG_TRY_HIP(hipMemcpy(p, host, n, hipMemcpyHostToDevice));
+    if (n) XDG_RETURN_IF(copy_h2d(p, host, n, nullptr));
+    return XDG_OK;
+}
+
+// Host <-> device transfers go through a page-locked buffer owned by the
+// library (per thread, grown on demand, chunks of at most 64 MiB) with an
+// explicit wait after every chunk: no DMA ever targets pageable caller
+// memory, and no transfer is still in flight when the call returns.
+namespace {
+// (kept until the process ends: freeing it from a thread-exit destructor
+// could run after the HIP runtime has shut down)
+struct PinnedStage {
+    void *p = nullptr;
+    size_t cap = 0;
+    int reserve(size_t n) {
+        if (n <= cap) return XDG_OK;
+        if (p) (void)hipHostFree(p);
+        p = nullptr;
+        cap = 0;
+        hipError_t e = hipHostMalloc(&p, n, hipHostMallocDefault);
+        if (e != hipSuccess) {
+            p = nullptr;
+            (void)hipGetLastError();
+            set_error("hipHostMalloc(%zu bytes) failed: %s", n, hipGetErrorString(e));
+            return XDG_ENOMEM;
+        }
+        cap = n;
+        return XDG_OK;
+    }
+};
+thread_local PinnedStage g_stage;
+constexpr size_t STAGE_CHUNK = (size_t)64 << 20;
+}  // namespace
+
+int copy_d2h(void *dst, const void *src, size_t n, hipStream_t st) {
+    size_t done = 0;
+    while (done < n) {
+        const size_t len = std::min(STAGE_CHUNK, n - done);
+        XDG_RETURN_IF(g_stage.reserve(len));
+        XDG_TRY_HIP(hipMemcpyAsync(g_stage.p, static_cast<const char *>(src) + done, len,
+                                   hipMemcpyDeviceToHost, st));
+        XDG_TRY_HIP(hipStreamSynchronize(st));
+        std::memcpy(static_cast<char *>(dst) + done, g_stage.p, len);
+        done += len;
+    }
+    return XDG_OK;
+}
+
+int copy_h2d(void *dst, const void *src, size_t n, hipStream_t st) {
+    size_t done = 0;
+    while (done < n) {
+        const size_t len = std::min(STAGE_CHUNK, n - done);
+        XDG_RETURN_IF(g_stage.reserve(len));
+        std::memcpy(g_stage.p, static_cast<const char *>(src) + done, len);
+        XDG_TRY_HIP(hipMemcpyAsync(static_cast<char *>(dst) + done, g_stage.p, len,
+                                   hipMemcpyHostToDevice, st));
+        XDG_TRY_HIP(hipStreamSynchronize(st));
+        done += len;
+    }
     return XDG_OK;
 }
 
@@ -451,7 +509,7 @@ int enumerate(xdg_basis_s *b, DevBuf &binom_d) {
                            counts.as<uint32_t>(), A.n_chunks, tiles.as<uint64_t>(),
                            offsets.as<uint64_t>());
         XDG_TRY_HIP(hipGetLastError());
-        XDG_TRY_HIP(hipMemcpy(&dim, tot.p, sizeof dim, hipMemcpyDeviceToHost));
+        XDG_RETURN_IF(copy_d2h(&dim, tot.p, sizeof dim, nullptr));
         A.offsets = offsets.as<uint64_t>();
     }
     if (dim >= 0xFFFFFFFFull) {
@@ -537,7 +595,7 @@ int build_rank(xdg_basis_s *b) {
     const uint64_t dim = (uint64_t)b->dim;
     if (b->plan.flags & XDG_FLAG_HASH_INDEX) return XDG_OK;
     uint64_t last = 0;
-    XDG_TRY_HIP(hipMemcpy(&last, b->reps.as<W>() + (dim - 1), sizeof(W), hipMemcpyDeviceToHost));
+    XDG_RETURN_IF(copy_d2h(&last, b->reps.as<W>() + (dim - 1), sizeof(W), nullptr));
     const uint64_t n_words = (colex_rank_host(last) >> 5) + 1;
     const int slots = sizeof(W) == 4 ? 8 : 5;
     const double hash_bytes = 64.0 * std::ceil((double)dim / (slots * 0.5));

@@ -88,12 +88,18 @@ int xdg_create_basis(int n_sites, int n_up, int n_sym, const int32_t *perm, cons
         b->wide = n_sites > 32;
         if (n_sym) {
             b->perm.assign(perm, perm + (size_t)n_sym * n_sites);
-            b->chi.assign(2 * (size_t)n_sym, 0.0);
-            for (int g = 0; g < n_sym; ++g) {
-                b->chi[2 * g] = chi ? chi[2 * g] : 1.0;
-                b->chi[2 * g + 1] = chi ? chi[2 * g + 1] : 0.0;
-                if (std::fabs(b->chi[2 * g + 1]) > 1e-13) b->is_complex = true;
+            // a plain copy, then a separate scan of the imaginary parts: the
+            // fused copy-and-test loop was vectorised by the host compiler
+            // into code that tests one entry past the end of chi
+            if (chi) {
+                b->chi.assign(chi, chi + 2 * (size_t)n_sym);
+            } else {
+                b->chi.assign(2 * (size_t)n_sym, 0.0);
+                for (int g = 0; g < n_sym; ++g) b->chi[2 * (size_t)g] = 1.0;
             }
+            bool cplx = false;
+            for (size_t e = 1; e < b->chi.size(); e += 2) cplx |= std::fabs(b->chi[e]) > 1e-13;
+            b->is_complex = cplx;
         }
         int rc = make_plan(n_sites, n_sym, n_sym ? b->perm.data() : nullptr, opts, &b->plan, true);
         if (rc == XDG_OK) {
@@ -168,12 +174,12 @@ int xdg_basis_copy_states(xdg_basis b, int64_t begin, int64_t count, uint64_t *h
         }
         if (count == 0) return XDG_OK;
         if (b->wide) {
-            XDG_TRY_HIP(hipMemcpy(host_out, b->reps.as<uint64_t>() + begin, 8 * (size_t)count,
-                                  hipMemcpyDeviceToHost));
+            XDG_RETURN_IF(copy_d2h(host_out, b->reps.as<uint64_t>() + begin, 8 * (size_t)count,
+                                   nullptr));
         } else {
             std::vector<uint32_t> tmp((size_t)count);
-            XDG_TRY_HIP(hipMemcpy(tmp.data(), b->reps.as<uint32_t>() + begin, 4 * (size_t)count,
-                                  hipMemcpyDeviceToHost));
+            XDG_RETURN_IF(copy_d2h(tmp.data(), b->reps.as<uint32_t>() + begin, 4 * (size_t)count,
+                                   nullptr));
             for (int64_t i = 0; i < count; ++i) host_out[i] = tmp[(size_t)i];
         }
         return XDG_OK;
@@ -192,8 +198,8 @@ int xdg_basis_copy_stabilisers(xdg_basis b, int64_t begin, int64_t count, int32_
             return XDG_OK;
         }
         std::vector<uint16_t> tmp((size_t)count);
-        XDG_TRY_HIP(hipMemcpy(tmp.data(), b->stab.as<uint16_t>() + begin, 2 * (size_t)count,
-                              hipMemcpyDeviceToHost));
+        XDG_RETURN_IF(copy_d2h(tmp.data(), b->stab.as<uint16_t>() + begin, 2 * (size_t)count,
+                               nullptr));
         for (int64_t i = 0; i < count; ++i) host_out[i] = tmp[(size_t)i];
         return XDG_OK;
     });
@@ -214,7 +220,7 @@ int xdg_basis_index(xdg_basis b, const uint64_t *states, int64_t n, int64_t *idx
         XDG_RETURN_IF(ds.upload(states, 8 * (size_t)n));
         XDG_RETURN_IF(di.alloc(8 * (size_t)n));
         XDG_RETURN_IF(basis_lookup(b, ds.as<uint64_t>(), n, di.as<int64_t>(), 0));
-        XDG_TRY_HIP(hipMemcpy(idx_out, di.p, 8 * (size_t)n, hipMemcpyDeviceToHost));
+        XDG_RETURN_IF(copy_d2h(idx_out, di.p, 8 * (size_t)n, nullptr));
         return XDG_OK;
     });
 }

@@ -458,11 +458,8 @@ int lanczos_single(xdg_ham_s *h, const void *v0, int k, double tol, int max_iter
         }
         const bool check = tol > 0.0 || m == max_iter || (m % 16) == 0;
         if (check) {
-            XDG_TRY_HIP(hipMemcpyAsync(ha.data(), hist_a, sizeof(double) * m,
-                                       hipMemcpyDeviceToHost, st));
-            XDG_TRY_HIP(hipMemcpyAsync(hb.data(), hist_b, sizeof(double) * m,
-                                       hipMemcpyDeviceToHost, st));
-            XDG_TRY_HIP(hipStreamSynchronize(st));
+            XDG_RETURN_IF(copy_d2h(ha.data(), hist_a, sizeof(double) * m, st));
+            XDG_RETURN_IF(copy_d2h(hb.data(), hist_b, sizeof(double) * m, st));
             float ms = 0;
             // breakdown anywhere since the last check truncates the run there
             for (int t = std::max(0, m - 16); t < m; ++t)
@@ -501,8 +498,8 @@ int lanczos_single(xdg_ham_s *h, const void *v0, int k, double tol, int max_iter
         float ms = 0;
         if (hipEventElapsedTime(&ms, evs[2 * j], evs[2 * j + 1]) == hipSuccess) apply_s += 1e-3 * ms;
     }
-    XDG_TRY_HIP(hipMemcpy(ha.data(), hist_a, sizeof(double) * m, hipMemcpyDeviceToHost));
-    XDG_TRY_HIP(hipMemcpy(hb.data(), hist_b, sizeof(double) * m, hipMemcpyDeviceToHost));
+    XDG_RETURN_IF(copy_d2h(ha.data(), hist_a, sizeof(double) * m, st));
+    XDG_RETURN_IF(copy_d2h(hb.data(), hist_b, sizeof(double) * m, st));
     if (tol == 0.0 && !stop) status = XDG_OK;
     tridiag_eigenvalues(m, ha.data(), hb.data(), ritz);
     for (int e = 0; e < k; ++e) evals[e] = e < m ? ritz[e] : NAN;
@@ -633,8 +630,8 @@ int lanczos_eigvec(xdg_ham_s *h, const void *v0, uint64_t seed, int prec, int m,
     double *nrm = scal.as<double>(), *zero = nrm + 1, *al_d = nrm + 2, *be_d = al_d + m;
     int *jdev = reinterpret_cast<int *>(be_d + m);
     XDG_TRY_HIP(hipMemsetAsync(scal.p, 0, scal.bytes, st));
-    XDG_TRY_HIP(hipMemcpyAsync(al_d, alpha, sizeof(double) * m, hipMemcpyHostToDevice, st));
-    XDG_TRY_HIP(hipMemcpyAsync(be_d, beta, sizeof(double) * m, hipMemcpyHostToDevice, st));
+    XDG_RETURN_IF(copy_h2d(al_d, alpha, sizeof(double) * m, st));
+    XDG_RETURN_IF(copy_h2d(be_d, beta, sizeof(double) * m, st));
     XDG_TRY_HIP(hipMemsetAsync(acc.p, 0, acc.bytes, st));
     VecOps ops{single, C, C, nsc, vec_grid(nsc), nullptr, st};
     XDG_RETURN_IF(parts.alloc(sizeof(double) * (size_t)ops.grid * MAXC));
@@ -877,10 +874,8 @@ int lanczos_batched(int n, xdg_ham_s *const *hams, const void *const *v0s, int64
         std::vector<double> ha((size_t)n_iter * nvec), hb((size_t)n_iter * nvec), a1(n_iter),
             b1(n_iter), ritz;
         for (int i = 0; i < n && rc == XDG_OK; ++i) {
-            if (hipMemcpy(ha.data(), S[i].hist_a, sizeof(double) * ha.size(),
-                          hipMemcpyDeviceToHost) != hipSuccess ||
-                hipMemcpy(hb.data(), S[i].hist_b, sizeof(double) * hb.size(),
-                          hipMemcpyDeviceToHost) != hipSuccess) {
+            if (copy_d2h(ha.data(), S[i].hist_a, sizeof(double) * ha.size(), st) != XDG_OK ||
+                copy_d2h(hb.data(), S[i].hist_b, sizeof(double) * hb.size(), st) != XDG_OK) {
                 set_error("batched lanczos: copy of the tridiagonal matrices failed");
                 rc = XDG_EHIP;
                 break;

@@ -218,9 +218,7 @@ int expect_szsz(xdg_basis_s *b, const void *psi, int dtype, int n_pairs, const i
         }
 #undef XDG_SZSZ
         XDG_TRY_HIP(hipGetLastError());
-        XDG_TRY_HIP(hipMemcpyAsync(host_parts.data(), pp, sizeof(double) * host_parts.size(),
-                                   hipMemcpyDeviceToHost, st));
-        XDG_TRY_HIP(hipStreamSynchronize(st));
+        XDG_RETURN_IF(copy_d2h(host_parts.data(), pp, sizeof(double) * host_parts.size(), st));
         for (int k = 0; k < np; ++k) {
             double s = 0.0;
             for (int blk = 0; blk < grid; ++blk) s += host_parts[(size_t)blk * PB + k];

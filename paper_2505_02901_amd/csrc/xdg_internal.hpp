@@ -99,6 +99,11 @@ struct Plan {
     int flags = 0;   // XDG_FLAG_*
 };
 
+// Transfers between host memory and the device through a page-locked
+// staging buffer, complete on return.
+int copy_d2h(void *dst, const void *src, size_t n, hipStream_t st);
+int copy_h2d(void *dst, const void *src, size_t n, hipStream_t st);
+
 int validate_group(int n_sites, int n_sym, const int32_t *perm, const double *chi);
 int validate_bonds(int n_sites, int n_sym, const int32_t *perm, int n_bonds, const int32_t *sites,
                    const double *jz, const double *jxy);
