@@ -50,6 +50,9 @@ def sector_models():
     out += [W.torus_model((6, 2), (-2, 6), 1.0, 0.0, "A1", reflections=False, n_up=n,
                           name="tilted40") for n in (4, 5)]
     out += [W.chain_model(40, n_up=5, l=3), W.chain_model(34, n_up=4)]
+    # 2-, 3- and 5-sublattice lattices (generic block count in the search)
+    from test_oracle_pins import other_sublattice_models
+    out += other_sublattice_models()
     return out
 
 

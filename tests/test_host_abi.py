@@ -121,6 +121,13 @@ def test_planner_kinds(X):
     relab = np.array([perm[g[inv]] for g in c3.perm], dtype=np.int32)
     assert X.xdg_check_group(36, relab, None) == 0
     assert X.xdg_plan_search(36, relab)[0] == X.XDG_SEARCH_TABLE
+    # 2-, 3- and 5-sublattice labellings
+    for kind, a1, a2, ns in (("square2", (3, 1), (-1, 3), 2), ("triangle3", (5, -1), (1, 4), 3),
+                             ("square5", (2, 4), (-4, 2), 5)):
+        m = W.sublattice_model(kind, a1, a2)
+        assert X.xdg_plan_search(m.n_sites, m.perm) == (X.XDG_SEARCH_SUBLATTICE, ns), kind
+        assert X.xdg_check_group(m.n_sites, m.perm, m.chi) == 0
+        assert X.xdg_check_bonds(m.n_sites, m.perm, m.sites, m.jz, m.jxy) == 0
     # option flags: the defined bits pass, any other bit is refused
     t16 = W.chain_translations(16)
     acc = X.XDG_FLAG_F32_ACCUMULATE | X.XDG_FLAG_HASH_INDEX

@@ -160,6 +160,25 @@ def small_sector_models():
     # XXZ with anisotropy and unequal couplings on a ring
     m = W.chain_model(10, l=3, delta=0.4, J=0.7)
     out.append(m)
+    # 2-, 3- and 5-sublattice lattices (real and complex rotation characters)
+    out += other_sublattice_models(small=True)
+    return out
+
+
+def other_sublattice_models(small=False):
+    """Lattices with 2, 3 and 5 sublattice blocks (checkerboard square,
+    triangular, (x + 2y) mod 5 square), trivial and complex point-group
+    characters."""
+    out = [W.sublattice_model("square2", (3, 1), (-1, 3)),
+           W.sublattice_model("square2", (3, 1), (-1, 3), rot_char=1j, name="square2_10_E"),
+           W.sublattice_model("triangle3", (4, -2), (2, 2)),
+           W.sublattice_model("triangle3", (4, -2), (2, 2), rot_char=np.exp(1j * np.pi / 3),
+                              name="triangle3_12_E")]
+    if not small:
+        out += [W.sublattice_model("square5", (2, 4), (-4, 2)),
+                W.sublattice_model("square5", (2, 4), (-4, 2), rot_char=-1, name="square5_20_B"),
+                W.sublattice_model("triangle3", (5, -1), (1, 4), n_up=7),
+                W.sublattice_model("square2", (4, 0), (0, 4), delta=0.5)]
     return out
 
 
@@ -260,6 +279,7 @@ def test_dimension_formula(oracle_lib):
     models += [W.torus_model((4, 0), (0, 4), 1.0, 0.5, ir) for ir in ("A1", "A2", "B1", "B2")]
     models += [W.torus_model((4, 2), (-2, 4), 1.0, 0.0, "A1", reflections=False)]
     models += [W.torus_model((4, 2), (-2, 4), 1.0, 0.0, "B1", reflections=False, n_up=8)]
+    models += other_sublattice_models()
     for m in models:
         assert len(oracle_lib.basis(m)) == dimension_formula(m), m.name
 

@@ -131,9 +131,13 @@ class Torus:
     2 (y mod 2), m = N / 4 and w the rank of the point within its
     sublattice; otherwise row-major in the order found."""
 
-    def __init__(self, a1: Tuple[int, int], a2: Tuple[int, int], blocked: bool = True):
+    def __init__(self, a1: Tuple[int, int], a2: Tuple[int, int], blocked: bool = True,
+                 classes: Optional[Tuple[int, int, int]] = None):
+        """classes = (cx, cy, n): sublattice q = (cx x + cy y) mod n instead of the
+        default 2x2 classes; used for labelling when both periods lie in class 0."""
         self.a1 = tuple(a1)
         self.a2 = tuple(a2)
+        self.classes = classes
         det = a1[0] * a2[1] - a1[1] * a2[0]
         if det == 0:
             raise ValueError("degenerate torus")
@@ -157,11 +161,15 @@ class Torus:
                 if key not in canon or cand < canon[key][0]:
                     canon[key] = (cand, (x, y))
         points = [canon[k][1] for k in canon]
-        even = all(c % 2 == 0 for c in (*a1, *a2))
-        self.blocked = blocked and even and self.det % 4 == 0
+        if classes is None:
+            even = all(c % 2 == 0 for c in (*a1, *a2))
+            self.blocked = blocked and even and self.det % 4 == 0
+        else:
+            cx, cy, n = classes
+            self.blocked = (blocked and self.det % n == 0 and
+                            all((cx * a[0] + cy * a[1]) % n == 0 for a in (a1, a2)))
         if self.blocked:
-            def q_of(p):
-                return (p[0] % 2) + 2 * (p[1] % 2)
+            q_of = self.sublattice_of
             points.sort(key=lambda p: (q_of(p), p[1], p[0]))
         else:
             points.sort(key=lambda p: (p[1], p[0]))
@@ -181,9 +189,46 @@ class Torus:
     def contains_vector(self, x: int, y: int) -> bool:
         return self.key(x, y) == self.key(0, 0)
 
+    def sublattice_of(self, p) -> int:
+        if self.classes is None:
+            return (p[0] % 2) + 2 * (p[1] % 2)
+        cx, cy, n = self.classes
+        return (cx * p[0] + cy * p[1]) % n
+
     def sublattice(self, i: int) -> int:
-        x, y = self.points[i]
-        return (x % 2) + 2 * (y % 2)
+        return self.sublattice_of(self.points[i])
+
+    def bonds(self, neighbours, J: float = 1.0):
+        """Bonds (i, i + d) for the neighbour vectors d, coupling J."""
+        sites = []
+        for i, (x, y) in enumerate(self.points):
+            for dx, dy in neighbours:
+                j = self.site(x + dx, y + dy)
+                if j == i:
+                    raise ValueError("bond onto itself")
+                sites.append((i, j))
+        js = np.full(len(sites), J, dtype=np.float64)
+        return np.array(sites, dtype=np.int32), js.copy(), js.copy()
+
+    def group_from(self, point_ops):
+        """Translations x the given point operations (2x2 integer matrices acting
+        on (x, y)) that map the torus onto itself; (perm, labels (tx, ty, op))."""
+        ops = []
+        for k, M in enumerate(point_ops):
+            ok = True
+            for a in (self.a1, self.a2):
+                x, y = M[0][0] * a[0] + M[0][1] * a[1], M[1][0] * a[0] + M[1][1] * a[1]
+                ok &= self.contains_vector(x, y)
+            if ok:
+                ops.append((k, M))
+        perms, labels = [], []
+        for (tx, ty) in self.points:
+            for k, M in ops:
+                def f(x, y, tx=tx, ty=ty, M=M):
+                    return M[0][0] * x + M[0][1] * y + tx, M[1][0] * x + M[1][1] * y + ty
+                perms.append(self._perm_of(f))
+                labels.append((tx, ty, k))
+        return np.array(perms, dtype=np.int32), labels
 
     def j1j2_bonds(self, J1: float = 1.0, J2: float = 0.0):
         sites, js = [], []
@@ -265,6 +310,48 @@ def torus_model(a1, a2, J1=1.0, J2=0.0, irrep: Optional[str] = "A1", n_up=None,
         cr, cm = IRREPS_C4V[irrep]
         m = m.with_sector(perm, gamma_characters(labels, cr, cm), m.name + "_" + irrep)
     return m
+
+
+SQUARE_NEIGHBOURS = ((1, 0), (0, 1))
+TRIANGULAR_NEIGHBOURS = ((1, 0), (0, 1), (1, -1))
+ROT90 = ((0, -1), (1, 0))
+ROT60_TRI = ((0, -1), (1, 1))        # (x, y) -> (-y, x + y) in triangular lattice coordinates
+INVERSION = ((-1, 0), (0, -1))
+
+
+def _powers(M, n):
+    out, P = [], ((1, 0), (0, 1))
+    for _ in range(n):
+        out.append(P)
+        P = ((M[0][0] * P[0][0] + M[0][1] * P[1][0], M[0][0] * P[0][1] + M[0][1] * P[1][1]),
+             (M[1][0] * P[0][0] + M[1][1] * P[1][0], M[1][0] * P[0][1] + M[1][1] * P[1][1]))
+    return out
+
+
+def sublattice_model(kind: str, a1, a2, n_up=None, delta: float = 1.0, name=None,
+                     rot_char: complex = 1.0) -> Model:
+    """Heisenberg/XXZ models whose natural sublattice coding has 2, 3 or 5
+    blocks (the 2-, 3- and 5-sublattice backends of Sec. 5.1), trivial
+    characters of translations x point group:
+      'square2'   square lattice, checkerboard classes (x + y) mod 2, T x C4;
+      'triangle3' triangular lattice, classes (x + 2y) mod 3, T x C6;
+      'square5'   square lattice, classes (x + 2y) mod 5, T x C4.
+    Characters: 1 for translations, rot_char^r for the r-th power of the
+    rotation (Gamma-point one-dimensional irreps of C4 / C6)."""
+    classes, neigh, ops = {
+        "square2": ((1, 1, 2), SQUARE_NEIGHBOURS, _powers(ROT90, 4)),
+        "triangle3": ((1, 2, 3), TRIANGULAR_NEIGHBOURS, _powers(ROT60_TRI, 6)),
+        "square5": ((1, 2, 5), SQUARE_NEIGHBOURS, _powers(ROT90, 4)),
+    }[kind]
+    t = Torus(a1, a2, classes=classes)
+    if not t.blocked:
+        raise ValueError("periods do not preserve the sublattice classes")
+    sites, jz, jxy = t.bonds(neigh)
+    perm, labels = t.group_from(ops)
+    n_up = t.n_sites // 2 if n_up is None else n_up
+    m = Model(name or f"{kind}_{t.n_sites}", t.n_sites, n_up, sites, jz * delta, jxy)
+    chi = np.array([complex(rot_char) ** k for (_, _, k) in labels], dtype=np.complex128)
+    return m.with_sector(perm, chi)
 
 
 # --------------------------------------------------------------------------
