@@ -272,6 +272,21 @@ int xdg_lanczos_eigvec(xdg_ham h, const void *v0, uint64_t seed, int prec, int n
 int xdg_expect_szsz(xdg_basis b, const void *psi, int dtype, int n_pairs, const int32_t *pairs,
                     double *out, void *stream);
 
+/* Finite-temperature Lanczos thermodynamics (the thermodynamics examples of
+ * Sec. 4.6, after Jaklic and Prelovsek): from n_rec Lanczos recurrences of m
+ * steps started at random unit vectors (e.g. xdg_lanczos_eigval_batched),
+ *   Z(T) = sum_r weight[r] sum_j w_rj exp(-eps_rj / T),
+ * eps_rj the Ritz values and w_rj the squared first components of the Ritz
+ * vectors of recurrence r (the Gauss quadrature of <r|f(H)|r>); weight[r] =
+ * block dimension / number of vectors in that block.  A breakdown
+ * (beta_j <= 1e-13 max(1, |alpha_j|)) ends a recurrence at step j.
+ *   alpha, beta: host double[n_rec][m] (layout of xdg_lanczos_eigval_batched);
+ *   temps: host double[n_temp] > 0; outputs host double[n_temp]:
+ *   energy <H>, heat (<H^2> - <H>^2) / T^2, log_z = ln Z.  Host only. */
+int xdg_ftlm_thermo(int n_rec, int m, const double *alpha, const double *beta,
+                    const double *weight, int n_temp, const double *temps, double *energy,
+                    double *heat, double *log_z);
+
 /* Timing of the last xdg_lanczos_eigval[_batched] call on this thread:
  * total seconds in the iteration loop and seconds spent in the apply
  * kernels (HIP events); either may be NULL. */

@@ -364,6 +364,14 @@ int xdg_expect_szsz(xdg_basis b, const void *psi, int dtype, int n_pairs, const 
     });
 }
 
+int xdg_ftlm_thermo(int n_rec, int m, const double *alpha, const double *beta,
+                    const double *weight, int n_temp, const double *temps, double *energy,
+                    double *heat, double *log_z) {
+    return guarded([&]() -> int {
+        return ftlm_thermo(n_rec, m, alpha, beta, weight, n_temp, temps, energy, heat, log_z);
+    });
+}
+
 int xdg_last_lanczos_timing(double *total_s, double *apply_s) {
     return last_timing(total_s, apply_s);
 }

@@ -272,12 +272,20 @@ int progress_every() {
 
 }  // namespace
 
-// Eigenvalues of the symmetric tridiagonal matrix (alpha on the diagonal,
-// beta[i] coupling i and i+1), ascending, by implicit QL with shifts taken
-// from the leading 2x2 block (Bowdler, Martin, Reinsch, Wilkinson 1968).
-void tridiag_eigenvalues(int m, const double *alpha, const double *beta, std::vector<double> &out) {
-    std::vector<double> d(alpha, alpha + m), e(m, 0.0);
+// Implicit QL with shifts taken from the leading 2x2 block (Bowdler, Martin,
+// Reinsch, Wilkinson 1968) on the symmetric tridiagonal matrix with alpha on
+// the diagonal and beta[i] coupling i and i+1.  d receives the eigenvalues
+// (unsorted); z0, if given, the first components of the eigenvectors (the
+// rotations applied to the first row of the identity).
+static void tridiag_ql(int m, const double *alpha, const double *beta, std::vector<double> &d,
+                       std::vector<double> *z0) {
+    d.assign(alpha, alpha + m);
+    std::vector<double> e(m, 0.0);
     for (int i = 0; i + 1 < m; ++i) e[i] = beta[i];
+    if (z0) {
+        z0->assign(m, 0.0);
+        (*z0)[0] = 1.0;
+    }
     for (int l = 0; l < m; ++l) {
         for (int sweep = 0; sweep < 200; ++sweep) {
             int q = l;
@@ -309,6 +317,12 @@ void tridiag_eigenvalues(int m, const double *alpha, const double *beta, std::ve
                 p = s * r;
                 d[i + 1] = g + p;
                 g = c * r - bb;
+                if (z0) {
+                    double &zi = (*z0)[i], &zj = (*z0)[i + 1];
+                    const double t = zj;
+                    zj = s * zi + c * t;
+                    zi = c * zi - s * t;
+                }
             }
             if (split) continue;
             d[l] -= p;
@@ -316,8 +330,32 @@ void tridiag_eigenvalues(int m, const double *alpha, const double *beta, std::ve
             e[q] = 0.0;
         }
     }
+}
+
+// Eigenvalues of the symmetric tridiagonal matrix, ascending.
+void tridiag_eigenvalues(int m, const double *alpha, const double *beta, std::vector<double> &out) {
+    std::vector<double> d;
+    tridiag_ql(m, alpha, beta, d, nullptr);
     std::sort(d.begin(), d.end());
     out = d;
+}
+
+// Eigenvalues (ascending) and the squared first components of their
+// eigenvectors: the nodes and weights of the Gauss quadrature that the
+// Lanczos recurrence defines for the start vector.
+void tridiag_spectral_weights(int m, const double *alpha, const double *beta,
+                              std::vector<double> &evals, std::vector<double> &weights) {
+    std::vector<double> d, z;
+    tridiag_ql(m, alpha, beta, d, &z);
+    std::vector<int> order(m);
+    for (int i = 0; i < m; ++i) order[i] = i;
+    std::sort(order.begin(), order.end(), [&](int a, int b) { return d[a] < d[b]; });
+    evals.resize(m);
+    weights.resize(m);
+    for (int i = 0; i < m; ++i) {
+        evals[i] = d[order[i]];
+        weights[i] = z[order[i]] * z[order[i]];
+    }
 }
 
 int lanczos_single(xdg_ham_s *h, const void *v0, int k, double tol, int max_iter, uint64_t seed,

@@ -236,6 +236,10 @@ int lanczos_batched(int n, xdg_ham_s *const *hams, const void *const *v0s, int64
                     int n_iter, uint64_t seed, int prec, double *evals, double *alpha,
                     double *beta, hipStream_t st, double *t_total, double *t_apply);
 void tridiag_eigenvalues(int m, const double *alpha, const double *beta, std::vector<double> &out);
+void tridiag_spectral_weights(int m, const double *alpha, const double *beta,
+                              std::vector<double> &evals, std::vector<double> &weights);
+int ftlm_thermo(int n_rec, int m, const double *alpha, const double *beta, const double *weight,
+                int n_temp, const double *temps, double *energy, double *heat, double *log_z);
 void tridiag_eigvec(int m, const double *alpha, const double *beta, int which,
                     std::vector<double> &x, double &theta);
 int lanczos_eigvec(xdg_ham_s *h, const void *v0, uint64_t seed, int prec, int m,

@@ -81,6 +81,7 @@ def lib():
             "xdg_last_lanczos_timing": (I, [P, P]),
             "xdg_lanczos_eigvec": (I, [P, P, U64, I, I, P, P, I, P, P, P]),
             "xdg_expect_szsz": (I, [P, P, I, I, P, P, P]),
+            "xdg_ftlm_thermo": (I, [I, I, P, P, P, I, P, P, P, P]),
         }
         for name, (res, args) in sig.items():
             f = getattr(L, name)
@@ -98,7 +99,8 @@ def exported_names():
             "xdg_basis_copy_stabilisers", "xdg_basis_index", "xdg_create_hamiltonian",
             "xdg_destroy_hamiltonian", "xdg_ham_nnz", "xdg_apply", "xdg_apply_batched",
             "xdg_random_state", "xdg_lanczos_eigval", "xdg_lanczos_eigval_batched",
-            "xdg_last_lanczos_timing", "xdg_lanczos_eigvec", "xdg_expect_szsz"]
+            "xdg_last_lanczos_timing", "xdg_lanczos_eigvec", "xdg_expect_szsz",
+            "xdg_ftlm_thermo"]
 
 
 def _check(rc: int, allow=(XDG_OK,)):
@@ -363,6 +365,24 @@ def xdg_expect_szsz(b, psi, pairs, dtype: Optional[int] = None, stream=None) -> 
     _check(lib().xdg_expect_szsz(b, _ptr(psi), dtype, len(p), p.ctypes.data_as(C.c_void_p),
                                  out.ctypes.data_as(C.c_void_p), _stream(stream)))
     return out
+
+
+def xdg_ftlm_thermo(alpha, beta, weight, temps):
+    """(energy, heat, log_z) per temperature from Lanczos recurrences
+    alpha, beta [n_rec, m] with weights [n_rec]."""
+    al = np.ascontiguousarray(alpha, dtype=np.float64)
+    be = np.ascontiguousarray(beta, dtype=np.float64)
+    m = al.shape[-1]
+    al = al.reshape(-1, m)
+    be = be.reshape(-1, m)
+    w = np.ascontiguousarray(np.broadcast_to(np.asarray(weight, np.float64), (al.shape[0],)))
+    T = np.ascontiguousarray(temps, dtype=np.float64)
+    e, c, z = (np.zeros(len(T)) for _ in range(3))
+    _check(lib().xdg_ftlm_thermo(al.shape[0], m, al.ctypes.data_as(C.c_void_p),
+                                 be.ctypes.data_as(C.c_void_p), w.ctypes.data_as(C.c_void_p),
+                                 len(T), T.ctypes.data_as(C.c_void_p), e.ctypes.data_as(C.c_void_p),
+                                 c.ctypes.data_as(C.c_void_p), z.ctypes.data_as(C.c_void_p)))
+    return e, c, z
 
 
 def xdg_last_lanczos_timing() -> Tuple[float, float]:

@@ -442,3 +442,44 @@ def test_second_pass_errors(X):
         X.xdg_lanczos_eigvec(H.handle, al, be, psi, seed=1, prec=0, which=20)
     with pytest.raises(X.XdgError):      # site out of range
         X.xdg_expect_szsz(b.handle, psi, [(0, 12)])
+
+
+def test_ftlm_batched_matches_oracle_quadrature(X):
+    """Thermodynamics from R random vectors x M Lanczos steps in every momentum
+    sector of the N = 10 ring (batched GPU recurrences, FP64): the library's
+    FTLM against the oracle's recurrences from the same start vectors, with
+    the quadrature taken by LAPACK."""
+    N, R, M = 10, 4, 15
+    ms = [W.chain_model(N, l=l) for l in range(N)]
+    bs = [X.Basis.from_model(m) for m in ms]
+    hs = [X.Hamiltonian.from_model(b, m) for b, m in zip(bs, ms)]
+    v0 = [W.random_vector(40 + i, b.dim, R, kind="gauss", complex_=True) for i, b in enumerate(bs)]
+    v0t = [torch.from_numpy(v).to("cuda", torch.complex128) for v in v0]
+    ev, al, be = X.xdg_lanczos_eigval_batched([h.handle for h in hs], nvec=R, n_iter=M, prec=0,
+                                              v0s=v0t)
+    weights = np.repeat([b.dim / R for b in bs], R)
+    T = np.array([0.2, 0.5, 1.0, 2.0, 10.0])
+    e, c, lz = X.xdg_ftlm_thermo(al.reshape(-1, M), be.reshape(-1, M), weights, T)
+    nodes, wts = [], []
+    for i, m in enumerate(ms):
+        basis = oracle_basis(m)
+        for v in range(R):
+            st, _, a_o, b_o = oracle.lanczos(m, basis, v0[i][:, v], k=1, tol=0.0, max_iter=M)
+            assert len(a_o) == M
+            assert np.max(np.abs(al[i, v] - a_o)) < 1e-9 and np.max(np.abs(be[i, v] - b_o)) < 1e-9
+            Tm = np.diag(a_o) + np.diag(b_o[:-1], 1) + np.diag(b_o[:-1], -1)
+            E_, U = np.linalg.eigh(Tm)
+            nodes.append(E_)
+            wts.append(bs[i].dim / R * U[0] ** 2)
+    nodes, wts = np.concatenate(nodes), np.concatenate(wts)
+    for t, T_ in enumerate(T):
+        f = wts * np.exp(-(nodes - nodes.min()) / T_)
+        Z = f.sum()
+        E = (f * nodes).sum() / Z
+        E2 = (f * nodes ** 2).sum() / Z
+        assert abs(e[t] - E) < 1e-9 * max(1, abs(E))
+        assert abs(c[t] - (E2 - E * E) / T_ ** 2) < 1e-8 * max(1, abs(c[t]))
+        assert abs(lz[t] - (np.log(Z) - nodes.min() / T_)) < 1e-9 * max(1, abs(lz[t]))
+    # the lowest node is the ground-state energy of the ring (Bethe, N = 10)
+    from test_oracle_pins import bethe_energy
+    assert abs(nodes.min() - bethe_energy(N, N // 2)) < 1e-8

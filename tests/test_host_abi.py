@@ -142,3 +142,60 @@ def test_benchmark_lattices_are_symmetric(X):
         for m in W.workload(name):
             assert X.xdg_check_group(m.n_sites, m.perm, m.chi) == 0, name
             assert X.xdg_check_bonds(m.n_sites, m.perm, m.sites, m.jz, m.jxy) == 0, name
+
+
+def test_ftlm_quadrature_against_eigh(X):
+    """Host-side thermodynamics: nodes and weights of the Lanczos quadrature
+    (Ritz values, squared first components) against LAPACK's eigenvectors of
+    the same tridiagonal matrices."""
+    rng = np.random.default_rng(5)
+    R, m = 3, 25
+    al = rng.normal(size=(R, m))
+    be = np.abs(rng.normal(size=(R, m))) + 0.1
+    w = np.array([2.0, 1.0, 0.5])
+    T = np.array([0.1, 0.5, 1.0, 3.0, 20.0])
+    e, c, lz = X.xdg_ftlm_thermo(al, be, w, T)
+    nodes, weights = [], []
+    for r in range(R):
+        Tm = np.diag(al[r]) + np.diag(be[r, :-1], 1) + np.diag(be[r, :-1], -1)
+        ev, U = np.linalg.eigh(Tm)
+        nodes.append(ev)
+        weights.append(w[r] * U[0] ** 2)
+    nodes, weights = np.concatenate(nodes), np.concatenate(weights)
+    for t, T_ in enumerate(T):
+        f = weights * np.exp(-(nodes - nodes.min()) / T_)
+        Z = f.sum()
+        E = (f * nodes).sum() / Z
+        E2 = (f * nodes ** 2).sum() / Z
+        assert abs(e[t] - E) < 1e-12 * max(1, abs(E))
+        assert abs(c[t] - (E2 - E * E) / T_ ** 2) < 1e-10 * max(1, abs(c[t]))
+        assert abs(lz[t] - (np.log(Z) - nodes.min() / T_)) < 1e-12 * max(1, abs(lz[t]))
+    with pytest.raises(X.XdgError):
+        X.xdg_ftlm_thermo(al, be, w, [0.0])
+
+
+def test_ftlm_exact_at_full_krylov_dimension(X):
+    """With as many (reorthogonalised) Lanczos steps as the block dimension
+    the quadrature is exact: the library's thermodynamics from the oracle's
+    recurrence equals <r|exp(-H/T)|r> from the oracle's dense block matrix."""
+    import oracle
+    m = W.chain_model(10, l=0)
+    b = oracle.basis(m)
+    D = len(b)
+    x0 = W.random_vector(8, D, kind="gauss")
+    st, ev, al, be = oracle.lanczos(m, b, x0, k=1, tol=0.0, max_iter=D, reorth=True)
+    H = oracle.apply(m, b, np.eye(D, dtype=np.complex128))
+    En, U = np.linalg.eigh(H)
+    r = x0 / np.linalg.norm(x0)
+    wts = np.abs(U.conj().T @ r) ** 2
+    T = np.array([0.3, 1.0, 4.0])
+    pad = np.zeros(D)
+    A = pad.copy(); A[:len(al)] = al
+    B = pad.copy(); B[:len(be)] = be
+    e, c, lz = X.xdg_ftlm_thermo(A[None, :len(al)], B[None, :len(al)], [1.0], T)
+    for t, T_ in enumerate(T):
+        f = wts * np.exp(-(En - En[0]) / T_)
+        Z = f.sum()
+        E = (f * En).sum() / Z
+        assert abs(e[t] - E) < 1e-10, (T_, e[t], E)
+        assert abs(lz[t] - (np.log(Z) - En[0] / T_)) < 1e-10
