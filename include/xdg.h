@@ -287,6 +287,28 @@ int xdg_ftlm_thermo(int n_rec, int m, const double *alpha, const double *beta,
                     const double *weight, int n_temp, const double *temps, double *energy,
                     double *heat, double *log_z);
 
+/* y = O x for the one-site diagonal operator O = sum_j c_j S^z_j taking a
+ * vector of block `in` to block `out` (an operator at momentum q from the
+ * symmetrisation of Sec. 3.13, e.g. c_j = e^{i q j} / sqrt(N); dynamical
+ * structure factors, Sec. 4.4).  The blocks need the same sites, n_up and
+ * group, and c must carry the character ratio:
+ * c_{g^-1(i)} = (chi_in(g) / chi_out(g)) c_i for all g, i (else
+ * XDG_ENOTSYM); then y[r] = o(s_r) x[index_in(s_r)] with
+ * o(s) = sum_j c_j sz_s(j), and 0 where s_r has no state in `in`.
+ *   coef: host double[2 n_sites] (re, im); x: device [dim_in], y: device
+ *   [dim_out] of dtype (complex unless c and both blocks are real). */
+int xdg_apply_sz_transfer(xdg_basis in, xdg_basis out, const double *coef, const void *x,
+                          void *y, int dtype, void *stream);
+
+/* Spectral function from a Lanczos recurrence started at phi / |phi| (the
+ * continued fraction of <phi|(z - H)^-1|phi>, Sec. 4.4):
+ *   S(omega) = -Im[ norm2 / (z - a_0 - b_0^2 / (z - a_1 - ...)) ] / pi,
+ *   z = omega + e0 + i eta;  a breakdown ends the fraction.
+ *   alpha, beta: host double[m]; norm2 = <phi|phi>; out: host double[n_omega].
+ * Host only. */
+int xdg_spectral_cf(int m, const double *alpha, const double *beta, double norm2, double e0,
+                    int n_omega, const double *omega, double eta, double *out);
+
 /* Timing of the last xdg_lanczos_eigval[_batched] call on this thread:
  * total seconds in the iteration loop and seconds spent in the apply
  * kernels (HIP events); either may be NULL. */

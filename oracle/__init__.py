@@ -270,3 +270,20 @@ def dense_ground_state(m, basis_list: np.ndarray) -> Tuple[float, np.ndarray]:
     H = apply(m, basis_list, np.eye(D, dtype=np.complex128))
     w, v = np.linalg.eigh(H)
     return float(w[0]), v[:, 0]
+
+
+def dense_sz_spectrum(m_u1, coef) -> Tuple[float, np.ndarray, np.ndarray]:
+    """Full U(1) space (no symmetry): ground energy E0 and, for every
+    eigenstate n, (E_n - E0, |<n| sum_j coef_j S^z_j |0>|^2).  Dense LAPACK on
+    the oracle's matrix; small cases only.  The ground state must be unique."""
+    b = basis(m_u1)
+    D = len(b)
+    H = apply(m_u1, b, np.eye(D, dtype=np.complex128))
+    E, U = np.linalg.eigh(H)
+    if E[1] - E[0] < 1e-9:
+        raise ValueError("degenerate ground state")
+    bits = ((b[:, None] >> np.arange(m_u1.n_sites, dtype=np.uint64)[None, :]) & np.uint64(1))
+    o = ((bits.astype(np.float64) - 0.5) * np.asarray(coef, np.complex128)[None, :]).sum(axis=1)
+    phi = o * U[:, 0]
+    w = np.abs(U.conj().T @ phi) ** 2
+    return float(E[0]), E - E[0], w

@@ -372,6 +372,24 @@ int xdg_ftlm_thermo(int n_rec, int m, const double *alpha, const double *beta,
     });
 }
 
+int xdg_apply_sz_transfer(xdg_basis in, xdg_basis out, const double *coef, const void *x,
+                          void *y, int dtype, void *stream) {
+    return guarded([&]() -> int {
+        if (!in || !out) {
+            set_error("null basis");
+            return XDG_EINVAL;
+        }
+        return apply_diag_transfer(in, out, coef, x, y, dtype, (hipStream_t)stream);
+    });
+}
+
+int xdg_spectral_cf(int m, const double *alpha, const double *beta, double norm2, double e0,
+                    int n_omega, const double *omega, double eta, double *out) {
+    return guarded([&]() -> int {
+        return spectral_cf(m, alpha, beta, norm2, e0, n_omega, omega, eta, out);
+    });
+}
+
 int xdg_last_lanczos_timing(double *total_s, double *apply_s) {
     return last_timing(total_s, apply_s);
 }

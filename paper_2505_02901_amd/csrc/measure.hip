@@ -7,6 +7,7 @@
 // pairs with weights; a lane owns a state and up to PB pairs; block sums and
 // their total are taken in a fixed order.
 #include <algorithm>
+#include <complex>
 #include <map>
 #include <utility>
 #include <vector>
@@ -83,6 +84,13 @@ __device__ __forceinline__ W unrank_u1(uint64_t r, int N, int n_up, const uint64
         }
     }
     return s;
+}
+
+__global__ __launch_bounds__(MB) void k_unrank_all(int64_t dim, int N, int n_up,
+                                                   const uint64_t *binom, uint64_t *out) {
+    const int64_t stride = (int64_t)gridDim.x * MB;
+    for (int64_t i = (int64_t)blockIdx.x * MB + threadIdx.x; i < dim; i += stride)
+        out[i] = unrank_u1<uint64_t>((uint64_t)i, N, n_up, binom);
 }
 
 template <class W, class T, int C>
@@ -225,6 +233,152 @@ int expect_szsz(xdg_basis_s *b, const void *psi, int dtype, int n_pairs, const i
             out[k0 + k] = s;
         }
     }
+    return XDG_OK;
+}
+
+}  // namespace xdg
+
+// ---------------------------------------------------------------------------
+// Diagonal one-site operators between blocks (the operator at a momentum of
+// Sec. 3.13, used for dynamical structure factors, Sec. 4.4):
+//   O = sum_j c_j S^z_j.  If c is covariant, c_{g^-1(i)} = mu(g) c_i with
+//   mu(g) = chi_in(g) / chi_out(g), then O maps the symmetric state of
+//   representative s in the input block to o(s) times the symmetric state of
+//   s in the output block, o(s) = sum_j c_j sz_s(j) (zero when s has no state
+//   in the output block).  y[r] = o(s_r) x[idx_in(s_r)] over the output rows.
+namespace xdg {
+namespace {
+
+template <class W, class T, bool CPLX>
+__global__ __launch_bounds__(MB) void k_diag_transfer(const W *reps_out, const uint64_t *reps_u1,
+                                                      int64_t dim_out, int N, const int64_t *idx,
+                                                      const double2 *c, const T *x, T *y) {
+    __shared__ double2 sc[64];
+    for (int j = threadIdx.x; j < N; j += MB) sc[j] = c[j];
+    __syncthreads();
+    const int64_t stride = (int64_t)gridDim.x * MB;
+    for (int64_t r = (int64_t)blockIdx.x * MB + threadIdx.x; r < dim_out; r += stride) {
+        const uint64_t s = reps_out ? (uint64_t)reps_out[r] : reps_u1[r];
+        double orr = 0.0, oi = 0.0;
+        for (int j = 0; j < N; ++j) {
+            const double sz = ((s >> j) & 1) ? 0.5 : -0.5;
+            orr = __builtin_fma(sc[j].x, sz, orr);
+            oi = __builtin_fma(sc[j].y, sz, oi);
+        }
+        const int64_t q = idx[r];
+        if constexpr (CPLX) {
+            double yr = 0.0, yi = 0.0;
+            if (q >= 0) {
+                const double xr = (double)x[2 * q], xi = (double)x[2 * q + 1];
+                yr = orr * xr - oi * xi;
+                yi = orr * xi + oi * xr;
+            }
+            y[2 * r] = (T)yr;
+            y[2 * r + 1] = (T)yi;
+        } else {
+            y[r] = q >= 0 ? (T)(orr * (double)x[q]) : T(0);
+        }
+    }
+}
+
+template <class W>
+__global__ __launch_bounds__(MB) void k_widen(const W *in, int64_t n, uint64_t *out) {
+    const int64_t stride = (int64_t)gridDim.x * MB;
+    for (int64_t i = (int64_t)blockIdx.x * MB + threadIdx.x; i < n; i += stride) out[i] = in[i];
+}
+
+}  // namespace
+
+int apply_diag_transfer(xdg_basis_s *bin, xdg_basis_s *bout, const double *coef, const void *x,
+                        void *y, int dtype, hipStream_t st) {
+    if (!coef || (bout->dim > 0 && (!y || (!x && bin->dim > 0))) || x == y) {
+        set_error("diag transfer: bad arguments");
+        return XDG_EINVAL;
+    }
+    if (dtype < XDG_F64 || dtype > XDG_C64) {
+        set_error("unknown dtype %d", dtype);
+        return XDG_EINVAL;
+    }
+    const int N = bin->n_sites;
+    if (bout->n_sites != N || bout->n_up != bin->n_up || bout->n_sym != bin->n_sym ||
+        bout->perm != bin->perm) {
+        set_error("diag transfer: the blocks need the same sites, n_up and group");
+        return XDG_EINVAL;
+    }
+    bool coef_cplx = false;
+    for (int j = 0; j < N; ++j) coef_cplx |= std::fabs(coef[2 * j + 1]) > 0.0;
+    const bool cplx = dtype_complex(dtype);
+    if (!cplx && (coef_cplx || bin->is_complex || bout->is_complex)) {
+        set_error("diag transfer: complex coefficients or blocks need XDG_C128 / XDG_C64");
+        return XDG_EINVAL;
+    }
+    // covariance: c_{g^-1(i)} = mu(g) c_i with mu(g) = chi_in(g) / chi_out(g)
+    if (bin->n_sym) {
+        double cmax = 0.0;
+        for (int j = 0; j < N; ++j) cmax = std::max(cmax, std::hypot(coef[2 * j], coef[2 * j + 1]));
+        for (int g = 0; g < bin->n_sym; ++g) {
+            const std::complex<double> ci(bin->chi[2 * g], bin->chi[2 * g + 1]);
+            const std::complex<double> co(bout->chi[2 * g], bout->chi[2 * g + 1]);
+            const std::complex<double> mu = ci / co;
+            std::vector<int> inv(N);
+            for (int i = 0; i < N; ++i) inv[bin->perm[(size_t)g * N + i]] = i;
+            for (int i = 0; i < N; ++i) {
+                const std::complex<double> a(coef[2 * inv[i]], coef[2 * inv[i] + 1]);
+                const std::complex<double> b(coef[2 * i], coef[2 * i + 1]);
+                if (std::abs(a - mu * b) > 1e-12 * std::max(1.0, cmax)) {
+                    set_error("diag transfer: coefficients do not carry the character ratio of "
+                              "the two blocks (element %d, site %d)", g, i);
+                    return XDG_ENOTSYM;
+                }
+            }
+        }
+    }
+    const int64_t Dout = bout->dim;
+    if (Dout == 0) return XDG_OK;
+    DevBuf states, idx, cd;
+    XDG_RETURN_IF(idx.alloc(8 * (size_t)Dout));
+    std::vector<double> c2(coef, coef + 2 * (size_t)N);
+    XDG_RETURN_IF(cd.upload(c2.data(), c2.size() * 8));
+    const int grid = (int)std::min<int64_t>((Dout + MB - 1) / MB, (int64_t)device_cu_count() * 16);
+    const uint64_t *u1 = nullptr;
+    if (bout->plan.kind == K_U1) {
+        // U(1) rows: the states are the colex unranking of the row numbers
+        std::vector<uint64_t> bt(65 * 65);
+        for (int p = 0; p <= 64; ++p)
+            for (int q = 0; q <= 64; ++q) bt[p * 65 + q] = binomial(p, q);
+        DevBuf binom_d;
+        XDG_RETURN_IF(binom_d.upload(bt.data(), bt.size() * 8));
+        XDG_RETURN_IF(states.alloc(8 * (size_t)Dout));
+        hipLaunchKernelGGL(k_unrank_all, dim3(grid), dim3(MB), 0, st, Dout, N, bout->n_up,
+                           binom_d.as<uint64_t>(), states.as<uint64_t>());
+        XDG_TRY_HIP(hipGetLastError());
+        XDG_TRY_HIP(hipStreamSynchronize(st));
+        u1 = states.as<uint64_t>();
+    } else {
+        XDG_RETURN_IF(states.alloc(8 * (size_t)Dout));
+        if (bout->wide)
+            hipLaunchKernelGGL(k_widen<uint64_t>, dim3(grid), dim3(MB), 0, st,
+                               bout->reps.as<uint64_t>(), Dout, states.as<uint64_t>());
+        else
+            hipLaunchKernelGGL(k_widen<uint32_t>, dim3(grid), dim3(MB), 0, st,
+                               bout->reps.as<uint32_t>(), Dout, states.as<uint64_t>());
+        XDG_TRY_HIP(hipGetLastError());
+        u1 = states.as<uint64_t>();
+    }
+    XDG_TRY_HIP(hipStreamSynchronize(st));
+    XDG_RETURN_IF(basis_lookup(bin, states.as<uint64_t>(), Dout, idx.as<int64_t>(), st));
+    const double2 *c = cd.as<double2>();
+    const int64_t *ix = idx.as<int64_t>();
+#define XDG_TRANSFER(T_, CPLX_)                                                                 \
+    hipLaunchKernelGGL((k_diag_transfer<uint64_t, T_, CPLX_>), dim3(grid), dim3(MB), 0, st,   \
+                       nullptr, u1, Dout, N, ix, c, (const T_ *)x, (T_ *)y)
+    if (dtype == XDG_F64) XDG_TRANSFER(double, false);
+    else if (dtype == XDG_F32) XDG_TRANSFER(float, false);
+    else if (dtype == XDG_C128) XDG_TRANSFER(double, true);
+    else XDG_TRANSFER(float, true);
+#undef XDG_TRANSFER
+    XDG_TRY_HIP(hipGetLastError());
+    XDG_TRY_HIP(hipStreamSynchronize(st));
     return XDG_OK;
 }
 

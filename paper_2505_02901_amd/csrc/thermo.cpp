@@ -10,6 +10,7 @@
 // Lanczos driver; exponents are shifted by the lowest Ritz value overall.
 #include <algorithm>
 #include <cmath>
+#include <complex>
 #include <vector>
 
 #include "xdg_internal.hpp"
@@ -57,6 +58,32 @@ int ftlm_thermo(int n_rec, int m, const double *alpha, const double *beta, const
         energy[t] = mean + e_min;
         heat[t] = (e2 / z - mean * mean) / (T * T);
         log_z[t] = std::log(z) - e_min / T;
+    }
+    return XDG_OK;
+}
+
+// Spectral function from a Lanczos recurrence started at phi (continued
+// fraction of the resolvent; the dynamical examples of Sec. 4.4):
+//   G(z) = |phi|^2 / (z - a_0 - b_0^2 / (z - a_1 - b_1^2 / (...))),
+//   z = omega + e0 + i eta,  S(omega) = -Im G(z) / pi.
+// The fraction is evaluated from the bottom; a breakdown ends it.
+int spectral_cf(int m, const double *alpha, const double *beta, double norm2, double e0,
+                int n_w, const double *omega, double eta, double *out) {
+    if (m < 1 || !alpha || !beta || n_w < 0 || (n_w > 0 && (!omega || !out)) || !(eta > 0.0)) {
+        set_error("spectral: bad arguments (need m >= 1, eta > 0)");
+        return XDG_EINVAL;
+    }
+    int mm = m;
+    for (int j = 0; j + 1 < m; ++j)
+        if (beta[j] <= 1e-13 * std::max(1.0, std::fabs(alpha[j])) || !std::isfinite(beta[j])) {
+            mm = j + 1;
+            break;
+        }
+    for (int k = 0; k < n_w; ++k) {
+        const std::complex<double> z(omega[k] + e0, eta);
+        std::complex<double> t = z - alpha[mm - 1];
+        for (int j = mm - 2; j >= 0; --j) t = z - alpha[j] - beta[j] * beta[j] / t;
+        out[k] = -std::imag(norm2 / t) / M_PI;
     }
     return XDG_OK;
 }

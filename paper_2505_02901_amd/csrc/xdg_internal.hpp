@@ -238,6 +238,10 @@ int lanczos_batched(int n, xdg_ham_s *const *hams, const void *const *v0s, int64
 void tridiag_eigenvalues(int m, const double *alpha, const double *beta, std::vector<double> &out);
 void tridiag_spectral_weights(int m, const double *alpha, const double *beta,
                               std::vector<double> &evals, std::vector<double> &weights);
+int spectral_cf(int m, const double *alpha, const double *beta, double norm2, double e0,
+                int n_w, const double *omega, double eta, double *out);
+int apply_diag_transfer(xdg_basis_s *bin, xdg_basis_s *bout, const double *coef, const void *x,
+                        void *y, int dtype, hipStream_t st);
 int ftlm_thermo(int n_rec, int m, const double *alpha, const double *beta, const double *weight,
                 int n_temp, const double *temps, double *energy, double *heat, double *log_z);
 void tridiag_eigvec(int m, const double *alpha, const double *beta, int which,

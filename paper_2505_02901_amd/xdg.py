@@ -82,6 +82,8 @@ def lib():
             "xdg_lanczos_eigvec": (I, [P, P, U64, I, I, P, P, I, P, P, P]),
             "xdg_expect_szsz": (I, [P, P, I, I, P, P, P]),
             "xdg_ftlm_thermo": (I, [I, I, P, P, P, I, P, P, P, P]),
+            "xdg_apply_sz_transfer": (I, [P, P, P, P, P, I, P]),
+            "xdg_spectral_cf": (I, [I, P, P, D, D, I, P, D, P]),
         }
         for name, (res, args) in sig.items():
             f = getattr(L, name)
@@ -100,7 +102,7 @@ def exported_names():
             "xdg_destroy_hamiltonian", "xdg_ham_nnz", "xdg_apply", "xdg_apply_batched",
             "xdg_random_state", "xdg_lanczos_eigval", "xdg_lanczos_eigval_batched",
             "xdg_last_lanczos_timing", "xdg_lanczos_eigvec", "xdg_expect_szsz",
-            "xdg_ftlm_thermo"]
+            "xdg_ftlm_thermo", "xdg_apply_sz_transfer", "xdg_spectral_cf"]
 
 
 def _check(rc: int, allow=(XDG_OK,)):
@@ -383,6 +385,29 @@ def xdg_ftlm_thermo(alpha, beta, weight, temps):
                                  len(T), T.ctypes.data_as(C.c_void_p), e.ctypes.data_as(C.c_void_p),
                                  c.ctypes.data_as(C.c_void_p), z.ctypes.data_as(C.c_void_p)))
     return e, c, z
+
+
+def xdg_apply_sz_transfer(b_in, b_out, coef, x, y, dtype: Optional[int] = None, stream=None):
+    """y = (sum_j coef_j S^z_j) x from block b_in to block b_out."""
+    c = np.asarray(coef, dtype=np.complex128)
+    ci = np.empty((len(c), 2), np.float64)
+    ci[:, 0], ci[:, 1] = c.real, c.imag
+    if dtype is None:
+        dtype = _dtype_code(x)
+    _check(lib().xdg_apply_sz_transfer(b_in, b_out, ci.ctypes.data_as(C.c_void_p), _ptr(x),
+                                       _ptr(y), dtype, _stream(stream)))
+    return y
+
+
+def xdg_spectral_cf(alpha, beta, norm2: float, e0: float, omega, eta: float) -> np.ndarray:
+    al = np.ascontiguousarray(alpha, dtype=np.float64)
+    be = np.ascontiguousarray(beta, dtype=np.float64)
+    w = np.ascontiguousarray(omega, dtype=np.float64)
+    out = np.zeros(len(w))
+    _check(lib().xdg_spectral_cf(len(al), al.ctypes.data_as(C.c_void_p),
+                                 be.ctypes.data_as(C.c_void_p), norm2, e0, len(w),
+                                 w.ctypes.data_as(C.c_void_p), eta, out.ctypes.data_as(C.c_void_p)))
+    return out
 
 
 def xdg_last_lanczos_timing() -> Tuple[float, float]:

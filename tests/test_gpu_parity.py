@@ -483,3 +483,39 @@ def test_ftlm_batched_matches_oracle_quadrature(X):
     # the lowest node is the ground-state energy of the ring (Bethe, N = 10)
     from test_oracle_pins import bethe_energy
     assert abs(nodes.min() - bethe_energy(N, N // 2)) < 1e-8
+
+
+@pytest.mark.parametrize("lq", [3, 6])
+def test_dynamical_structure_factor_matches_dense(X, lq):
+    """S^zz(q, omega) of the N = 12 ring: ground state of the k = 0 block (two
+    Lanczos passes), S^z_q applied into the k = q block, Lanczos from there and
+    the continued fraction, against the dense full-space spectrum of the
+    oracle with the same Lorentzian width."""
+    N = 12
+    m0, mq = W.chain_model(N, l=0), W.chain_model(N, l=lq)
+    b0, bq = X.Basis.from_model(m0), X.Basis.from_model(mq)
+    H0, Hq = X.Hamiltonian.from_model(b0, m0), X.Hamiltonian.from_model(bq, mq)
+    e0, psi, _, _ = H0.eig0(tol=1e-14, max_iter=min(b0.dim, 200), seed=3, prec=0)
+    q = 2 * np.pi * lq / N
+    coef = np.exp(1j * q * np.arange(N)) / np.sqrt(N)
+    phi = torch.zeros(bq.dim, dtype=torch.complex128, device="cuda")
+    X.xdg_apply_sz_transfer(b0.handle, bq.handle, coef, psi.to(torch.complex128), phi)
+    torch.cuda.synchronize()
+    norm2 = float((phi.abs() ** 2).sum())
+    v0 = phi if bq.is_complex else phi.real.contiguous()
+    if not bq.is_complex:
+        assert float(phi.imag.abs().max()) < 1e-14
+    _, _, al, be = Hq.lanczos(k=1, tol=0.0, max_iter=min(bq.dim, 60), prec=0, v0=v0)
+    omega = np.linspace(0.0, 4.0, 161)
+    eta = 0.1
+    got = X.xdg_spectral_cf(al, be, norm2, e0, omega, eta)
+    E0, dE, w = oracle.dense_sz_spectrum(W.chain_model(N), coef)
+    assert abs(E0 - e0) < 1e-10
+    # the Lanczos ground state is accurate to ~sqrt(dE / gap) ~ 1e-7, so
+    # quantities linear in |psi><psi| agree to that order
+    assert abs(norm2 - w.sum()) < 1e-7 * w.sum()
+    want = (w[None, :] * eta / np.pi / ((omega[:, None] - dE[None, :]) ** 2 + eta ** 2)).sum(axis=1)
+    assert np.max(np.abs(got - want)) < 1e-6 * np.max(want), np.max(np.abs(got - want))
+    # a coefficient vector that does not carry the character ratio is refused
+    with pytest.raises(X.XdgError):
+        X.xdg_apply_sz_transfer(b0.handle, bq.handle, np.ones(N), psi.to(torch.complex128), phi)

@@ -199,3 +199,23 @@ def test_ftlm_exact_at_full_krylov_dimension(X):
         E = (f * En).sum() / Z
         assert abs(e[t] - E) < 1e-10, (T_, e[t], E)
         assert abs(lz[t] - (np.log(Z) - En[0] / T_)) < 1e-10
+
+
+def test_spectral_continued_fraction_against_eigh(X):
+    """The continued fraction of a tridiagonal matrix equals its resolvent's
+    (0, 0) element: sum_j w_j / (z - eps_j) with LAPACK's eigenpairs."""
+    rng = np.random.default_rng(9)
+    m = 30
+    al = rng.normal(size=m)
+    be = np.abs(rng.normal(size=m)) + 0.2
+    Tm = np.diag(al) + np.diag(be[:-1], 1) + np.diag(be[:-1], -1)
+    ev, U = np.linalg.eigh(Tm)
+    w = U[0] ** 2
+    omega = np.linspace(-3, 6, 91)
+    e0, eta, norm2 = -1.5, 0.07, 2.5
+    got = X.xdg_spectral_cf(al, be, norm2, e0, omega, eta)
+    z = omega + e0 + 1j * eta
+    want = -np.imag(norm2 * (w[None, :] / (z[:, None] - ev[None, :])).sum(axis=1)) / np.pi
+    assert np.max(np.abs(got - want)) < 1e-12 * np.max(np.abs(want))
+    with pytest.raises(X.XdgError):
+        X.xdg_spectral_cf(al, be, norm2, e0, omega, 0.0)

@@ -521,3 +521,26 @@ def test_symmetrised_diagonal_equals_plain_expectation(oracle_lib, case):
                 o += 0.25 if ba == bc else -0.25
             sym += abs(p) ** 2 * o / m.n_sym
         assert abs(plain - sym) < 1e-13, (a, c)
+
+
+def test_dynamical_sum_rule_matches_static_correlations(oracle_lib):
+    """Sum rule of the dynamical structure factor: sum_n |<n|S^z_q|0>|^2 (full
+    U(1) space, dense) = sum_j e^{iqj} <S^z_0 S^z_j> (ground state of the k = 0
+    block expanded into product states), for every q of the N = 12 ring."""
+    N = 12
+    m_u1 = W.chain_model(N)
+    m0 = W.chain_model(N, l=0)
+    b = oracle_lib.basis(m0)
+    e0, psi = oracle_lib.dense_ground_state(m0, b)
+    full, amp = oracle_lib.expand_state(m0, b, psi)
+    c = np.array([oracle_lib.szsz_definition(full, amp, 0, j) for j in range(N)])
+    for l in range(N):
+        q = 2 * np.pi * l / N
+        coef = np.exp(1j * q * np.arange(N)) / np.sqrt(N)
+        E0, dE, w = oracle_lib.dense_sz_spectrum(m_u1, coef)
+        assert abs(E0 - e0) < 1e-11
+        Sq = np.real(np.sum(np.exp(1j * q * np.arange(N)) * c))
+        assert abs(w.sum() - Sq) < 1e-12, (l, w.sum(), Sq)
+    # q = 0: S^z_tot |0> = 0 at Sz = 0, so no weight at all
+    E0, dE, w = oracle_lib.dense_sz_spectrum(m_u1, np.ones(N) / np.sqrt(N))
+    assert w.sum() < 1e-24
