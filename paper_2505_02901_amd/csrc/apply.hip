@@ -18,6 +18,13 @@ static size_t lds_budget() {
     return lds_limit() > stat ? lds_limit() - stat : 0;
 }
 
+// two workgroups of the apply kernel fit in one CU's LDS: run the variant
+// limited to 64 VGPRs (8 waves per SIMD)
+static int occ_for(size_t lds) {
+    const size_t stat = sizeof(SectorDesc) + 64;
+    return 2 * (lds + stat) <= lds_limit() ? 1 : 0;
+}
+
 size_t dtype_size(int dtype) {
     switch (dtype) {
         case XDG_F64: return 8;
@@ -162,6 +169,7 @@ int apply_launch(xdg_ham_s *h, const void *x, void *y, int64_t nvec, int dtype, 
         lds = f.tsingle ? stage_bytes<float>(A.one, b->plan.kind, 0)
                         : stage_bytes<double>(A.one, b->plan.kind, 0);
     }
+    A.occ = A.stage_sub ? occ_for(lds) : 0;
     const int cap = c.nv > 0 ? c.nv : 8;
     for (int64_t v0 = 0; v0 < f.cols;) {
         const int nv = pick_nv(f.cols - v0, cap);
@@ -333,6 +341,7 @@ int batch_launch(const BatchPlan &P, int grid, int nv_cap, hipStream_t st) {
     A.queue = P.queue.as<uint32_t>();
     A.nvec = P.cols;
     A.stage_sub = P.stage_sub;
+    A.occ = P.stage_sub ? occ_for(P.lds) : 0;
     const unsigned g = (unsigned)(grid > 0 ? grid : apply_grid_for(2));
     for (int64_t v0 = 0; v0 < P.cols;) {
         const int nv = pick_nv(P.cols - v0, nv_cap > 0 ? nv_cap : 8);

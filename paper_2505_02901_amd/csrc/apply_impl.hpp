@@ -21,6 +21,9 @@ namespace xdg {
 #define XDG_APPLY_BLOCK 1024
 #endif
 constexpr int APPLY_BLOCK = XDG_APPLY_BLOCK;
+// Occupancy variant: at most 64 VGPRs (8 waves per SIMD, two 1024-lane
+// workgroups per CU), chosen when two workgroups' LDS fit in one CU.
+constexpr int OCC_WAVES = 8;
 constexpr int BLOCKS_PER_1024 = 1024 / APPLY_BLOCK;   // grid scale for smaller workgroups
 
 template <class T> struct Vec2;
@@ -85,6 +88,7 @@ struct ApplyArgs {
     int64_t nvec;
     int v0;                      // first vector of this pass
     int stage_sub;               // copy sublattice tables into LDS
+    int occ;                     // use the 8-waves-per-SIMD variant
     unsigned long long *count;   // nnz counting mode (nullptr otherwise)
 };
 
@@ -303,8 +307,8 @@ __device__ __forceinline__ uint32_t count_row(const SectorDesc &d, const Staged<
     return n;
 }
 
-template <class W, int KIND, class T, class AC, bool CPLX, int NV, bool STAGE>
-__global__ __launch_bounds__(APPLY_BLOCK) void k_apply(ApplyArgs A) {
+template <class W, int KIND, class T, class AC, bool CPLX, int NV, bool STAGE, bool OCC>
+__global__ __launch_bounds__(APPLY_BLOCK, OCC ? OCC_WAVES : 1) void k_apply(ApplyArgs A) {
     extern __shared__ __align__(16) unsigned char smem[];
     __shared__ uint32_t s_tile;
     __shared__ SectorDesc s_desc;
@@ -378,13 +382,13 @@ template <int KIND>
 int launch_count_kind(bool wide, const ApplyArgs &A, unsigned grid, unsigned block, size_t lds,
                       hipStream_t st);
 
-template <class W, int KIND, class T, class AC, bool CPLX, bool STAGE>
+template <class W, int KIND, class T, class AC, bool CPLX, bool STAGE, bool OCC>
 void (*apply_kernel(int nv))(ApplyArgs) {
     switch (nv) {
-        case 1: return k_apply<W, KIND, T, AC, CPLX, 1, STAGE>;
-        case 2: return k_apply<W, KIND, T, AC, CPLX, 2, STAGE>;
-        case 4: return k_apply<W, KIND, T, AC, CPLX, 4, STAGE>;
-        case 8: return k_apply<W, KIND, T, AC, CPLX, 8, STAGE>;
+        case 1: return k_apply<W, KIND, T, AC, CPLX, 1, STAGE, OCC>;
+        case 2: return k_apply<W, KIND, T, AC, CPLX, 2, STAGE, OCC>;
+        case 4: return k_apply<W, KIND, T, AC, CPLX, 4, STAGE, OCC>;
+        case 8: return k_apply<W, KIND, T, AC, CPLX, 8, STAGE, OCC>;
     }
     return nullptr;
 }
@@ -395,9 +399,10 @@ int launch_nv(int nv, const ApplyArgs &A, unsigned grid, unsigned block, size_t 
     void (*f)(ApplyArgs) = nullptr;
     // only the sublattice kind has tables that may stay in global memory
     if (KIND != K_SUB || A.stage_sub)
-        f = apply_kernel<W, KIND, T, AC, CPLX, true>(nv);
+        f = A.occ ? apply_kernel<W, KIND, T, AC, CPLX, true, true>(nv)
+                  : apply_kernel<W, KIND, T, AC, CPLX, true, false>(nv);
     else if constexpr (KIND == K_SUB)
-        f = apply_kernel<W, KIND, T, AC, CPLX, false>(nv);
+        f = apply_kernel<W, KIND, T, AC, CPLX, false, false>(nv);
     if (!f) {
         set_error("vectors per pass %d not in {1, 2, 4, 8}", nv);
         return XDG_EINVAL;
