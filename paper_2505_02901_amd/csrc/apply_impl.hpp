@@ -188,7 +188,7 @@ __device__ __forceinline__ int64_t locate(const SectorDesc &d, const Staged<T> &
         const uint32_t *lin = d.lin;
         u = 0;
         cnt = 1;
-        return (int64_t)lin[(1ull << d.nlo) + hi] + (int64_t)lin[lo];
+        return (int64_t)gld(lin + (1ull << d.nlo) + hi) + (int64_t)gld(lin + lo);
     } else {
         W rep;
         if constexpr (KIND == K_AFF) {
@@ -218,7 +218,7 @@ __device__ __forceinline__ void process_row(const SectorDesc &d, const Staged<A>
                                             int64_t nvec, int v0) {
     using B = typename BondT<A>::type;
     constexpr int C = CPLX ? 2 : 1;
-    const W s = reinterpret_cast<const W *>(d.reps)[row];
+    const W s = gld(reinterpret_cast<const W *>(d.reps) + row);
     const T *X = reinterpret_cast<const T *>(d.x);
     T *Y = reinterpret_cast<T *>(d.y);
     const int nb = d.n_bonds;
@@ -231,9 +231,9 @@ __device__ __forceinline__ void process_row(const SectorDesc &d, const Staged<A>
     A acc[NV * C];
     const size_t base = ((size_t)row * nvec + v0) * C;
 #pragma unroll
-    for (int v = 0; v < NV * C; ++v) acc[v] = diag * (A)X[base + v];
+    for (int v = 0; v < NV * C; ++v) acc[v] = diag * (A)gld(X + base + v);
     A rn = A(1);
-    if constexpr (KIND != K_U1) rn = S.rsq[d.stab[row]];
+    if constexpr (KIND != K_U1) rn = S.rsq[gld(d.stab + row)];
     auto term = [&](const B &bd) {
         const W t = s ^ ((W(1) << bd.i) | (W(1) << bd.j));
         int u, cnt;
@@ -252,11 +252,11 @@ __device__ __forceinline__ void process_row(const SectorDesc &d, const Staged<A>
 #pragma unroll
         for (int v = 0; v < NV; ++v) {
             if constexpr (CPLX) {
-                const A xr = X[xb + 2 * v], xi = X[xb + 2 * v + 1];
+                const A xr = gld(X + xb + 2 * v), xi = gld(X + xb + 2 * v + 1);
                 acc[2 * v] = fmadd<A>(-ai, xi, fmadd<A>(ar, xr, acc[2 * v]));
                 acc[2 * v + 1] = fmadd<A>(ai, xr, fmadd<A>(ar, xi, acc[2 * v + 1]));
             } else {
-                acc[v] = fmadd<A>(ar, (A)X[xb + v], acc[v]);
+                acc[v] = fmadd<A>(ar, (A)gld(X + xb + v), acc[v]);
             }
         }
     };
@@ -288,7 +288,7 @@ __device__ __forceinline__ void process_row(const SectorDesc &d, const Staged<A>
         }
     }
 #pragma unroll
-    for (int v = 0; v < NV * C; ++v) Y[base + v] = (T)acc[v];
+    for (int v = 0; v < NV * C; ++v) gst(Y + base + v, (T)acc[v]);
 }
 
 // count of the off-diagonal terms of a row that land in the block

@@ -14,6 +14,27 @@ namespace xdg {
 enum : int { K_U1 = XDG_SEARCH_U1, K_AFF = XDG_SEARCH_AFFINE, K_SUB = XDG_SEARCH_SUBLATTICE,
              K_TAB = XDG_SEARCH_TABLE };
 
+// ------------------------------------------------- global memory access --
+// Loads and stores through the global address space.  A generic (flat)
+// access is counted by the LDS counter as well, so the wait for an LDS table
+// read that follows it would also wait for the HBM access; these helpers are
+// for pointers known to address device memory from the allocator.
+template <class T>
+__device__ __forceinline__ T gld(const T *p) {
+    return *(const __attribute__((address_space(1))) T *)p;
+}
+// uint4 is a class whose copy constructor takes a generic reference, which
+// would turn the load back into a flat one: load a native vector instead.
+__device__ __forceinline__ uint4 gld(const uint4 *p) {
+    typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
+    const u32x4 v = *(const __attribute__((address_space(1))) u32x4 *)p;
+    return make_uint4(v.x, v.y, v.z, v.w);
+}
+template <class T>
+__device__ __forceinline__ void gst(T *p, T v) {
+    *(__attribute__((address_space(1))) T *)p = v;
+}
+
 // ------------------------------------------------------------ bit helpers --
 template <class W>
 __device__ __forceinline__ W rotr_n(W t, int a, int N) {
@@ -61,10 +82,13 @@ __device__ __forceinline__ uint64_t colex_rank(const uint64_t *T, int cb, int nc
 __device__ __forceinline__ int64_t rank_find(const uint2 *words, uint64_t n_words, uint64_t r) {
     const uint64_t w = r >> 5;
     if (w >= n_words) return -1;
-    const uint2 e = words[w];
+    // one 8-byte read of {count, bits}, no branch on the bit: both halves
+    // come back with the same load
+    const uint64_t e = gld(reinterpret_cast<const uint64_t *>(words) + w);
+    const uint32_t cnt = (uint32_t)e, bits = (uint32_t)(e >> 32);
     const uint32_t b = (uint32_t)r & 31u;
-    if (!((e.y >> b) & 1u)) return -1;
-    return (int64_t)e.x + __popc(e.y & ((1u << b) - 1u));
+    const int64_t idx = (int64_t)cnt + __popc(bits & ((1u << b) - 1u));
+    return ((bits >> b) & 1u) ? idx : -1;
 }
 
 // ------------------------------------------------------------- hash index --
@@ -98,7 +122,7 @@ __device__ __forceinline__ int64_t hash_find(const void *table, uint64_t n_lines
         if constexpr (sizeof(W) == 4) {
             const uint4 *p = reinterpret_cast<const uint4 *>(
                 reinterpret_cast<const Line32 *>(table) + line);
-            const uint4 k0 = p[0], k1 = p[1], v0 = p[2], v1 = p[3];
+            const uint4 k0 = gld(p), k1 = gld(p + 1), v0 = gld(p + 2), v1 = gld(p + 3);
             const uint32_t ks[8] = {k0.x, k0.y, k0.z, k0.w, k1.x, k1.y, k1.z, k1.w};
             const uint32_t vs[8] = {v0.x, v0.y, v0.z, v0.w, v1.x, v1.y, v1.z, v1.w};
             int64_t found = -1;
@@ -113,7 +137,7 @@ __device__ __forceinline__ int64_t hash_find(const void *table, uint64_t n_lines
         } else {
             const uint4 *p = reinterpret_cast<const uint4 *>(
                 reinterpret_cast<const Line64 *>(table) + line);
-            const uint4 a = p[0], b = p[1], c = p[2], d = p[3];
+            const uint4 a = gld(p), b = gld(p + 1), c = gld(p + 2), d = gld(p + 3);
             const uint64_t ks[5] = {((uint64_t)a.y << 32) | a.x, ((uint64_t)a.w << 32) | a.z,
                                     ((uint64_t)b.y << 32) | b.x, ((uint64_t)b.w << 32) | b.z,
                                     ((uint64_t)c.y << 32) | c.x};
