@@ -52,8 +52,9 @@ struct SectorDesc {
     uint64_t empty;
     const uint2 *rwords;         // rank index (null: hash)
     uint64_t n_rwords;
-    const uint64_t *rtab;        // colex chunk tables [rnc][rnb][2^rcb]
-    int rcb, rnc, rnb;
+    const void *rtab;            // colex chunk tables: rrows rows of 2^rcb entries of resz bytes
+    int rcb, rnc, rrows, resz;
+    int n_up;
     const uint32_t *lin;         // Lin tables (U(1))
     int nlo;
     int n_sites, n_sym, n_bonds;
@@ -101,8 +102,8 @@ __host__ __device__ inline size_t sub_table_bytes(const SectorDesc &d) {
            a16(2 * (size_t)d.n_perm * 2 * ((size_t)1 << d.pb));
 }
 
-__host__ __device__ inline size_t rank_table_len(const SectorDesc &d) {
-    return d.rwords ? ((size_t)d.rnc * d.rnb) << d.rcb : 0;
+__host__ __device__ inline size_t rank_table_bytes(const SectorDesc &d) {
+    return d.rwords ? ((size_t)d.rrows << d.rcb) * d.resz : 0;
 }
 
 // LDS bytes needed to stage a sector's tables.
@@ -112,7 +113,7 @@ __host__ __device__ inline size_t stage_bytes(const SectorDesc &d, int kind, int
     if (kind != K_U1) {
         n += a16(sizeof(typename Vec2<T>::type) * d.n_sym);
         n += a16(sizeof(T) * 2 * (d.n_sym + 1));
-        n += a16(8 * rank_table_len(d));
+        n += a16(rank_table_bytes(d));
         if (kind == K_AFF) n += a16(sizeof(AffineElem) * d.n_sym) + a16(4 * (size_t)d.n_sites);
         if (kind == K_SUB && stage_sub) n += sub_table_bytes(d);
     }
@@ -127,7 +128,7 @@ struct Staged {
     const T *rsq;      // 1/sqrt(c)
     const AffineElem *aff;
     const int16_t *ring_gidx;
-    const uint64_t *rtab;
+    const void *rtab;
     SubCtx sub;
 };
 
@@ -154,7 +155,8 @@ __device__ inline void stage(const SectorDesc &d, unsigned char *smem, Staged<T>
         const T *ls = stage_copy(smem, off, reinterpret_cast<const T *>(d.sqrtt), 2 * (d.n_sym + 1));
         S.sq = ls;
         S.rsq = ls + d.n_sym + 1;
-        S.rtab = stage_copy(smem, off, d.rtab, rank_table_len(d));
+        S.rtab = stage_copy(smem, off, reinterpret_cast<const uint32_t *>(d.rtab),
+                            rank_table_bytes(d) / 4);
         if constexpr (KIND == K_AFF) {
             S.aff = stage_copy(smem, off, d.aff, d.n_sym);
             int16_t *lg = reinterpret_cast<int16_t *>(smem + off);
@@ -206,7 +208,8 @@ __device__ __forceinline__ int64_t locate(const SectorDesc &d, const Staged<T> &
         }
         if (d.rwords)
             return rank_find(d.rwords, d.n_rwords,
-                             colex_rank<W>(S.rtab, d.rcb, d.rnc, d.rnb, rep));
+                             colex_rank<W>(static_cast<const typename RankEntry<W>::type *>(S.rtab),
+                                           d.n_sites, d.n_up, d.rcb, d.rnc, rep));
         return hash_find<W>(d.hash, d.n_lines, (W)d.empty, rep);
     }
 }

@@ -327,22 +327,24 @@ __global__ __launch_bounds__(256) void k_hash_insert(const W *reps, uint64_t dim
 // are ascending and the colex rank preserves their order) writes its index
 // as the word's count.
 template <class W>
-__global__ __launch_bounds__(256) void k_rank_build(const W *reps, uint64_t dim, const uint64_t *T,
-                                                    int cb, int nc, int nb, uint2 *words) {
+__global__ __launch_bounds__(256) void k_rank_build(const W *reps, uint64_t dim,
+                                                    const typename RankEntry<W>::type *T, int N,
+                                                    int n_up, int cb, int nc, uint2 *words) {
     const uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= dim) return;
-    const uint64_t r = colex_rank<W>(T, cb, nc, nb, reps[i]);
+    const uint64_t r = colex_rank<W>(T, N, n_up, cb, nc, reps[i]);
     const uint64_t w = r >> 5;
     atomicOr(&words[w].y, 1u << (uint32_t)(r & 31));
-    if (i == 0 || (colex_rank<W>(T, cb, nc, nb, reps[i - 1]) >> 5) != w) words[w].x = (uint32_t)i;
+    if (i == 0 || (colex_rank<W>(T, N, n_up, cb, nc, reps[i - 1]) >> 5) != w)
+        words[w].x = (uint32_t)i;
 }
 
 // index of arbitrary states (-1 when absent)
 struct RankArgs {
     const uint2 *words;
     uint64_t n_words;   // 0: no rank index
-    const uint64_t *tab;
-    int cb, nc, nb;
+    const void *tab;
+    int cb, nc;
 };
 
 template <class W>
@@ -360,7 +362,9 @@ __global__ __launch_bounds__(256) void k_lookup(const uint64_t *states, int64_t 
             const uint64_t lo = s & ((1ull << nlo) - 1), hi = s >> nlo;
             r = (int64_t)lin[(1ull << nlo) + hi] + (int64_t)lin[lo];
         } else if (R.n_words) {
-            r = rank_find(R.words, R.n_words, colex_rank<W>(R.tab, R.cb, R.nc, R.nb, (W)s));
+            r = rank_find(R.words, R.n_words,
+                          colex_rank<W>(static_cast<const typename RankEntry<W>::type *>(R.tab),
+                                        N, n_up, R.cb, R.nc, (W)s));
         } else if (n_lines) {
             r = hash_find<W>(table, n_lines, empty, (W)s);
         }
@@ -553,20 +557,28 @@ int build_hash(xdg_basis_s *b) {
     return XDG_OK;
 }
 
-// Chunk tables of the colex rank: T[k][below][v] = sum over the set bits of
-// v, the i-th (from the bottom) at site p = k cb + q, of C(p, below + i);
-// sites beyond N contribute nothing.  cb is the widest chunk whose tables
-// stay within 32 KiB (they are staged in LDS by the apply kernels).
-void rank_tables(int N, int n_up, int &cb, int &nc, std::vector<uint64_t> &T) {
-    const int nb = n_up + 1;
-    for (cb = 8; cb > 1; --cb) {
-        nc = (N + cb - 1) / cb;
-        if ((((size_t)nc * nb) << cb) * 8 <= 32768) break;
-    }
-    nc = (N + cb - 1) / cb;
-    T.assign(((size_t)nc * nb) << cb, 0);
-    for (int k = 0; k < nc; ++k)
-        for (int below = 0; below < nb; ++below)
+// Chunk tables of the colex rank (the layout read by colex_rank): the entry
+// of chunk k, below set bits under it, chunk bits v is the sum over the set
+// bits of v, the i-th (from the bottom) at site p = k cb + q, of
+// C(p, below + i); sites beyond N contribute nothing.  32-bit states: four
+// chunks of 8 sites, rows only for below in [rank_lo, rank_hi], u32 entries.
+// Wider states: every row, the widest chunk whose table stays within 32 KiB
+// (it is staged in LDS by the apply kernels), u64 entries.
+int rank_rows(int N, int n_up, int cb, int nc, bool wide) {
+    if (wide) return nc * (n_up + 1);
+    int rows = 0;
+    for (int k = 0; k < nc; ++k) rows += rank_hi(n_up, cb, k) - rank_lo(N, n_up, cb, k) + 1;
+    return rows;
+}
+
+template <class E>
+void rank_tables(int N, int n_up, int cb, int nc, bool wide, std::vector<E> &T) {
+    T.assign((size_t)rank_rows(N, n_up, cb, nc, wide) << cb, 0);
+    size_t row = 0;
+    for (int k = 0; k < nc; ++k) {
+        const int lo = wide ? 0 : rank_lo(N, n_up, cb, k);
+        const int hi = wide ? n_up : rank_hi(n_up, cb, k);
+        for (int below = lo; below <= hi; ++below, ++row)
             for (uint32_t v = 0; v < (1u << cb); ++v) {
                 uint64_t r = 0;
                 int c = below;
@@ -576,8 +588,22 @@ void rank_tables(int N, int n_up, int &cb, int &nc, std::vector<uint64_t> &T) {
                     const int p = k * cb + q;
                     if (p < N) r += binomial(p, c);
                 }
-                T[(((size_t)k * nb + below) << cb) | v] = r;
+                T[(row << cb) | v] = (E)r;
             }
+    }
+}
+
+void rank_shape(int N, int n_up, bool wide, int &cb, int &nc) {
+    if (!wide) {
+        cb = RANK_CB32;
+        nc = RANK_NC32;
+        return;
+    }
+    for (cb = 8; cb > 1; --cb) {
+        nc = (N + cb - 1) / cb;
+        if (((size_t)rank_rows(N, n_up, cb, nc, true) << cb) * 8 <= 32768) break;
+    }
+    nc = (N + cb - 1) / cb;
 }
 
 uint64_t colex_rank_host(uint64_t s) {
@@ -600,21 +626,29 @@ int build_rank(xdg_basis_s *b) {
     const int slots = sizeof(W) == 4 ? 8 : 5;
     const double hash_bytes = 64.0 * std::ceil((double)dim / (slots * 0.5));
     if ((double)n_words * 8.0 > 4.0 * hash_bytes + 64.0 * (1 << 20)) return XDG_OK;
-    std::vector<uint64_t> T;
+    using E = typename RankEntry<W>::type;
+    std::vector<E> T;
     int cb = 0, nc = 0;
-    rank_tables(b->n_sites, b->n_up, cb, nc, T);
-    XDG_RETURN_IF(b->rtab.upload(T.data(), T.size() * 8));
+    rank_shape(b->n_sites, b->n_up, sizeof(W) == 8, cb, nc);
+    rank_tables<E>(b->n_sites, b->n_up, cb, nc, sizeof(W) == 8, T);
+    // the table read of the device rank must give the plain colex rank
+    if (colex_rank<W>(T.data(), b->n_sites, b->n_up, cb, nc, (W)last) != colex_rank_host(last)) {
+        set_error("internal: colex chunk tables disagree with the colex rank");
+        return XDG_EINVAL;
+    }
+    XDG_RETURN_IF(b->rtab.upload(T.data(), T.size() * sizeof(E)));
     XDG_RETURN_IF(b->rwords.alloc(8 * n_words));
     XDG_TRY_HIP(hipMemset(b->rwords.p, 0, 8 * n_words));
     const int block = 256;
     hipLaunchKernelGGL(k_rank_build<W>, dim3((unsigned)((dim + block - 1) / block)), dim3(block), 0,
-                       0, b->reps.as<W>(), dim, b->rtab.as<uint64_t>(), cb, nc, b->n_up + 1,
+                       0, b->reps.as<W>(), dim, b->rtab.as<E>(), b->n_sites, b->n_up, cb, nc,
                        b->rwords.as<uint2>());
     XDG_TRY_HIP(hipGetLastError());
     XDG_TRY_HIP(hipDeviceSynchronize());
     b->n_rwords = n_words;
     b->rank_cb = cb;
     b->rank_nc = nc;
+    b->rank_rows = rank_rows(b->n_sites, b->n_up, cb, nc, sizeof(W) == 8);
     return XDG_OK;
 }
 
@@ -721,8 +755,7 @@ int basis_lookup(xdg_basis_s *b, const uint64_t *d_states, int64_t n, int64_t *d
     const int block = 256;
     const unsigned grid = (unsigned)((n + block - 1) / block);
     const int u1 = b->plan.kind == K_U1;
-    const RankArgs R{b->rwords.as<uint2>(), b->n_rwords, b->rtab.as<uint64_t>(), b->rank_cb,
-                     b->rank_nc, b->n_up + 1};
+    const RankArgs R{b->rwords.as<uint2>(), b->n_rwords, b->rtab.p, b->rank_cb, b->rank_nc};
     if (b->wide) {
         const uint64_t empty = b->n_up == b->n_sites ? 0ull : ~0ull;
         hipLaunchKernelGGL(k_lookup<uint64_t>, dim3(grid), dim3(block), 0, st, d_states, n, d_idx,

@@ -61,19 +61,57 @@ __device__ __forceinline__ W rev_n(W t, int N) {
 // ------------------------------------------------------------- rank index --
 // Colex rank of a state among the states of its popcount: the i-th set bit
 // (from the bottom, i = 1, 2, ...) at site p contributes C(p, i).  It is
-// summed per chunk of cb sites from tables T[k][below][v] (below = set bits
-// under chunk k, v = the chunk's bits), so a rank costs nc table reads.
+// summed per chunk of cb sites from tables indexed by (chunk k, below = set
+// bits under the chunk, v = the chunk's bits).
+//  * 32-bit states: four chunks of 8 sites and 4-byte entries (C(32, 16) <
+//    2^32).  For states of n_up set bits on N sites, below lies in
+//    [rank_lo, rank_hi] for chunk k, and only those rows are stored, chunk
+//    after chunk; the four reads are independent and issued together.
+//  * wider states: nc chunks of cb sites, every row below = 0 .. n_up,
+//    8-byte entries, read chunk after chunk.
+constexpr int RANK_CB32 = 8, RANK_NC32 = 4;
+
+template <class W> struct RankEntry { using type = uint64_t; };
+template <> struct RankEntry<uint32_t> { using type = uint32_t; };
+
+__host__ __device__ inline int rank_lo(int N, int n_up, int cb, int k) {
+    const int a = n_up - (N - k * cb);
+    return a < 0 ? 0 : (a > n_up ? n_up : a);
+}
+__host__ __device__ inline int rank_hi(int n_up, int cb, int k) {
+    return k * cb < n_up ? k * cb : n_up;
+}
+
 template <class W>
-__device__ __forceinline__ uint64_t colex_rank(const uint64_t *T, int cb, int nc, int nb, W s) {
-    uint64_t r = 0;
-    uint32_t below = 0;
-    const uint32_t mask = (1u << cb) - 1;
-    for (int k = 0; k < nc; ++k) {
-        const uint32_t v = (uint32_t)((uint64_t)s >> (k * cb)) & mask;
-        r += T[(((uint32_t)k * nb + below) << cb) | v];
-        below += __popc(v);
+__host__ __device__ __forceinline__ uint64_t colex_rank(const typename RankEntry<W>::type *T,
+                                                        int N, int n_up, int cb, int nc, W s) {
+    if constexpr (sizeof(W) == 4) {
+        (void)cb;
+        (void)nc;
+        uint32_t e[RANK_NC32];
+        int row = 0;
+        uint32_t below = 0;
+#pragma unroll
+        for (int k = 0; k < RANK_NC32; ++k) {
+            const int lo = rank_lo(N, n_up, RANK_CB32, k);
+            const uint32_t v = (s >> (k * RANK_CB32)) & 0xFFu;
+            e[k] = T[((uint32_t)(row + (int)below - lo) << RANK_CB32) | v];
+            below += (uint32_t)__builtin_popcount(v);
+            row += rank_hi(n_up, RANK_CB32, k) - lo + 1;
+        }
+        return (uint64_t)((e[0] + e[1]) + (e[2] + e[3]));
+    } else {
+        const uint32_t nb = (uint32_t)n_up + 1;
+        const uint32_t mask = (1u << cb) - 1;
+        uint64_t r = 0;
+        uint32_t below = 0;
+        for (int k = 0; k < nc; ++k) {
+            const uint32_t v = (uint32_t)(s >> (k * cb)) & mask;
+            r += T[(((uint32_t)k * nb + below) << cb) | v];
+            below += (uint32_t)__builtin_popcountll(v);
+        }
+        return r;
     }
-    return r;
 }
 
 // Position of the state of colex rank r, or -1: words[r / 32] holds the

@@ -153,7 +153,7 @@ struct xdg_basis_s {
     xdg::DevBuf rwords;
     uint64_t n_rwords = 0;      // 0: the hash index is used
     xdg::DevBuf rtab;
-    int rank_cb = 0, rank_nc = 0;
+    int rank_cb = 0, rank_nc = 0, rank_rows = 0;
     int lin_nlo = 0, lin_nhi = 0;
     // sublattice tables on the device: t_src = u8 first bit of the source block
     // [n_sym][n_s], t_pid = u32 offset of its permutation tables in t_tperm
