@@ -36,22 +36,40 @@ __device__ __forceinline__ void gst(T *p, T v) {
 }
 
 // ------------------------------------------------------------ bit helpers --
-template <class W>
-__device__ __forceinline__ W rotr_n(W t, int a, int N) {
-    if constexpr (sizeof(W) == 4) {
-        if (N == 32) return __builtin_amdgcn_alignbit(t, t, (uint32_t)a);
-        if (a == 0) return t;
-        const W mask = (W(1) << N) - 1;
-        return ((t >> a) | (t << (N - a))) & mask;
+// Rotations of the low N bits of t by 0 <= a < N sites.  FULL: N is the
+// width of W (a plain rotate); otherwise N < width, t < 2^N and mask = 2^N - 1,
+// so that no shift reaches the width of W.
+template <class W, bool FULL>
+__host__ __device__ __forceinline__ W rot_r(W t, int a, int N, W mask) {
+    if constexpr (FULL) {
+        if constexpr (sizeof(W) == 4)
+            return __builtin_rotateright32(t, (uint32_t)a);
+        else
+            return __builtin_rotateright64(t, (uint64_t)a);
     } else {
-        if (a == 0) return t;
-        const W mask = N == 64 ? ~W(0) : ((W(1) << N) - 1);
         return ((t >> a) | (t << (N - a))) & mask;
+    }
+}
+template <class W, bool FULL>
+__host__ __device__ __forceinline__ W rot_l(W t, int a, int N, W mask) {
+    if constexpr (FULL) {
+        if constexpr (sizeof(W) == 4)
+            return __builtin_rotateleft32(t, (uint32_t)a);
+        else
+            return __builtin_rotateleft64(t, (uint64_t)a);
+    } else {
+        return ((t << a) | (t >> (N - a))) & mask;
     }
 }
 
 template <class W>
-__device__ __forceinline__ W rev_n(W t, int N) {
+__host__ __device__ __forceinline__ W rotr_n(W t, int a, int N) {
+    if (N == 8 * (int)sizeof(W)) return rot_r<W, true>(t, a, N, ~W(0));
+    return rot_r<W, false>(t, a, N, (W(1) << N) - 1);
+}
+
+template <class W>
+__host__ __device__ __forceinline__ W rev_n(W t, int N) {
     if constexpr (sizeof(W) == 4)
         return __builtin_bitreverse32(t) >> (32 - N);
     else
@@ -221,31 +239,42 @@ __device__ __forceinline__ void aff_search(const AffineElem *aff, int n_sym, int
 // reflection i -> a - i), the image under rotation a is rotr_N(t, a); read
 // from its top bit it is t read downward from site a - 1.  The smallest image
 // therefore begins with a longest run of zeros of t, so only the tops of the
-// maximal zero runs need a full comparison: y_k has bit p set iff sites
-// p, p-1, .., p-k+1 of t are all down, and y_{k+1} = y_k & rotl(z, k).  All
-// minimising rotations are among these candidates, so the first minimising
-// element and the number of minimisers (= |Stab|) come out exact.
-template <class W>
-__device__ __forceinline__ W rotl_n(W t, int k, int N) {
-    return rotr_n<W>(t, (N - k) % N, N);
-}
-
+// maximal zero runs need a full comparison.  With z = ~t, let y_m have bit p
+// set iff sites p, p-1, .., p-m+1 (cyclically) of t are all down: y_1 = z,
+// y_{m+n} = y_m & rotl(y_n, m).  Doubling gives y_1, y_2, y_4, ..; the
+// longest run L and y_L then follow by binary lifting (add the largest power
+// of two that keeps y nonzero), a fixed number of steps with no divergence.
+// All minimising rotations are among the set bits of y_L, so the first
+// minimising element and the number of minimisers (= |Stab|) come out exact.
+//
 // Scans the rotations of t; merges into (best, u, cnt) using gidx[a] as the
 // group index of rotation a.
-template <class W>
-__device__ __forceinline__ void ring_scan(W t, int N, const int16_t *gidx, W &best, int &u,
-                                          int &cnt) {
-    const W mask = N == (int)(8 * sizeof(W)) ? ~W(0) : ((W(1) << N) - 1);
+template <class W, bool FULL>
+__host__ __device__ __forceinline__ void ring_scan_t(W t, int N, const int16_t *gidx, W &best,
+                                                     int &u, int &cnt) {
+    constexpr int J = sizeof(W) == 4 ? 5 : 6;   // 2^J > the longest run < N
+    const W mask = FULL ? ~W(0) : ((W(1) << N) - 1);
     const W z = ~t & mask;
     W y;
     if (z == 0 || z == mask) {
         y = mask;                      // all rotations give the same image
     } else {
-        y = z;
-        for (int k = 1; k < N; ++k) {
-            const W y2 = y & rotl_n<W>(z, k, N);
-            if (y2 == 0) break;
-            y = y2;
+        W p[J];                        // p[j] = y_{2^j}
+        p[0] = z;
+#pragma unroll
+        for (int j = 1; j < J; ++j) {
+            const int h = 1 << (j - 1);
+            p[j] = h < N ? (p[j - 1] & rot_l<W, FULL>(p[j - 1], h, N, mask)) : W(0);
+        }
+        y = mask;                      // y_0
+        int L = 0;
+#pragma unroll
+        for (int j = J - 1; j >= 0; --j) {
+            const W c = y & rot_l<W, FULL>(p[j], L, N, mask);
+            if (c) {
+                y = c;
+                L += 1 << j;
+            }
         }
     }
     while (y) {
@@ -256,7 +285,7 @@ __device__ __forceinline__ void ring_scan(W t, int N, const int16_t *gidx, W &be
             p = __builtin_ctzll(y);
         y &= y - 1;
         const int a = p + 1 == N ? 0 : p + 1;
-        const W img = rotr_n<W>(t, a, N);
+        const W img = rot_r<W, FULL>(t, a, N, mask);
         const int g = gidx[a];
         if (img < best) {
             best = img;
@@ -269,11 +298,20 @@ __device__ __forceinline__ void ring_scan(W t, int N, const int16_t *gidx, W &be
     }
 }
 
+template <class W>
+__host__ __device__ __forceinline__ void ring_scan(W t, int N, const int16_t *gidx, W &best,
+                                                   int &u, int &cnt) {
+    if (N == 8 * (int)sizeof(W))
+        ring_scan_t<W, true>(t, N, gidx, best, u, cnt);
+    else
+        ring_scan_t<W, false>(t, N, gidx, best, u, cnt);
+}
+
 // ring = 1: rotations only; ring = 2: rotations and reflections.
 // gidx[a] (rotation a) and gidx[N + a] (reflection image rotr_N(rev_N(t), a)).
 template <class W>
-__device__ __forceinline__ void ring_search(const int16_t *gidx, int ring, int N, W t, W &best,
-                                            int &u, int &cnt) {
+__host__ __device__ __forceinline__ void ring_search(const int16_t *gidx, int ring, int N, W t,
+                                                     W &best, int &u, int &cnt) {
     best = ~W(0);
     u = 0x7fffffff;
     cnt = 0;
