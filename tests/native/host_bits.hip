@@ -1,0 +1,116 @@
+// Host-side checks of two integer building blocks of the apply and index
+// kernels, compiled from the library's own sources and run on the CPU:
+//  * the colex rank read from the chunk tables equals the plain colex rank
+//    (sum over the i-th set bit at site p of C(p, i)) for every N <= 64 and
+//    every n_up, on random states and the smallest and largest ones;
+//  * the ring representative search (longest zero run by doubling and
+//    binary lifting, then the candidate rotations) equals a scan of all N
+//    rotations (and N reflections) written with plain per-bit loops.
+// Prints "bad <count>" and exits nonzero on any mismatch.
+#include "basis.hip"
+
+#include <cstdio>
+#include <random>
+
+using namespace xdg;
+
+static uint64_t binom_plain(int n, int k) {
+    if (k < 0 || k > n) return 0;
+    unsigned __int128 r = 1;   // r = C(n - k + i, i) after step i; the product needs 128 bits
+    for (int i = 1; i <= k; ++i) r = r * (unsigned)(n - k + i) / (unsigned)i;
+    return (uint64_t)r;
+}
+
+static uint64_t colex_plain(uint64_t s) {
+    uint64_t r = 0;
+    int i = 0;
+    for (int p = 0; p < 64; ++p)
+        if ((s >> p) & 1) r += binom_plain(p, ++i);
+    return r;
+}
+
+template <class W>
+static int check_rank(int N, int n_up, std::mt19937_64 &g) {
+    using E = typename RankEntry<W>::type;
+    const bool wide = sizeof(W) == 8;
+    int cb = 0, nc = 0;
+    rank_shape(N, n_up, wide, cb, nc);
+    std::vector<E> T;
+    rank_tables<E>(N, n_up, cb, nc, wide, T);
+    int bad = 0;
+    std::vector<int> perm(N);
+    for (int it = 0; it < 300; ++it) {
+        for (int i = 0; i < N; ++i) perm[i] = i;
+        for (int i = 0; i < n_up; ++i) std::swap(perm[i], perm[i + (int)(g() % (uint64_t)(N - i))]);
+        uint64_t s = 0;
+        for (int i = 0; i < n_up; ++i) s |= 1ull << perm[i];
+        const uint64_t low = n_up ? (~0ull >> (64 - n_up)) : 0;
+        if (it == 0) s = low;
+        if (it == 1) s = low << (N - n_up);
+        if (colex_rank<W>(T.data(), N, n_up, cb, nc, (W)s) != colex_plain(s)) ++bad;
+    }
+    return bad;
+}
+
+static uint64_t rot_plain(uint64_t t, int a, int N) {   // site i -> i - a (cyclic)
+    uint64_t r = 0;
+    for (int i = 0; i < N; ++i)
+        if ((t >> i) & 1) r |= 1ull << ((i - a + N) % N);
+    return r;
+}
+
+static uint64_t rev_plain(uint64_t t, int N) {
+    uint64_t r = 0;
+    for (int i = 0; i < N; ++i)
+        if ((t >> i) & 1) r |= 1ull << (N - 1 - i);
+    return r;
+}
+
+template <class W>
+static int check_ring(int N, std::mt19937_64 &g) {
+    std::vector<int16_t> gidx(2 * N);
+    for (int a = 0; a < 2 * N; ++a) gidx[a] = (int16_t)((a * 7 + 3) % (2 * N));
+    int bad = 0;
+    for (int it = 0; it < 600; ++it) {
+        uint64_t t = g();
+        if (it % 3 == 1) t &= g();
+        if (it % 3 == 2) t |= g();
+        if (N < 64) t &= (1ull << N) - 1;
+        if (it == 0) t = 0;
+        if (it == 1) t = N < 64 ? (1ull << N) - 1 : ~0ull;
+        for (int ring = 1; ring <= 2; ++ring) {
+            W best;
+            int u, cnt;
+            ring_search<W>(gidx.data(), ring, N, (W)t, best, u, cnt);
+            uint64_t b = ~0ull;
+            int bu = 1 << 30, bc = 0;
+            for (int e = 0; e < ring * N; ++e) {
+                const uint64_t img = rot_plain(e < N ? t : rev_plain(t, N), e % N, N);
+                if (img < b) {
+                    b = img;
+                    bu = gidx[e];
+                    bc = 1;
+                } else if (img == b) {
+                    ++bc;
+                    bu = gidx[e] < bu ? gidx[e] : bu;
+                }
+            }
+            if ((uint64_t)best != b || u != bu || cnt != bc) ++bad;
+        }
+    }
+    return bad;
+}
+
+int main() {
+    std::mt19937_64 g(20250505);
+    int bad = 0;
+    for (int N = 1; N <= 64; ++N)
+        for (int n = 0; n <= N; ++n)
+            bad += N <= 32 ? check_rank<uint32_t>(N, n, g) : check_rank<uint64_t>(N, n, g);
+    for (int N = 2; N <= 64; ++N) {
+        if (N <= 32) bad += check_ring<uint32_t>(N, g);
+        bad += check_ring<uint64_t>(N, g);
+    }
+    printf("bad %d\n", bad);
+    return bad != 0;
+}
