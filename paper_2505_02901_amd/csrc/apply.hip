@@ -100,6 +100,9 @@ SectorDesc make_desc(const xdg_ham_s *h, bool single, const void *x, void *y) {
     d.bonds = single ? h->bonds_f.p : h->bonds_d.p;
     d.chi = single ? b->chi_f.p : b->chi_d.p;
     d.sqrtt = single ? b->sqrt_f.p : b->sqrt_d.p;
+    double jq = 0.0;
+    for (double j : h->jz) jq += 0.25 * j;
+    d.jz_quarter = jq;
     d.x = x;
     d.y = y;
     return d;

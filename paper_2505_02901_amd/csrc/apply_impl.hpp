@@ -74,6 +74,7 @@ struct SectorDesc {
     const void *bonds;           // BondD / BondF [n_bonds]
     const void *chi;             // double2 / float2 [n_sym]
     const void *sqrtt;           // T [2 (n_sym + 1)]: sqrt(c), then 1/sqrt(c)
+    double jz_quarter;           // (1/4) sum_b Jz_b: the diagonal of the all-aligned state
     const void *x;
     void *y;
 };
@@ -225,16 +226,13 @@ __device__ __forceinline__ void process_row(const SectorDesc &d, const Staged<A>
     const T *X = reinterpret_cast<const T *>(d.x);
     T *Y = reinterpret_cast<T *>(d.y);
     const int nb = d.n_bonds;
-    A diag = 0;
-    for (int b = 0; b < nb; ++b) {
-        const B bd = S.bonds[b];
-        const bool eq = ((s >> bd.i) & 1) == ((s >> bd.j) & 1);
-        diag += (eq ? A(0.25) : A(-0.25)) * bd.jz;
-    }
+    // Diagonal: sum_b Jz_b (+1/4 if the spins of b are equal, -1/4 if not)
+    // = (1/4) sum_b Jz_b - (1/2) sum over the unequal-spin bonds of Jz_b; the
+    // second sum is taken in the walk over those bonds below.
+    A junq = 0;
     A acc[NV * C];
-    const size_t base = ((size_t)row * nvec + v0) * C;
 #pragma unroll
-    for (int v = 0; v < NV * C; ++v) acc[v] = diag * (A)gld(X + base + v);
+    for (int v = 0; v < NV * C; ++v) acc[v] = 0;
     A rn = A(1);
     if constexpr (KIND != K_U1) rn = S.rsq[gld(d.stab + row)];
     auto term = [&](const B &bd) {
@@ -264,20 +262,22 @@ __device__ __forceinline__ void process_row(const SectorDesc &d, const Staged<A>
         }
     };
     if constexpr (KIND == K_AFF || KIND == K_U1) {
-        // Cheap searches: per group of 64 bonds, a mask of the bonds with
+        // Cheap searches: per group of 32 bonds, a mask of the bonds with
         // unequal spins, walked lowest first (the order of the plain bond
         // loop), so that a wave iterates over its lanes' active bonds only.
-        for (int b0 = 0; b0 < nb; b0 += 64) {
-            const int bn = nb - b0 < 64 ? nb - b0 : 64;
-            uint64_t act = 0;
+        for (int b0 = 0; b0 < nb; b0 += 32) {
+            const int bn = nb - b0 < 32 ? nb - b0 : 32;
+            uint32_t act = 0;
             for (int k = 0; k < bn; ++k) {
                 const B bd = S.bonds[b0 + k];
-                act |= (uint64_t)((uint32_t)((s >> bd.i) ^ (s >> bd.j)) & 1u) << k;
+                act |= (((uint32_t)(s >> bd.i) ^ (uint32_t)(s >> bd.j)) & 1u) << k;
             }
             while (act) {
-                const int b = b0 + __builtin_ctzll(act);
+                const int b = b0 + __builtin_ctz(act);
                 act &= act - 1;
-                term(S.bonds[b]);
+                const B bd = S.bonds[b];
+                junq += bd.jz;
+                term(bd);
             }
         }
     } else {
@@ -287,11 +287,15 @@ __device__ __forceinline__ void process_row(const SectorDesc &d, const Staged<A>
         for (int b = 0; b < nb; ++b) {
             const B bd = S.bonds[b];
             if (((s >> bd.i) & 1) == ((s >> bd.j) & 1)) continue;
+            junq += bd.jz;
             term(bd);
         }
     }
+    const size_t base = ((size_t)row * nvec + v0) * C;
+    const A diag = (A)d.jz_quarter - A(0.5) * junq;
 #pragma unroll
-    for (int v = 0; v < NV * C; ++v) gst(Y + base + v, (T)acc[v]);
+    for (int v = 0; v < NV * C; ++v)
+        gst(Y + base + v, (T)fmadd<A>(diag, (A)gld(X + base + v), acc[v]));
 }
 
 // count of the off-diagonal terms of a row that land in the block
