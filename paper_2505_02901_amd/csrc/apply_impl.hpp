@@ -207,10 +207,15 @@ __device__ __forceinline__ int64_t locate(const SectorDesc &d, const Staged<T> &
         } else {
             tab_search<W>(d.bytetab, d.n_bchunks, d.n_sym, t, rep, u, cnt);
         }
-        if (d.rwords)
-            return rank_find(d.rwords, d.n_rwords,
-                             colex_rank<W>(static_cast<const typename RankEntry<W>::type *>(S.rtab),
-                                           d.n_sites, d.n_up, d.rcb, d.rnc, rep));
+        if (d.rwords) {
+            const uint64_t r =
+                colex_rank<W>(static_cast<const typename RankEntry<W>::type *>(S.rtab), d.n_sites,
+                              d.n_up, d.rcb, d.rnc, rep);
+            if constexpr (sizeof(W) == 4)
+                return rank_find32(d.rwords, (uint32_t)d.n_rwords, (uint32_t)r);
+            else
+                return rank_find(d.rwords, d.n_rwords, r);
+        }
         return hash_find<W>(d.hash, d.n_lines, (W)d.empty, rep);
     }
 }
@@ -247,7 +252,10 @@ __device__ __forceinline__ void process_row(const SectorDesc &d, const Staged<A>
             ar = f * c.x;
             if constexpr (CPLX) ai = f * c.y;
         }
-        const size_t xb = ((size_t)idx * nvec + v0) * C;
+        // 32-bit states: positions below 2^31, one 32 x 32 -> 64-bit multiply-add
+        const size_t xb = sizeof(W) == 4
+                              ? (uint64_t)(uint32_t)idx * (uint32_t)(nvec * C) + (uint64_t)(v0 * C)
+                              : ((size_t)idx * nvec + v0) * C;
         // explicit fused multiply-adds: a complex kernel on a block with real
         // characters (ai = 0) rounds exactly like the real kernel
 #pragma unroll

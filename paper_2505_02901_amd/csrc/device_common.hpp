@@ -147,6 +147,18 @@ __device__ __forceinline__ int64_t rank_find(const uint2 *words, uint64_t n_word
     return ((bits >> b) & 1u) ? idx : -1;
 }
 
+// The same for ranks and positions below 2^31 (32-bit states: every colex
+// rank is below C(32, 16)), in 32-bit arithmetic.
+__device__ __forceinline__ int32_t rank_find32(const uint2 *words, uint32_t n_words, uint32_t r) {
+    const uint32_t w = r >> 5;
+    if (w >= n_words) return -1;
+    const uint64_t e = gld(reinterpret_cast<const uint64_t *>(words) + w);
+    const uint32_t cnt = (uint32_t)e, bits = (uint32_t)(e >> 32);
+    const uint32_t b = r & 31u;
+    const int32_t idx = (int32_t)(cnt + __popc(bits & ((1u << b) - 1u)));
+    return ((bits >> b) & 1u) ? idx : -1;
+}
+
 // ------------------------------------------------------------- hash index --
 // Open addressing over 64-byte lines; a lookup reads one line in the common
 // case.  A line holds 8 (key u32, value u32) or 5 (key u64, value u32) pairs.
@@ -240,16 +252,18 @@ __device__ __forceinline__ void aff_search(const AffineElem *aff, int n_sym, int
 // from its top bit it is t read downward from site a - 1.  The smallest image
 // therefore begins with a longest run of zeros of t, so only the tops of the
 // maximal zero runs need a full comparison.  With z = ~t, let y_m have bit p
-// set iff sites p, p-1, .., p-m+1 (cyclically) of t are all down: y_1 = z,
-// y_{m+n} = y_m & rotl(y_n, m).  Doubling gives y_1, y_2, y_4, ..; the
-// longest run L and y_L then follow by binary lifting (add the largest power
-// of two that keeps y nonzero), a fixed number of steps with no divergence.
-// All minimising rotations are among the set bits of y_L, so the first
-// minimising element and the number of minimisers (= |Stab|) come out exact.
+// set iff sites p, p-1, .., p-m+1 (cyclically) of t are all down: y_1 = z and
+// y_{m+n} = y_m & rotl(y_n, m).  Doubling gives p_j = y_{2^j}; the longest
+// run L and y_L then follow by binary lifting, y <- p_j & rotl(y, 2^j) while
+// that stays nonzero, for j from high to low: a fixed number of steps, every
+// rotation by a constant, no divergence.  All minimising rotations are among
+// the set bits of y_L, so the first minimising element and the number of
+// minimisers (= |Stab|) come out exact.
 //
 // Scans the rotations of t; merges into (best, u, cnt) using gidx[a] as the
-// group index of rotation a.
-template <class W, bool FULL>
+// group index of rotation a.  FIRST: (best, u, cnt) hold nothing yet and are
+// set from the first candidate.
+template <class W, bool FULL, bool FIRST>
 __host__ __device__ __forceinline__ void ring_scan_t(W t, int N, const int16_t *gidx, W &best,
                                                      int &u, int &cnt) {
     constexpr int J = sizeof(W) == 4 ? 5 : 6;   // 2^J > the longest run < N
@@ -264,30 +278,27 @@ __host__ __device__ __forceinline__ void ring_scan_t(W t, int N, const int16_t *
 #pragma unroll
         for (int j = 1; j < J; ++j) {
             const int h = 1 << (j - 1);
-            p[j] = h < N ? (p[j - 1] & rot_l<W, FULL>(p[j - 1], h, N, mask)) : W(0);
+            p[j] = (FULL || h < N) ? (p[j - 1] & rot_l<W, FULL>(p[j - 1], h, N, mask)) : W(0);
         }
         y = mask;                      // y_0
-        int L = 0;
 #pragma unroll
         for (int j = J - 1; j >= 0; --j) {
-            const W c = y & rot_l<W, FULL>(p[j], L, N, mask);
-            if (c) {
-                y = c;
-                L += 1 << j;
+            const int h = 1 << j;
+            if (FULL || h < N) {
+                const W c = p[j] & rot_l<W, FULL>(y, h, N, mask);
+                y = c ? c : y;
             }
         }
     }
-    while (y) {
-        int p;
-        if constexpr (sizeof(W) == 4)
-            p = __builtin_ctz(y);
-        else
-            p = __builtin_ctzll(y);
-        y &= y - 1;
-        const int a = p + 1 == N ? 0 : p + 1;
+    auto take = [&](int pos, bool first) {
+        const int a = pos + 1 == N ? 0 : pos + 1;
         const W img = rot_r<W, FULL>(t, a, N, mask);
         const int g = gidx[a];
-        if (img < best) {
+        if (first) {
+            best = img;
+            u = g;
+            cnt = 1;
+        } else if (img < best) {
             best = img;
             u = g;
             cnt = 1;
@@ -295,16 +306,30 @@ __host__ __device__ __forceinline__ void ring_scan_t(W t, int N, const int16_t *
             ++cnt;
             u = g < u ? g : u;
         }
+    };
+    auto ctz = [](W v) -> int {
+        if constexpr (sizeof(W) == 4)
+            return __builtin_ctz(v);
+        else
+            return __builtin_ctzll(v);
+    };
+    if constexpr (FIRST) {             // y has at least one bit
+        take(ctz(y), true);
+        y &= y - 1;
+    }
+    while (y) {
+        take(ctz(y), false);
+        y &= y - 1;
     }
 }
 
-template <class W>
+template <class W, bool FIRST>
 __host__ __device__ __forceinline__ void ring_scan(W t, int N, const int16_t *gidx, W &best,
                                                    int &u, int &cnt) {
     if (N == 8 * (int)sizeof(W))
-        ring_scan_t<W, true>(t, N, gidx, best, u, cnt);
+        ring_scan_t<W, true, FIRST>(t, N, gidx, best, u, cnt);
     else
-        ring_scan_t<W, false>(t, N, gidx, best, u, cnt);
+        ring_scan_t<W, false, FIRST>(t, N, gidx, best, u, cnt);
 }
 
 // ring = 1: rotations only; ring = 2: rotations and reflections.
@@ -312,11 +337,8 @@ __host__ __device__ __forceinline__ void ring_scan(W t, int N, const int16_t *gi
 template <class W>
 __host__ __device__ __forceinline__ void ring_search(const int16_t *gidx, int ring, int N, W t,
                                                      W &best, int &u, int &cnt) {
-    best = ~W(0);
-    u = 0x7fffffff;
-    cnt = 0;
-    ring_scan<W>(t, N, gidx, best, u, cnt);
-    if (ring == 2) ring_scan<W>(rev_n<W>(t, N), N, gidx + N, best, u, cnt);
+    ring_scan<W, true>(t, N, gidx, best, u, cnt);
+    if (ring == 2) ring_scan<W, false>(rev_n<W>(t, N), N, gidx + N, best, u, cnt);
 }
 
 // Representative test for enumeration: false as soon as some image is smaller.
