@@ -103,6 +103,11 @@ SectorDesc make_desc(const xdg_ham_s *h, bool single, const void *x, void *y) {
     double jq = 0.0;
     for (double j : h->jz) jq += 0.25 * j;
     d.jz_quarter = jq;
+    d.ring_bonds = h->n_bonds == b->n_sites;
+    for (int i = 0; i < h->n_bonds && d.ring_bonds; ++i) {
+        const int p = h->sites[2 * i], q = h->sites[2 * i + 1], r = (i + 1) % b->n_sites;
+        d.ring_bonds = (p == i && q == r) || (p == r && q == i);
+    }
     d.x = x;
     d.y = y;
     return d;

@@ -75,6 +75,7 @@ struct SectorDesc {
     const void *chi;             // double2 / float2 [n_sym]
     const void *sqrtt;           // T [2 (n_sym + 1)]: sqrt(c), then 1/sqrt(c)
     double jz_quarter;           // (1/4) sum_b Jz_b: the diagonal of the all-aligned state
+    int ring_bonds;              // 1: n_bonds = n_sites and bond b joins sites b and b + 1 mod N
     const void *x;
     void *y;
 };
@@ -247,7 +248,7 @@ __device__ __forceinline__ void process_row(const SectorDesc &d, const Staged<A>
         if (idx < 0) return;
         A ar = bd.h, ai = 0;
         if constexpr (KIND != K_U1) {
-            const A f = bd.h * S.sq[cnt] * rn;
+            const A f = bd.h * S.sq[cnt];   // times 1/sqrt|Stab r| once per row
             const auto c = S.chi[u];
             ar = f * c.x;
             if constexpr (CPLX) ai = f * c.y;
@@ -273,12 +274,18 @@ __device__ __forceinline__ void process_row(const SectorDesc &d, const Staged<A>
         // Cheap searches: per group of 32 bonds, a mask of the bonds with
         // unequal spins, walked lowest first (the order of the plain bond
         // loop), so that a wave iterates over its lanes' active bonds only.
+        // Bonds b = (b, b + 1 mod N) in order: bit b of s ^ rotr(s, 1).
+        const W walls = d.ring_bonds ? (s ^ rotr_n<W>(s, 1, d.n_sites)) : W(0);
         for (int b0 = 0; b0 < nb; b0 += 32) {
             const int bn = nb - b0 < 32 ? nb - b0 : 32;
             uint32_t act = 0;
-            for (int k = 0; k < bn; ++k) {
-                const B bd = S.bonds[b0 + k];
-                act |= (((uint32_t)(s >> bd.i) ^ (uint32_t)(s >> bd.j)) & 1u) << k;
+            if (d.ring_bonds) {
+                act = (uint32_t)(walls >> b0) & (bn == 32 ? ~0u : ((1u << bn) - 1u));
+            } else {
+                for (int k = 0; k < bn; ++k) {
+                    const B bd = S.bonds[b0 + k];
+                    act |= (((uint32_t)(s >> bd.i) ^ (uint32_t)(s >> bd.j)) & 1u) << k;
+                }
             }
             while (act) {
                 const int b = b0 + __builtin_ctz(act);
@@ -302,8 +309,10 @@ __device__ __forceinline__ void process_row(const SectorDesc &d, const Staged<A>
     const size_t base = ((size_t)row * nvec + v0) * C;
     const A diag = (A)d.jz_quarter - A(0.5) * junq;
 #pragma unroll
-    for (int v = 0; v < NV * C; ++v)
-        gst(Y + base + v, (T)fmadd<A>(diag, (A)gld(X + base + v), acc[v]));
+    for (int v = 0; v < NV * C; ++v) {
+        const A off = KIND != K_U1 ? rn * acc[v] : acc[v];
+        gst(Y + base + v, (T)fmadd<A>(diag, (A)gld(X + base + v), off));
+    }
 }
 
 // count of the off-diagonal terms of a row that land in the block

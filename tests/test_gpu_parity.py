@@ -205,6 +205,29 @@ def test_apply_other_search_kinds(X, search, flags):
         assert rel_err(y1, y_or) < TOL64
 
 
+def test_ring_bond_order(X):
+    # a ring whose bonds are listed in order (b, b + 1 mod N) takes the
+    # domain-wall mask s ^ rotr(s, 1); reversed pairs take it too, a shuffled
+    # list walks the bonds one by one: all give the oracle's y, and the first
+    # two give the same bits
+    for m in (W.chain_model(20, l=3), W.chain_model(18), W.chain_model(36, n_up=3, l=5)):
+        basis = oracle_basis(m)
+        b = X.Basis.from_model(m)
+        x = W.random_vector(17, len(basis), 1, kind="gauss", complex_=True)
+        y_or = oracle.apply(m, basis, x)
+        sites = np.asarray(m.sites, dtype=np.int32).reshape(-1, 2)
+        jz = np.asarray(m.jz, dtype=np.float64)
+        jxy = np.asarray(m.jxy, dtype=np.float64)
+        order = np.random.default_rng(5).permutation(len(jz))
+        ys = []
+        for st, z, j in ((sites, jz, jxy), (sites[:, ::-1].copy(), jz, jxy),
+                         (sites[order].copy(), jz[order].copy(), jxy[order].copy())):
+            H = X.Hamiltonian(b, st, z, j)
+            ys.append(gpu_apply(X, H, x, torch.complex128))
+            assert rel_err(ys[-1], y_or) < TOL64, m.name
+        assert np.array_equal(ys[0], ys[1])
+
+
 def test_fp32_accumulation_modes(X):
     # FP32 vectors: by default the row is accumulated in FP64 and rounded once,
     # so y agrees with the exact product of the FP32-rounded x to one FP32
