@@ -89,8 +89,7 @@ SectorDesc make_desc(const xdg_ham_s *h, bool single, const void *x, void *y) {
     d.mintop = b->t_mintop.as<uint16_t>();
     d.cand_off = b->t_candoff.as<uint32_t>();
     d.cand_list = b->t_candlist.as<uint16_t>();
-    d.srcoff = b->t_src.as<uint8_t>();
-    d.tpoff = b->t_pid.as<uint32_t>();
+    d.sp = b->t_pid.as<uint32_t>();
     d.tperm = b->t_tperm.as<uint16_t>();
     d.n_s = b->plan.sub.n_s;
     d.m = b->plan.sub.m;

@@ -66,8 +66,7 @@ struct SectorDesc {
     const uint16_t *mintop;
     const uint32_t *cand_off;
     const uint16_t *cand_list;
-    const uint8_t *srcoff;
-    const uint32_t *tpoff;
+    const uint32_t *sp;
     const uint16_t *tperm;
     int n_s, m, pb, n_perm;
     uint32_t n_cand;
@@ -100,7 +99,7 @@ __host__ __device__ inline size_t a16(size_t x) { return (x + 15) & ~(size_t)15;
 __host__ __device__ inline size_t sub_table_bytes(const SectorDesc &d) {
     const size_t NV = (size_t)d.n_s << d.m;
     return a16(2 * NV) + a16(4 * (NV + 1)) + a16(2 * (size_t)d.n_cand) +
-           a16((size_t)d.n_sym * d.n_s) + a16(4 * (size_t)d.n_sym * d.n_s) +
+           a16(4 * (size_t)d.n_sym * d.n_s) +
            a16(2 * (size_t)d.n_perm * 2 * ((size_t)1 << d.pb));
 }
 
@@ -151,7 +150,7 @@ __device__ inline void stage(const SectorDesc &d, unsigned char *smem, Staged<T>
     using T2 = typename Vec2<T>::type;
     size_t off = 0;
     S.bonds = stage_copy(smem, off, reinterpret_cast<const B *>(d.bonds), d.n_bonds);
-    S.sub = SubCtx{d.mintop, d.cand_off, d.cand_list, d.srcoff, d.tpoff, d.tperm, d.n_s, d.m, d.pb};
+    S.sub = SubCtx{d.mintop, d.cand_off, d.cand_list, d.sp, d.tperm, d.n_s, d.m, d.pb};
     if constexpr (KIND != K_U1) {
         S.chi = stage_copy(smem, off, reinterpret_cast<const T2 *>(d.chi), d.n_sym);
         const T *ls = stage_copy(smem, off, reinterpret_cast<const T *>(d.sqrtt), 2 * (d.n_sym + 1));
@@ -173,8 +172,7 @@ __device__ inline void stage(const SectorDesc &d, unsigned char *smem, Staged<T>
                 S.sub.mintop = stage_copy(smem, off, d.mintop, NV);
                 S.sub.cand_off = stage_copy(smem, off, d.cand_off, NV + 1);
                 S.sub.cand_list = stage_copy(smem, off, d.cand_list, d.n_cand);
-                S.sub.srcoff = stage_copy(smem, off, d.srcoff, (size_t)d.n_sym * d.n_s);
-                S.sub.tpoff = stage_copy(smem, off, d.tpoff, (size_t)d.n_sym * d.n_s);
+                S.sub.sp = stage_copy(smem, off, d.sp, (size_t)d.n_sym * d.n_s);
                 S.sub.tperm = stage_copy(smem, off, d.tperm, (size_t)d.n_perm * 2 * ((size_t)1 << d.pb));
             }
         }

@@ -140,8 +140,7 @@ struct EnumArgs {
     const uint16_t *mintop;
     const uint32_t *cand_off;
     const uint16_t *cand_list;
-    const uint8_t *srcoff;
-    const uint32_t *tpoff;
+    const uint32_t *sp;
     const uint16_t *tperm;
     int n_s, m, pb, n_perm;
     uint32_t n_cand;
@@ -153,7 +152,7 @@ __global__ __launch_bounds__(256) void k_enum(EnumArgs<W> A) {
     extern __shared__ __align__(16) unsigned char smem[];
     const double2 *chi = A.chi;
     const AffineElem *aff = A.aff;
-    SubCtx C{A.mintop, A.cand_off, A.cand_list, A.srcoff, A.tpoff, A.tperm, A.n_s, A.m, A.pb};
+    SubCtx C{A.mintop, A.cand_off, A.cand_list, A.sp, A.tperm, A.n_s, A.m, A.pb};
     if constexpr (KIND != K_U1) {
         double2 *lchi = reinterpret_cast<double2 *>(smem);
         size_t off = align16(sizeof(double2) * A.n_sym);
@@ -177,22 +176,16 @@ __global__ __launch_bounds__(256) void k_enum(EnumArgs<W> A) {
                 for (uint32_t e = threadIdx.x; e < A.n_cand; e += blockDim.x) lcl[e] = A.cand_list[e];
                 off = align16(off + 2 * (size_t)A.n_cand);
                 const uint32_t GS = (uint32_t)A.n_sym * A.n_s;
-                uint8_t *lsrc = reinterpret_cast<uint8_t *>(smem + off);
-                off = align16(off + GS);
-                uint32_t *lpid = reinterpret_cast<uint32_t *>(smem + off);
+                uint32_t *lsp = reinterpret_cast<uint32_t *>(smem + off);
                 off = align16(off + 4 * (size_t)GS);
                 uint16_t *ltp = reinterpret_cast<uint16_t *>(smem + off);
                 const uint32_t TP = (uint32_t)A.n_perm * 2u << A.pb;
-                for (uint32_t e = threadIdx.x; e < GS; e += blockDim.x) {
-                    lsrc[e] = A.srcoff[e];
-                    lpid[e] = A.tpoff[e];
-                }
+                for (uint32_t e = threadIdx.x; e < GS; e += blockDim.x) lsp[e] = A.sp[e];
                 for (uint32_t e = threadIdx.x; e < TP; e += blockDim.x) ltp[e] = A.tperm[e];
                 C.mintop = lmt;
                 C.cand_off = lco;
                 C.cand_list = lcl;
-                C.srcoff = lsrc;
-                C.tpoff = lpid;
+                C.sp = lsp;
                 C.tperm = ltp;
             }
         }
@@ -436,8 +429,7 @@ int enumerate(xdg_basis_s *b, DevBuf &binom_d) {
     A.mintop = b->t_mintop.as<uint16_t>();
     A.cand_off = b->t_candoff.as<uint32_t>();
     A.cand_list = b->t_candlist.as<uint16_t>();
-    A.srcoff = b->t_src.as<uint8_t>();
-    A.tpoff = b->t_pid.as<uint32_t>();
+    A.sp = b->t_pid.as<uint32_t>();
     A.tperm = b->t_tperm.as<uint16_t>();
     A.n_s = b->plan.sub.n_s;
     A.m = b->plan.sub.m;
@@ -459,7 +451,7 @@ int enumerate(xdg_basis_s *b, DevBuf &binom_d) {
             const size_t NV = (size_t)A.n_s << A.m;
             const size_t GS = (size_t)A.n_sym * A.n_s;
             size_t need = align16(2 * NV) + align16(4 * (NV + 1)) + align16(2 * (size_t)A.n_cand) +
-                          align16(GS) + align16(4 * GS) +
+                          align16(4 * GS) +
                           align16(2 * ((size_t)A.n_perm * 2 << A.pb));
             if (lds + need <= lds_limit()) {
                 A.stage_sub = 1;
@@ -712,15 +704,21 @@ int basis_build_device(xdg_basis_s *b) {
             XDG_RETURN_IF(b->t_ring.upload(P.ring_gidx.data(), P.ring_gidx.size() * 2));
     }
     if (P.kind == K_SUB) {
-        // device form: the first bit of the source block, and the offset of
-        // the block permutation's tables in tperm
-        const int E = 1 << P.sub.pb;
-        std::vector<uint8_t> so(P.sub.src.size());
-        std::vector<uint32_t> to(P.sub.pid.size());
-        for (size_t e = 0; e < so.size(); ++e) so[e] = (uint8_t)(P.sub.src[e] * P.sub.m);
-        for (size_t e = 0; e < to.size(); ++e) to[e] = (uint32_t)P.sub.pid[e] * 2u * (uint32_t)E;
-        XDG_RETURN_IF(b->t_src.upload(so.data(), so.size()));
-        XDG_RETURN_IF(b->t_pid.upload(to.data(), to.size() * 4));
+        // device form, one word per (element, block): the offset of the block
+        // permutation's tables in tperm, shifted left by 8, or'ed with the
+        // first bit of the source block
+        const uint64_t E = 1ull << P.sub.pb;
+        std::vector<uint32_t> sp(P.sub.pid.size());
+        for (size_t e = 0; e < sp.size(); ++e) {
+            const uint64_t to = (uint64_t)P.sub.pid[e] * 2u * E;
+            const uint32_t so = (uint32_t)(P.sub.src[e] * P.sub.m);
+            if (to >= (1ull << 24) || so > 255u) {
+                set_error("sublattice tables too large for their packed offsets");
+                return XDG_EINVAL;
+            }
+            sp[e] = (uint32_t)(to << 8) | so;
+        }
+        XDG_RETURN_IF(b->t_pid.upload(sp.data(), sp.size() * 4));
         XDG_RETURN_IF(b->t_tperm.upload(P.sub.tperm.data(), P.sub.tperm.size() * 2));
         XDG_RETURN_IF(b->t_mintop.upload(P.sub.mintop.data(), P.sub.mintop.size() * 2));
         XDG_RETURN_IF(b->t_candoff.upload(P.sub.cand_off.data(), P.sub.cand_off.size() * 4));

@@ -375,8 +375,8 @@ struct SubCtx {
     const uint16_t *mintop;    // [n_s][V]
     const uint32_t *cand_off;  // [n_s*V + 1]
     const uint16_t *cand_list;
-    const uint8_t *srcoff;     // [n_sym][n_s] first bit of the block of t feeding block a
-    const uint32_t *tpoff;     // [n_sym][n_s] offset in tperm of that block's tables
+    const uint32_t *sp;        // [n_sym][n_s]: (offset in tperm of the tables of the block
+                               // permutation feeding block a) << 8 | first bit of its source block
     const uint16_t *tperm;     // [n_perm][2][E]
     int n_s, m, pb;            // E = 1 << pb
 };
@@ -386,15 +386,39 @@ __device__ __forceinline__ uint32_t chunk_of(W t, int k, int m, uint32_t vmask) 
     return (uint32_t)(t >> (k * m)) & vmask;
 }
 
-// image bits of block a of g.t (two half-chunk lookups)
+// image bits of a block of g.t from its packed entry w = sp[g][a] (two
+// half-chunk lookups)
 template <class W>
-__device__ __forceinline__ uint32_t sub_block(const SubCtx &C, const uint8_t *so,
-                                              const uint32_t *to, int a, W t, uint32_t vmask) {
-    const uint32_t v = (uint32_t)(t >> so[a]) & vmask;
-    const uint16_t *tp = C.tperm + to[a];
+__device__ __forceinline__ uint32_t sub_block(const SubCtx &C, uint32_t w, W t, uint32_t vmask) {
+    const uint32_t v = (uint32_t)(t >> (w & 0xFFu)) & vmask;
+    const uint16_t *tp = C.tperm + (w >> 8);
     const uint32_t lo = (1u << C.pb) - 1;
     return (uint32_t)tp[v & lo] | tp[lo + 1 + (v >> C.pb)];
 }
+
+// the n_s packed entries of element g; four blocks come in one 16-byte read
+template <int NS>
+struct SubEntries {
+    uint32_t w[NS > 0 ? NS : 1];
+    const uint32_t *p;
+    __device__ __forceinline__ SubEntries(const SubCtx &C, int g, int ns) {
+        p = C.sp + g * ns;
+        if constexpr (NS == 4) {
+            typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
+            const u32x4 q = *reinterpret_cast<const u32x4 *>(p);
+            w[0] = q.x;
+            w[1] = q.y;
+            w[2] = q.z;
+            w[3] = q.w;
+        }
+    }
+    __device__ __forceinline__ uint32_t operator[](int a) const {
+        if constexpr (NS == 4)
+            return w[a];
+        else
+            return p[a];
+    }
+};
 
 // NS > 0: the number of blocks is a compile-time constant (loops unrolled);
 // NS = 0: taken from C.n_s.
@@ -419,15 +443,14 @@ __device__ __forceinline__ void sub_search(const SubCtx &C, W t, W &best, int &u
         const uint32_t q1 = C.cand_off[e + 1];
         for (uint32_t q = C.cand_off[e]; q < q1; ++q) {
             const int g = C.cand_list[q];
-            const uint8_t *so = C.srcoff + g * ns;
-            const uint32_t *to = C.tpoff + g * ns;
+            const SubEntries<NS> ent(C, g, ns);
             // blocks from the top down; while the image agrees with the best
             // one so far, each block is compared with the best one's block
             W img = (W)mt << (top * m);
             bool eq = true, lose = false;
 #pragma unroll
             for (int a = top - 1; a >= 0; --a) {
-                const uint32_t v = sub_block<W>(C, so, to, a, t, vmask);
+                const uint32_t v = sub_block<W>(C, ent[a], t, vmask);
                 img |= (W)v << (a * m);
                 if (eq) {
                     const uint32_t bb = (uint32_t)(best >> (a * m)) & vmask;
@@ -468,11 +491,10 @@ __device__ __forceinline__ bool sub_is_rep(const SubCtx &C, W s, const double2 *
         const uint32_t q1 = C.cand_off[e + 1];
         for (uint32_t q = C.cand_off[e]; q < q1; ++q) {
             const int g = C.cand_list[q];
-            const uint8_t *so = C.srcoff + g * ns;
-            const uint32_t *to = C.tpoff + g * ns;
+            const uint32_t *sp = C.sp + g * ns;
             int cmp = 0;   // -1: image < s, +1: image > s
             for (int a = top - 1; a >= 0; --a) {
-                const uint32_t v = sub_block<W>(C, so, to, a, s, vmask);
+                const uint32_t v = sub_block<W>(C, sp[a], s, vmask);
                 const uint32_t sv = chunk_of<W>(s, a, m, vmask);
                 if (v != sv) {
                     cmp = v < sv ? -1 : 1;

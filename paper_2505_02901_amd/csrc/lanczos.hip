@@ -83,10 +83,12 @@ __global__ __launch_bounds__(RB) void k_update(T *w, const T *v, const T *vprev,
     __shared__ double sh[RB];
     double acc = 0.0;
     const uint64_t stride = (uint64_t)gridDim.x * RB;
+    // cols divides RB, so every scalar of this thread is in column threadIdx.x % cols
+    const int vec = (int)(threadIdx.x % cols) / C;
+    const double a = alpha[vec], b = vprev ? beta[vec] : 0.0;
     for (uint64_t q = (uint64_t)blockIdx.x * RB + threadIdx.x; q < n; q += stride) {
-        const int vec = (int)(q % cols) / C;
-        double x = (double)w[q] - alpha[vec] * (double)v[q];
-        if (vprev) x -= beta[vec] * (double)vprev[q];
+        double x = (double)w[q] - a * (double)v[q];
+        if (vprev) x -= b * (double)vprev[q];
         const T r = (T)x;
         w[q] = r;
         acc += (double)r * (double)r;
@@ -101,10 +103,10 @@ template <class T>
 __global__ __launch_bounds__(RB) void k_scale(const T *src, T *dst, uint64_t n, int cols, int C,
                                               const double *beta) {
     const uint64_t stride = (uint64_t)gridDim.x * RB;
-    for (uint64_t q = (uint64_t)blockIdx.x * RB + threadIdx.x; q < n; q += stride) {
-        const double bt = beta[(int)(q % cols) / C];
+    // cols divides RB, so every scalar of this thread is in column threadIdx.x % cols
+    const double bt = beta[(int)(threadIdx.x % cols) / C];
+    for (uint64_t q = (uint64_t)blockIdx.x * RB + threadIdx.x; q < n; q += stride)
         dst[q] = bt > 0.0 ? (T)((double)src[q] / bt) : T(0);
-    }
 }
 
 __global__ void k_step_end(int *jdev, double *prev_beta, const double *cur_beta, int nv) {

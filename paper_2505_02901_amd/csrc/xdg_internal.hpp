@@ -155,9 +155,9 @@ struct xdg_basis_s {
     xdg::DevBuf rtab;
     int rank_cb = 0, rank_nc = 0, rank_rows = 0;
     int lin_nlo = 0, lin_nhi = 0;
-    // sublattice tables on the device: t_src = u8 first bit of the source block
-    // [n_sym][n_s], t_pid = u32 offset of its permutation tables in t_tperm
-    xdg::DevBuf t_src, t_pid, t_tperm, t_mintop, t_candoff, t_candlist, t_bytes, t_aff, t_ring;
+    // sublattice tables on the device: t_pid = u32 [n_sym][n_s], the offset of
+    // the block permutation's tables in t_tperm << 8 | first bit of the source block
+    xdg::DevBuf t_pid, t_tperm, t_mintop, t_candoff, t_candlist, t_bytes, t_aff, t_ring;
     xdg::DevBuf chi_d;          // double2 [n_sym]
     xdg::DevBuf chi_f;          // float2 [n_sym]
     xdg::DevBuf sqrt_d;         // double [n_sym+1] sqrt(c), then [n_sym+1] 1/sqrt(c)
