@@ -179,18 +179,23 @@ __device__ inline void stage(const SectorDesc &d, unsigned char *smem, Staged<T>
     }
 }
 
+// Positions of 32-bit states are below C(32, 16) < 2^31: 32-bit indices.
+template <class W> struct IndexT { using type = int64_t; };
+template <> struct IndexT<uint32_t> { using type = int32_t; };
+
 // Locate the representative of t and its index; returns -1 when the orbit
 // is not in the block.  On success writes u and |Stab(s)|.
 template <class W, int KIND, class T>
-__device__ __forceinline__ int64_t locate(const SectorDesc &d, const Staged<T> &S, W t, int &u,
-                                          int &cnt) {
+__device__ __forceinline__ typename IndexT<W>::type locate(const SectorDesc &d, const Staged<T> &S,
+                                                           W t, int &u, int &cnt) {
+    using I = typename IndexT<W>::type;
     if constexpr (KIND == K_U1) {
         const uint64_t lo = (uint64_t)t & ((1ull << d.nlo) - 1);
         const uint64_t hi = (uint64_t)t >> d.nlo;
         const uint32_t *lin = d.lin;
         u = 0;
         cnt = 1;
-        return (int64_t)gld(lin + (1ull << d.nlo) + hi) + (int64_t)gld(lin + lo);
+        return (I)((int64_t)gld(lin + (1ull << d.nlo) + hi) + (int64_t)gld(lin + lo));
     } else {
         W rep;
         if constexpr (KIND == K_AFF) {
@@ -215,7 +220,7 @@ __device__ __forceinline__ int64_t locate(const SectorDesc &d, const Staged<T> &
             else
                 return rank_find(d.rwords, d.n_rwords, r);
         }
-        return hash_find<W>(d.hash, d.n_lines, (W)d.empty, rep);
+        return (I)hash_find<W>(d.hash, d.n_lines, (W)d.empty, rep);
     }
 }
 
@@ -242,7 +247,7 @@ __device__ __forceinline__ void process_row(const SectorDesc &d, const Staged<A>
     auto term = [&](const B &bd) {
         const W t = s ^ ((W(1) << bd.i) | (W(1) << bd.j));
         int u, cnt;
-        const int64_t idx = locate<W, KIND, A>(d, S, t, u, cnt);
+        const auto idx = locate<W, KIND, A>(d, S, t, u, cnt);
         if (idx < 0) return;
         A ar = bd.h, ai = 0;
         if constexpr (KIND != K_U1) {
