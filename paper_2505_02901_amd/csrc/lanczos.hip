@@ -109,6 +109,83 @@ __global__ __launch_bounds__(RB) void k_scale(const T *src, T *dst, uint64_t n, 
         dst[q] = bt > 0.0 ? (T)((double)src[q] / bt) : T(0);
 }
 
+// One column (a single real vector): four consecutive scalars per thread
+// through one vector load each, the same arithmetic per scalar as the
+// kernels above.  Scalars past the last full group of four go to block 0.
+template <class T>
+using Vec4 = T __attribute__((ext_vector_type(4)));
+
+template <class T>
+__global__ __launch_bounds__(RB) void k_dot1(const T *a, const T *b, uint64_t n,
+                                             double *partials) {
+    __shared__ double sh[RB];
+    double acc = 0.0;
+    const uint64_t n4 = n / 4, stride = (uint64_t)gridDim.x * RB;
+    for (uint64_t q = (uint64_t)blockIdx.x * RB + threadIdx.x; q < n4; q += stride) {
+        const Vec4<T> x = reinterpret_cast<const Vec4<T> *>(a)[q];
+        const Vec4<T> y = reinterpret_cast<const Vec4<T> *>(b)[q];
+#pragma unroll
+        for (int e = 0; e < 4; ++e) acc += (double)x[e] * (double)y[e];
+    }
+    if (blockIdx.x == 0)
+        for (uint64_t q = 4 * n4 + threadIdx.x; q < n; q += RB) acc += (double)a[q] * (double)b[q];
+    sh[threadIdx.x] = acc;
+    block_col_reduce(sh, 1);
+    if (threadIdx.x == 0) partials[blockIdx.x] = sh[0];
+}
+
+template <class T>
+__global__ __launch_bounds__(RB) void k_update1(T *w, const T *v, const T *vprev, uint64_t n,
+                                                const double *alpha, const double *beta,
+                                                double *partials) {
+    __shared__ double sh[RB];
+    double acc = 0.0;
+    const double a = alpha[0], b = vprev ? beta[0] : 0.0;
+    const uint64_t n4 = n / 4, stride = (uint64_t)gridDim.x * RB;
+    for (uint64_t q = (uint64_t)blockIdx.x * RB + threadIdx.x; q < n4; q += stride) {
+        Vec4<T> x = reinterpret_cast<const Vec4<T> *>(w)[q];
+        const Vec4<T> y = reinterpret_cast<const Vec4<T> *>(v)[q];
+        Vec4<T> z = {};
+        if (vprev) z = reinterpret_cast<const Vec4<T> *>(vprev)[q];
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+            double t = (double)x[e] - a * (double)y[e];
+            if (vprev) t -= b * (double)z[e];
+            const T r = (T)t;
+            x[e] = r;
+            acc += (double)r * (double)r;
+        }
+        reinterpret_cast<Vec4<T> *>(w)[q] = x;
+    }
+    if (blockIdx.x == 0)
+        for (uint64_t q = 4 * n4 + threadIdx.x; q < n; q += RB) {
+            double t = (double)w[q] - a * (double)v[q];
+            if (vprev) t -= b * (double)vprev[q];
+            const T r = (T)t;
+            w[q] = r;
+            acc += (double)r * (double)r;
+        }
+    sh[threadIdx.x] = acc;
+    block_col_reduce(sh, 1);
+    if (threadIdx.x == 0) partials[blockIdx.x] = sh[0];
+}
+
+template <class T>
+__global__ __launch_bounds__(RB) void k_scale1(const T *src, T *dst, uint64_t n,
+                                               const double *beta) {
+    const double bt = beta[0];
+    const uint64_t n4 = n / 4, stride = (uint64_t)gridDim.x * RB;
+    for (uint64_t q = (uint64_t)blockIdx.x * RB + threadIdx.x; q < n4; q += stride) {
+        Vec4<T> x = reinterpret_cast<const Vec4<T> *>(src)[q];
+#pragma unroll
+        for (int e = 0; e < 4; ++e) x[e] = bt > 0.0 ? (T)((double)x[e] / bt) : T(0);
+        reinterpret_cast<Vec4<T> *>(dst)[q] = x;
+    }
+    if (blockIdx.x == 0)
+        for (uint64_t q = 4 * n4 + threadIdx.x; q < n; q += RB)
+            dst[q] = bt > 0.0 ? (T)((double)src[q] / bt) : T(0);
+}
+
 __global__ void k_step_end(int *jdev, double *prev_beta, const double *cur_beta, int nv) {
     for (int v = threadIdx.x; v < nv; v += blockDim.x) prev_beta[v] = cur_beta[v];
     __syncthreads();
@@ -201,7 +278,21 @@ struct VecOps {
     double *partials;  // [grid][cols]
     hipStream_t st;
 
+    // one column and vector-aligned buffers: the four-wide kernels
+    bool vec4(const void *p) const {
+        return cols == 1 && ((uintptr_t)p % (single ? 16 : 32)) == 0;
+    }
     int dot(const void *a, const void *b) const {
+        if (vec4(a) && vec4(b)) {
+            if (single)
+                hipLaunchKernelGGL(k_dot1<float>, dim3(grid), dim3(RB), 0, st, (const float *)a,
+                                   (const float *)b, n, partials);
+            else
+                hipLaunchKernelGGL(k_dot1<double>, dim3(grid), dim3(RB), 0, st, (const double *)a,
+                                   (const double *)b, n, partials);
+            XDG_TRY_HIP(hipGetLastError());
+            return XDG_OK;
+        }
         if (single)
             hipLaunchKernelGGL(k_dot<float>, dim3(grid), dim3(RB), 0, st, (const float *)a,
                                (const float *)b, n, cols, partials);
@@ -219,6 +310,18 @@ struct VecOps {
     }
     int update(void *w, const void *v, const void *vprev, const double *alpha,
                const double *beta) const {
+        if (vec4(w) && vec4(v) && (!vprev || vec4(vprev))) {
+            if (single)
+                hipLaunchKernelGGL(k_update1<float>, dim3(grid), dim3(RB), 0, st, (float *)w,
+                                   (const float *)v, (const float *)vprev, n, alpha, beta,
+                                   partials);
+            else
+                hipLaunchKernelGGL(k_update1<double>, dim3(grid), dim3(RB), 0, st, (double *)w,
+                                   (const double *)v, (const double *)vprev, n, alpha, beta,
+                                   partials);
+            XDG_TRY_HIP(hipGetLastError());
+            return XDG_OK;
+        }
         if (single)
             hipLaunchKernelGGL(k_update<float>, dim3(grid), dim3(RB), 0, st, (float *)w,
                                (const float *)v, (const float *)vprev, n, cols, C, alpha, beta,
@@ -231,6 +334,16 @@ struct VecOps {
         return XDG_OK;
     }
     int scale(const void *src, void *dst, const double *beta) const {
+        if (vec4(src) && vec4(dst)) {
+            if (single)
+                hipLaunchKernelGGL(k_scale1<float>, dim3(grid), dim3(RB), 0, st,
+                                   (const float *)src, (float *)dst, n, beta);
+            else
+                hipLaunchKernelGGL(k_scale1<double>, dim3(grid), dim3(RB), 0, st,
+                                   (const double *)src, (double *)dst, n, beta);
+            XDG_TRY_HIP(hipGetLastError());
+            return XDG_OK;
+        }
         if (single)
             hipLaunchKernelGGL(k_scale<float>, dim3(grid), dim3(RB), 0, st, (const float *)src,
                                (float *)dst, n, cols, C, beta);
@@ -384,11 +497,14 @@ int lanczos_single(xdg_ham_s *h, const void *v0, int k, double tol, int max_iter
     const size_t esz = (single ? 4 : 8) * C;
     const uint64_t nsc = (uint64_t)D * C;
     const size_t vbytes = (size_t)D * esz;
+    // slots 256-byte aligned (the vector kernels load four scalars at a time)
+    const size_t vstride = (vbytes + 255) & ~(size_t)255;
+    const uint64_t ld = vstride / (single ? 4 : 8);   // slot stride in scalars
 
     DevBuf bufs, wbuf, scal, parts, rparts;
     // vectors: reorth keeps every v_j (column j of V); otherwise three rotate
     const int nstore = reorth ? max_iter + 1 : 3;
-    XDG_RETURN_IF(bufs.alloc(vbytes * nstore));
+    XDG_RETURN_IF(bufs.alloc(vstride * nstore));
     XDG_RETURN_IF(wbuf.alloc(vbytes));
     // scalars: cur_alpha, cur_beta, prev_beta, hist_alpha[max_iter], hist_beta[max_iter], jdev
     XDG_RETURN_IF(scal.alloc(sizeof(double) * (3 + 2 * (size_t)max_iter + 2 * (size_t)(max_iter + 1)) + 16));
@@ -402,7 +518,7 @@ int lanczos_single(xdg_ham_s *h, const void *v0, int k, double tol, int max_iter
     const int rgrid = (int)std::min<int64_t>(std::max<int64_t>(1, D / 4096), device_cu_count() * 2);
     if (reorth) XDG_RETURN_IF(rparts.alloc(sizeof(double) * 2 * (size_t)rgrid * (max_iter + 1)));
 
-    auto vec = [&](int i) -> char * { return bufs.as<char>() + vbytes * i; };
+    auto vec = [&](int i) -> char * { return bufs.as<char>() + vstride * i; };
     char *w = wbuf.as<char>();
     if (v0)
         XDG_TRY_HIP(hipMemcpyAsync(vec(0), v0, vbytes, hipMemcpyDeviceToDevice, st));
@@ -446,20 +562,20 @@ int lanczos_single(xdg_ham_s *h, const void *v0, int k, double tol, int max_iter
                 if (single) {
                     if (C == 1)
                         hipLaunchKernelGGL((k_reorth_dots<float, 1>), dim3(rgrid), dim3(RB), 0, st,
-                                           (const float *)vec(0), (uint64_t)nsc, kk,
+                                           (const float *)vec(0), ld, kk,
                                            (const float *)w, (uint64_t)D, rparts.as<double>());
                     else
                         hipLaunchKernelGGL((k_reorth_dots<float, 2>), dim3(rgrid), dim3(RB), 0, st,
-                                           (const float *)vec(0), (uint64_t)nsc, kk,
+                                           (const float *)vec(0), ld, kk,
                                            (const float *)w, (uint64_t)D, rparts.as<double>());
                 } else {
                     if (C == 1)
                         hipLaunchKernelGGL((k_reorth_dots<double, 1>), dim3(rgrid), dim3(RB), 0,
-                                           st, (const double *)vec(0), (uint64_t)nsc, kk,
+                                           st, (const double *)vec(0), ld, kk,
                                            (const double *)w, (uint64_t)D, rparts.as<double>());
                     else
                         hipLaunchKernelGGL((k_reorth_dots<double, 2>), dim3(rgrid), dim3(RB), 0,
-                                           st, (const double *)vec(0), (uint64_t)nsc, kk,
+                                           st, (const double *)vec(0), ld, kk,
                                            (const double *)w, (uint64_t)D, rparts.as<double>());
                 }
                 hipLaunchKernelGGL(k_reorth_finalize, dim3(1), dim3(RB), 0, st,
@@ -468,20 +584,20 @@ int lanczos_single(xdg_ham_s *h, const void *v0, int k, double tol, int max_iter
                 if (single) {
                     if (C == 1)
                         hipLaunchKernelGGL((k_reorth_sub<float, 1>), dim3(sgrid), dim3(RB), 0, st,
-                                           (const float *)vec(0), (uint64_t)nsc, kk, coef,
+                                           (const float *)vec(0), ld, kk, coef,
                                            (float *)w, (uint64_t)D);
                     else
                         hipLaunchKernelGGL((k_reorth_sub<float, 2>), dim3(sgrid), dim3(RB), 0, st,
-                                           (const float *)vec(0), (uint64_t)nsc, kk, coef,
+                                           (const float *)vec(0), ld, kk, coef,
                                            (float *)w, (uint64_t)D);
                 } else {
                     if (C == 1)
                         hipLaunchKernelGGL((k_reorth_sub<double, 1>), dim3(sgrid), dim3(RB), 0, st,
-                                           (const double *)vec(0), (uint64_t)nsc, kk, coef,
+                                           (const double *)vec(0), ld, kk, coef,
                                            (double *)w, (uint64_t)D);
                     else
                         hipLaunchKernelGGL((k_reorth_sub<double, 2>), dim3(sgrid), dim3(RB), 0, st,
-                                           (const double *)vec(0), (uint64_t)nsc, kk, coef,
+                                           (const double *)vec(0), ld, kk, coef,
                                            (double *)w, (uint64_t)D);
                 }
                 XDG_TRY_HIP(hipGetLastError());
@@ -661,8 +777,9 @@ int lanczos_eigvec(xdg_ham_s *h, const void *v0, uint64_t seed, int prec, int m,
     const size_t esz = (single ? 4 : 8) * C;
     const uint64_t nsc = (uint64_t)D * C;
     const size_t vbytes = (size_t)D * esz;
+    const size_t vstride = (vbytes + 255) & ~(size_t)255;   // 256-byte aligned slots
     DevBuf bufs, wbuf, acc, scal, parts;
-    XDG_RETURN_IF(bufs.alloc(vbytes * 3));
+    XDG_RETURN_IF(bufs.alloc(vstride * 3));
     XDG_RETURN_IF(wbuf.alloc(vbytes));
     XDG_RETURN_IF(acc.alloc(sizeof(double) * nsc));
     // scalars: nrm, alpha[m], beta[m], zero
@@ -676,7 +793,7 @@ int lanczos_eigvec(xdg_ham_s *h, const void *v0, uint64_t seed, int prec, int m,
     VecOps ops{single, C, C, nsc, vec_grid(nsc), nullptr, st};
     XDG_RETURN_IF(parts.alloc(sizeof(double) * (size_t)ops.grid * MAXC));
     ops.partials = parts.as<double>();
-    auto vec = [&](int i) -> char * { return bufs.as<char>() + vbytes * i; };
+    auto vec = [&](int i) -> char * { return bufs.as<char>() + vstride * i; };
     char *w = wbuf.as<char>();
     // start vector exactly as in the first pass
     if (v0)
@@ -763,6 +880,7 @@ int lanczos_batched(int n, xdg_ham_s *const *hams, const void *const *v0s, int64
     struct Sec {
         DevBuf buf, parts, scal;
         uint64_t nsc;
+        size_t slot;   // bytes between the vector slots of buf
         VecOps ops;
         double *cur_a, *cur_b, *prev_b, *hist_a, *hist_b;
     };
@@ -774,7 +892,8 @@ int lanczos_batched(int n, xdg_ham_s *const *hams, const void *const *v0s, int64
         Sec &s = S[i];
         const int64_t D = hams[i]->basis->dim;
         s.nsc = (uint64_t)D * cols;
-        XDG_RETURN_IF(s.buf.alloc(ssz * s.nsc * 4));   // v0, v1, v2 (rotating) + w
+        s.slot = (ssz * s.nsc + 255) & ~(size_t)255;   // 256-byte aligned slots
+        XDG_RETURN_IF(s.buf.alloc(s.slot * 4));   // v0, v1, v2 (rotating) + w
         s.ops = VecOps{single, cols, C, s.nsc, vec_grid(s.nsc), nullptr, st};
         XDG_RETURN_IF(s.parts.alloc(sizeof(double) * (size_t)s.ops.grid * MAXC));
         s.ops.partials = s.parts.as<double>();
@@ -794,7 +913,7 @@ int lanczos_batched(int n, xdg_ham_s *const *hams, const void *const *v0s, int64
         XDG_RETURN_IF(s.ops.finalize(1, s.cur_b, nullptr, jdev));
         XDG_RETURN_IF(s.ops.scale(v, v, s.cur_b));
     }
-    auto vecp = [&](int i, int slot) -> char * { return S[i].buf.as<char>() + ssz * S[i].nsc * slot; };
+    auto vecp = [&](int i, int slot) -> char * { return S[i].buf.as<char>() + S[i].slot * slot; };
     // phase p: v = slot p, vprev = slot (p+2)%3 (none at j = 0), next = slot (p+1)%3, w = slot 3
     BatchPlan plans[3];
     std::vector<xdg_ham_s *> hv(hams, hams + n);
