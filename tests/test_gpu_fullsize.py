@@ -154,6 +154,23 @@ def test_c2_fullsize(X, i):
     check_windows(m, b, 10 + i)
     check_membership(X, m, b, 20 + i)
     check_columns(X, m, b, H, 30 + i, 4, [(torch.float64, 1e-12), (torch.float32, 2e-6)])
+    check_hermitian(b, H, 60 + i)
+
+
+def check_hermitian(b, H, seed, fp32=True):
+    """<w, H x> = <x, H w> for random real x, w over every row of the block
+    (FP64 to 1e-10; FP32 vectors with FP64 row sums to 1e-5)."""
+    g = torch.Generator(device="cuda").manual_seed(seed)
+    for dt, tol in ((torch.float64, 1e-10), (torch.float32, 1e-5))[: 2 if fp32 else 1]:
+        x = torch.randn(b.dim, dtype=dt, device="cuda", generator=g)
+        w = torch.randn(b.dim, dtype=dt, device="cuda", generator=g)
+        hx, hw = torch.empty_like(x), torch.empty_like(w)
+        H.apply(x, hx)
+        H.apply(w, hw)
+        lhs = torch.dot(w.double(), hx.double()).item()
+        rhs = torch.dot(x.double(), hw.double()).item()
+        assert abs(lhs - rhs) < tol * max(abs(lhs), torch.linalg.vector_norm(hx.double()).item()), (dt, lhs, rhs)
+        del x, w, hx, hw
 
 
 def test_c3_fullsize(X):
@@ -202,6 +219,7 @@ def test_c5_fullsize(X):
     check_windows(m, b, 50, n_windows=2, width=400)
     check_membership(X, m, b, 51, n_members=600, n_random=600)
     check_columns(X, m, b, H, 52, 2, [(torch.float64, 1e-12)])
+    check_hermitian(b, H, 53, fp32=False)
 
 
 def test_c2_ground_state_correlations(X):
