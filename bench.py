@@ -101,6 +101,27 @@ def load_traffic(workload: str, kernel_hash: str):
     return t.get("traffic_bytes_per_launch")
 
 
+# VALU issue peak: 256 CUs x 4 SIMDs x 2.4 GHz, one wave64 instruction per SIMD
+# every 4 cycles (16 lanes per cycle)
+VALU_PEAK_WAVE_INSTS = 256 * 4 * 2.4e9 / 4
+
+
+def load_issue(workload: str, kernel_hash: str, launch_s: float):
+    """VALU wave instructions of one apply launch from the committed counter
+    summary (taken on the current kernel sources), as issue time at the peak
+    rate and its share of the measured launch."""
+    p = os.path.join(ROOT, "profiles", f"issue_{workload}.json")
+    if not os.path.exists(p):
+        return None
+    with open(p) as f:
+        t = json.load(f)
+    if t.get("source_hash") != kernel_hash:
+        return None
+    ms = t["valu_wave_insts"] / VALU_PEAK_WAVE_INSTS * 1e3
+    return {"valu_wave_insts": t["valu_wave_insts"], "peak_wave_insts_per_s": VALU_PEAK_WAVE_INSTS,
+            "issue_ms": ms, "frac_of_launch": ms / (launch_s * 1e3)}
+
+
 def cpu_baseline(models, seconds: float = 15.0):
     """The oracle's H x on a bounded random sample of rows of the first sector."""
     import oracle
@@ -194,6 +215,7 @@ class Ctx:
         return {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": achieved / HBM_PEAK_GBS,
                 "traffic": load_traffic(self.args.workload, khash),
+                "valu_issue": load_issue(self.args.workload, khash, sec),
                 "kernel": f"k_apply ({'complex ' if self.cplx else ''}FP32, {nvec} vector(s), "
                           f"sector {m.name})",
                 "avg_launch_ms": sec * 1e3, "alg_bytes_per_launch": alg,
@@ -292,6 +314,28 @@ def counters_run(args):
                       "copy_bytes": a.numel() * 4}))
 
 
+def summarize_issue(args):
+    """profiles/issue_<workload>.json from the CSV of the SQ_INSTS_* run (last
+    apply dispatch; counts summed over the chip)."""
+    import csv
+    import glob
+    f = glob.glob(os.path.join(args.summarize_issue, "**", "*counter_collection.csv"),
+                  recursive=True)[0]
+    rows = list(csv.DictReader(open(f)))
+    last = [r["Dispatch_Id"] for r in rows if "k_apply" in r["Kernel_Name"]][-1]
+    vals, kname = {}, ""
+    for r in rows:
+        if r["Dispatch_Id"] == last:
+            vals[r["Counter_Name"]] = vals.get(r["Counter_Name"], 0.0) + float(r["Counter_Value"])
+            kname = r["Kernel_Name"]
+    out = {"workload": args.workload, "kernel": kname, "source_hash": source_hash(),
+           "valu_wave_insts": vals["SQ_INSTS_VALU"], "counters": vals}
+    p = os.path.join(ROOT, "profiles", f"issue_{args.workload}.json")
+    with open(p, "w") as fh:
+        json.dump(out, fh, indent=1)
+    print(json.dumps(out))
+
+
 def summarize_counters(args):
     """profiles/traffic_<workload>.json from the CSVs of the FETCH_SIZE and
     WRITE_SIZE runs (last apply dispatch of each; counts in KiB, scaled by the
@@ -328,6 +372,8 @@ def main():
     ap.add_argument("--counters", action="store_true",
                     help="run the profiled apply + calibration copy (under rocprofv3 --pmc)")
     ap.add_argument("--summarize-counters", nargs=2, metavar=("FETCH_DIR", "WRITE_DIR"))
+    ap.add_argument("--summarize-issue", metavar="SQ_DIR",
+                    help="write profiles/issue_<workload>.json from an SQ_INSTS_* counter run")
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=None)
     ap.add_argument("--warmup", type=int, default=None)
@@ -338,6 +384,9 @@ def main():
     args = ap.parse_args()
     if args.summarize_counters:
         summarize_counters(args)
+        return
+    if args.summarize_issue:
+        summarize_issue(args)
         return
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU: the library has no multi-GPU path "
