@@ -425,9 +425,12 @@ int launch_nv(int nv, const ApplyArgs &A, unsigned grid, unsigned block, size_t 
               hipStream_t st) {
     void (*f)(ApplyArgs) = nullptr;
     // only the sublattice kind has tables that may stay in global memory
+    // the 64-VGPR copy only while a lane holds at most two accumulator
+    // scalars: with more it spills them (complex 8-vector passes: 200 bytes)
+    const bool occ = A.occ && nv * (CPLX ? 2 : 1) <= 2;
     if (KIND != K_SUB || A.stage_sub)
-        f = A.occ ? apply_kernel<W, KIND, T, AC, CPLX, true, true>(nv)
-                  : apply_kernel<W, KIND, T, AC, CPLX, true, false>(nv);
+        f = occ ? apply_kernel<W, KIND, T, AC, CPLX, true, true>(nv)
+                : apply_kernel<W, KIND, T, AC, CPLX, true, false>(nv);
     else if constexpr (KIND == K_SUB)
         f = apply_kernel<W, KIND, T, AC, CPLX, false, false>(nv);
     if (!f) {
