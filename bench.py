@@ -1,18 +1,18 @@
 #!/usr/bin/env python3
 """Benchmark: matrix-free H x and Lanczos on symmetry-adapted spin-1/2 sectors.
 
-Default workload (chain32_k0_kpi): Heisenberg ring N = 32, J = 1, Sz = 0,
-translation group (32 elements), momentum sectors k = 0 and k = pi
-(18,784,170 states each).  One step = one Lanczos iteration (H x, the vector
-operations and the scalar read-back) in each of the two sectors, with FP32
-vectors and FP64 scalars.  The same steps in FP64 are timed beside it, and a
-200-iteration run in both precisions gives the ground-state energies (vs the
-Bethe ansatz).
+Default workload (square36_j1j2_A1): J1-J2 Heisenberg model (J1 = 1,
+J2 = 0.5) on the 6x6 periodic square lattice, Sz = 0, translations x C4v
+(288 elements), Gamma-point A1 sector (31,566,122 states).  One step = one
+Lanczos iteration with FP32 vectors and FP64 full reorthogonalisation; the
+default K = 200 steps are one complete 200-iteration run, whose lowest Ritz
+value is the ground-state energy.  The same run with FP64 vectors (with and
+without reorthogonalisation) is timed beside it, and the energies compared.
 
 Other workloads (--workload):
   chain16_u1        N = 16 ring, U(1) block only (12,870 states), FP64
-  square36_j1j2_A1  6x6 J1-J2 (J2 = 0.5), T x C4v (288), Gamma A1: FP32
-                    vectors + FP64 full reorthogonalisation vs FP64
+  chain32_k0_kpi    N = 32 ring, T_32, k = 0 and pi (18,784,170 states each):
+                    FP32 vectors vs FP64, 200 iterations, Bethe-ansatz energies
   chain32_allk      all 32 momenta of the N = 32 ring x 8 vectors, batched
                     persistent launch replayed from a HIP graph (complex FP32)
                     vs sector-by-sector single-vector FP64
@@ -40,8 +40,9 @@ METRIC = ("H·x nonzeros/sec + Lanczos iters/sec; FP32-vector & batched vs FP64 
 HBM_PEAK_GBS = 8000.0
 E0_ITERS = {"chain16_u1": 300, "chain32_k0_kpi": 200, "square36_j1j2_A1": 200,
             "chain32_allk": 100, "tilted40_xxz": 100}
-DEFAULT_STEPS = {"chain16_u1": 200, "chain32_k0_kpi": 40, "square36_j1j2_A1": 10,
+DEFAULT_STEPS = {"chain16_u1": 200, "chain32_k0_kpi": 40, "square36_j1j2_A1": 200,
                  "chain32_allk": 20, "tilted40_xxz": 3}
+DEFAULT_WORKLOAD = "square36_j1j2_A1"
 
 
 def log(*a):
@@ -68,15 +69,29 @@ def bethe_energy(N: int, M: int) -> float:
     return float(N / 4.0 - np.sum(2.0 / (1.0 + 4.0 * lam ** 2)))
 
 
-def alg_bytes(dim: int, nnz: int, word: int, vec: int, nvec: int, symmetric: bool) -> int:
-    """Algorithmic bytes of one application: per row the state word, the
-    stabiliser (2 B, symmetric blocks), x[r] read and y[r] written; per
-    off-diagonal term in the block the gathered x values and, for symmetric
-    blocks, one index entry (key word + 4-byte position)."""
-    T = nnz - dim
-    row = word + (2 if symmetric else 0) + 2 * nvec * vec
-    term = nvec * vec + ((word + 4) if symmetric else 0)
-    return dim * row + T * term
+def mean_terms_full_space(n_sites: int, n_up: int, n_bonds: int) -> float:
+    """Mean number of unequal-spin bonds per state over all states with n_up
+    up spins: each bond has unequal spins with probability
+    2 n_up (N - n_up) / (N (N - 1))."""
+    N = n_sites
+    return n_bonds * 2.0 * n_up * (N - n_up) / (N * (N - 1))
+
+
+def alg_bytes(dim: int, n_sites: int, n_up: int, n_bonds: int, vec: int, nvec: int,
+              symmetric: bool) -> int:
+    """Algorithmic bytes of one application (the byte model of the method):
+        B = D (b_r + b_n + 2 nvec b_v) + T (nvec b_v + [sym] (b_p + n_probe b_k))
+    per row the state word b_r (4 B for N <= 32, else 8), the stabiliser
+    class b_n = 1 B, x[r] read and y[r] written; per generated off-diagonal
+    term (T = D x the full-space mean number of unequal-spin bonds) the
+    gathered x values and, for symmetric blocks, one index lookup priced as a
+    prefix-table entry (b_p = 4 B) plus n_probe = 5 postfix keys of b_k = 4 B.
+    The U(1) Lin tables are cache resident and count 0."""
+    b_r = 4 if n_sites <= 32 else 8
+    T = dim * mean_terms_full_space(n_sites, n_up, n_bonds)
+    row = b_r + 1 + 2 * nvec * vec
+    term = nvec * vec + ((4 + 5 * 4) if symmetric else 0)
+    return int(round(dim * row + T * term))
 
 
 def source_hash() -> str:
@@ -102,8 +117,9 @@ def load_traffic(workload: str, kernel_hash: str):
 
 
 # VALU issue peak: 256 CUs x 4 SIMDs x 2.4 GHz, one wave64 instruction per SIMD
-# every 4 cycles (16 lanes per cycle)
+# every 4 cycles (16 lanes per cycle); as lane operations: 256 x 4 x 16 x 2.4e9
 VALU_PEAK_WAVE_INSTS = 256 * 4 * 2.4e9 / 4
+VALU_PEAK_LANE_OPS = VALU_PEAK_WAVE_INSTS * 64
 
 
 def load_issue(workload: str, kernel_hash: str, launch_s: float):
@@ -122,33 +138,105 @@ def load_issue(workload: str, kernel_hash: str, launch_s: float):
             "issue_ms": ms, "frac_of_launch": ms / (launch_s * 1e3)}
 
 
-def cpu_baseline(models, seconds: float = 15.0):
-    """The oracle's H x on a bounded random sample of rows of the first sector."""
+def roofline_entry(alg: int, launch_s: float, traffic, issue):
+    """The roofline object of the dominant kernel.  The limiter (`bound`) is
+    whichever of HBM traffic (counter bytes per launch over the launch time,
+    against 8 TB/s) and VALU issue (counter instructions at the issue peak,
+    as a share of the launch) is closer to its peak.  With bound "hbm" the
+    figures are the algorithmic bytes over the launch time against 8 TB/s;
+    with bound "alu" they are the executed VALU lane operations over the
+    launch time against 256 CUs x 64 lanes x 2.4 GHz = 39.3 Tops/s, and the
+    algorithmic-byte figures stay under "hbm".  Without counters for the
+    current kernel sources the limiter is unknown and the HBM roofline is
+    reported."""
+    hbm = {"achieved": alg / launch_s / 1e9, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+           "frac": alg / launch_s / 1e9 / HBM_PEAK_GBS}
+    traffic_frac = None if traffic is None else traffic / launch_s / 1e9 / HBM_PEAK_GBS
+    valu_frac = None if issue is None else issue["frac_of_launch"]
+    out = {"bound": "hbm", **hbm, "traffic": traffic,
+           "traffic_frac_of_peak": traffic_frac, "valu_issue": issue}
+    if traffic_frac is None or valu_frac is None:
+        out["limiter"] = "unknown (no counters for the current kernel sources)"
+        return out
+    if valu_frac > traffic_frac:
+        lane_ops = issue["valu_wave_insts"] * 64
+        out.update({"bound": "alu", "achieved": lane_ops / launch_s / 1e12,
+                    "peak": VALU_PEAK_LANE_OPS / 1e12, "unit": "Tops/s",
+                    "frac": lane_ops / launch_s / VALU_PEAK_LANE_OPS, "hbm": hbm})
+    out["limiter"] = (f"VALU issue {valu_frac:.2f} of the launch vs HBM traffic "
+                      f"{traffic_frac:.2f} of 8 TB/s")
+    return out
+
+
+def cpu_model() -> str:
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    try:
+        import subprocess
+        out = subprocess.run(["lscpu"], capture_output=True, text=True).stdout
+        for line in out.splitlines():
+            if line.startswith("Model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def cpu_baseline(models, nvec: int = 1, target_s: float = 3.0):
+    """The oracle's H x on a bounded sample of rows: per row the diagonal,
+    the pull-form terms (representative search by scanning the group,
+    stabiliser and character sums) and the gather of x at the target states
+    (x keyed by state, so no basis list is enumerated).  Three runs on all
+    host cores and three on one core; the medians are reported."""
     import oracle
     oracle.build()
-    m = models[0]
-    t0 = time.perf_counter()
-    basis = oracle.basis(m)
-    t_basis = time.perf_counter() - t0
-    rng = np.random.default_rng(0)
-    x = np.ones(len(basis), np.complex128)
-    n0 = min(len(basis), 2000)
-    rows = np.sort(rng.choice(len(basis), size=n0, replace=False))
-    t0 = time.perf_counter()
-    oracle.apply_rows(m, basis, rows, x)
-    dt = time.perf_counter() - t0
-    n = int(min(len(basis), max(n0, n0 * seconds / max(dt, 1e-6))))
-    rows = np.sort(rng.choice(len(basis), size=n, replace=False))
-    t0 = time.perf_counter()
-    oracle.apply_rows(m, basis, rows, x)
-    dt = time.perf_counter() - t0
-    nnz = sum(1 + len(oracle.row_terms(m, int(basis[r]))[1]) for r in rows[:500])
-    nnz_per_row = nnz / min(500, len(rows))
-    return {"value": len(rows) * nnz_per_row / dt, "unit": "nonzeros/s",
-            "cores": oracle.num_threads(), "kind": "oracle",
-            "sample": f"{len(rows)} random rows of sector {m.name} (H x, complex128, OpenMP over "
-                      f"rows); the oracle's basis enumeration of that sector ({t_basis:.1f} s) "
-                      "is not included"}
+    cores = oracle.num_threads()
+    per = max(1, 64 // len(models))
+    samples = [(m, oracle.sample_basis_states(m, per, 1000 + i)) for i, m in enumerate(models)]
+
+    def nnz_of(rows_per_model):
+        """nonzeros the sampled rows hold (diagonal + terms in the block), untimed"""
+        n = 0
+        for m, rows in rows_per_model:
+            _, _, cnt, _, _ = oracle.rows_terms(m, rows)
+            n += int(len(rows) + cnt.sum()) * nvec
+        return n
+
+    def run(rows_per_model):
+        t0 = time.perf_counter()
+        for m, rows in rows_per_model:
+            oracle.apply_keyed(m, rows, 9, nvec=nvec, complex_=m.is_complex)
+        return time.perf_counter() - t0
+
+    def timed(threads):
+        oracle.set_num_threads(threads)
+        dt = run(samples)               # size the sample to ~target_s per run
+        scale = max(1.0, target_s / max(dt, 1e-3))
+        n_rows = int(min(200000, per * scale))
+        big = [(m, oracle.sample_basis_states(m, n_rows, 2000 + i)) for i, m in enumerate(models)]
+        nnz = nnz_of(big)
+        times = [run(big) for _ in range(3)]
+        rates = sorted(nnz / t for t in times)
+        return {"value": rates[1], "runs": rates, "threads": threads,
+                "rows": n_rows * len(models), "s_per_run": float(np.median(times))}
+
+    allc = timed(cores)
+    one = timed(1)
+    oracle.set_num_threads(cores)
+    names = ", ".join(m.name for m in models[:3]) + (" ..." if len(models) > 3 else "")
+    return {"value": allc["value"], "unit": "nonzeros/s", "cores": cores, "kind": "oracle",
+            "sample": f"{allc['rows']} rows drawn by the oracle from {names} (random states "
+                      f"mapped to their representatives), {nvec} vector(s), median of 3 runs "
+                      f"of ~{allc['s_per_run']:.1f} s; x keyed by state, so the oracle's "
+                      "basis enumeration (brute force over all states) is not part of it",
+            "one_core": {"value": one["value"], "runs": one["runs"], "rows": one["rows"]},
+            "all_core_runs": allc["runs"], "cpu_model": cpu_model(),
+            "nproc": os.cpu_count()}
 
 
 class Ctx:
@@ -184,51 +272,68 @@ class Ctx:
         torch.cuda.synchronize()
         return time.perf_counter() - t
 
-    def apply_roofline(self, nvec=1, reps=20):
-        """Average duration of one apply launch of the first sector, timed with
+    def apply_roofline(self, nvec=1, reps=20, batched=False):
+        """Average duration of one launch of the dominant kernel (the apply of
+        the first sector, or the batched apply over every sector), timed with
         HIP events on the stream it is launched on, and its algorithmic bytes."""
-        torch = self.torch
-        h, d, n = self.hams[0], self.dims[0], self.nnzs[0]
+        torch, X = self.torch, self.X
         vdt = torch.complex64 if self.cplx else torch.float32
-        shape = (d,) if nvec == 1 else (d, nvec)
-        x = torch.randn(*shape, dtype=vdt, device="cuda")
-        y = torch.empty_like(x)
-        h.apply(x, y)
+        idx = range(len(self.hams)) if batched else [0]
+        xs, ys = [], []
+        for i in idx:
+            d = self.dims[i]
+            xs.append(torch.randn(*((d,) if nvec == 1 else (d, nvec)), dtype=vdt, device="cuda"))
+            ys.append(torch.empty_like(xs[-1]))
+        hs = [self.hams[i] for i in idx]
+
+        def launch(st=None):
+            if batched:
+                X.xdg_apply_batched([h.handle for h in hs], xs, ys, stream=st)
+            else:
+                hs[0].apply(xs[0], ys[0], stream=st)
+        launch()
         torch.cuda.synchronize()
         st = torch.cuda.current_stream()
         e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
         e0.record(st)
         for _ in range(reps):
-            h.apply(x, y, stream=st)
+            launch(st)
         e1.record(st)
         e1.synchronize()
         sec = e0.elapsed_time(e1) * 1e-3 / reps
-        del x, y
-        m = self.models[0]
-        sym = m.perm is not None
-        word = 8 if m.n_sites > 32 else 4
+        del xs, ys
         vb = 8 if self.cplx else 4
-        alg = alg_bytes(d, n, word, vb, nvec, sym)
+        alg = 0
+        for i in idx:
+            m = self.models[i]
+            alg += alg_bytes(self.dims[i], m.n_sites, m.n_up, len(m.jz), vb, nvec,
+                             m.perm is not None)
         khash = source_hash()
-        achieved = alg / sec / 1e9
         torch.cuda.empty_cache()
-        return {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": achieved / HBM_PEAK_GBS,
-                "traffic": load_traffic(self.args.workload, khash),
-                "valu_issue": load_issue(self.args.workload, khash, sec),
-                "kernel": f"k_apply ({'complex ' if self.cplx else ''}FP32, {nvec} vector(s), "
-                          f"sector {m.name})",
-                "avg_launch_ms": sec * 1e3, "alg_bytes_per_launch": alg,
-                "nnz_per_launch": n * nvec, "source_hash": khash}
+        roof = roofline_entry(alg, sec, load_traffic(self.args.workload, khash),
+                              load_issue(self.args.workload, khash, sec))
+        what = (f"batched k_apply over {len(hs)} sectors" if batched
+                else f"k_apply, sector {self.models[0].name}")
+        roof.update({"kernel": f"{what} ({'complex ' if self.cplx else ''}FP32 vectors, "
+                               f"{nvec} per sector)",
+                     "avg_launch_ms": sec * 1e3, "alg_bytes_per_launch": alg,
+                     "nnz_per_launch": sum(self.nnzs[i] for i in idx) * nvec,
+                     "source_hash": khash})
+        return roof
 
 
-def run_standard(c: Ctx, prec_fast, prec_ref, step_name):
-    """Per-sector single-vector Lanczos steps in two precision forms."""
+def run_standard(c: Ctx, prec_fast, prec_ref, step_name, extra_ref=None):
+    """Per-sector single-vector Lanczos runs of K iterations in two precision
+    forms (K = the E0 iteration count by default, so the timed runs are the
+    energy runs); a third form (extra_ref) is run for its energy only."""
     X, a = c.X, c.args
+    res = {}
 
     def steps(prec):
         def f(warm):
-            c.lanczos(prec, a.warmup if warm else a.steps)
+            r = c.lanczos(prec, a.warmup if warm else a.steps)
+            if not warm:
+                res[prec] = r
         return f
 
     el_fast = c.timed(steps(prec_fast))
@@ -236,10 +341,13 @@ def run_standard(c: Ctx, prec_fast, prec_ref, step_name):
     el_ref = c.timed(steps(prec_ref))
     log(f"timed {a.steps} steps (reference form): {el_ref:.3f}s")
     nnz_step = sum(c.nnzs)
-    e_fast = [r[1][0] for r in c.lanczos(prec_fast, a.e0_iters)]
-    e_ref = [r[1][0] for r in c.lanczos(prec_ref, a.e0_iters)]
+
+    def e0(prec):
+        runs = res[prec] if a.steps == a.e0_iters and prec in res else c.lanczos(prec, a.e0_iters)
+        return [r[1][0] for r in runs]
+    e_fast, e_ref = e0(prec_fast), e0(prec_ref)
     log(f"E0 fast {e_fast} ref {e_ref}")
-    return {
+    out = {
         "value": nnz_step * a.steps / el_fast,
         "ms_per_step": 1e3 * el_fast / a.steps,
         "lanczos_iters_per_s": len(c.hams) * a.steps / el_fast,
@@ -250,6 +358,9 @@ def run_standard(c: Ctx, prec_fast, prec_ref, step_name):
                "rel_delta": [abs(p - q) / abs(q) for p, q in zip(e_fast, e_ref)]},
         "step": step_name,
     }
+    if extra_ref is not None:
+        out["e0"]["reference_reorth"] = e0(extra_ref)
+    return out
 
 
 def run_batched(c: Ctx):
@@ -291,27 +402,37 @@ def run_batched(c: Ctx):
 
 
 def counters_run(args):
-    """Workload for the counter runs: three applies of the first sector (FP32,
-    one vector), the last of which is summarised, then a plain 1 GiB device
-    copy whose FETCH_SIZE / WRITE_SIZE calibrate the counters."""
+    """Workload for the counter runs: three launches of the dominant kernel
+    (the FP32 apply of the first sector, one vector; for chain32_allk the
+    batched apply over all 32 sectors with 8 complex vectors each), the last
+    of which is summarised, then a plain 1 GiB device copy whose FETCH_SIZE /
+    WRITE_SIZE calibrate the counters."""
     import torch
     import paper_2505_02901_amd as X
     import workloads as W
-    m = W.workload(args.workload)[0]
-    b = X.Basis.from_model(m)
-    h = X.Hamiltonian.from_model(b, m)
-    dt = torch.complex64 if b.is_complex else torch.float32
-    x = torch.randn(b.dim, dtype=dt, device="cuda")
-    y = torch.empty_like(x)
+    batched = args.workload == "chain32_allk"
+    ms = W.workload(args.workload) if batched else W.workload(args.workload)[:1]
+    bs = [X.Basis.from_model(m) for m in ms]
+    hs = [X.Hamiltonian.from_model(b, m) for b, m in zip(bs, ms)]
+    cplx = any(b.is_complex for b in bs)
+    dt = torch.complex64 if cplx else torch.float32
+    nvec = 8 if batched else 1
+    xs = [torch.randn(*((b.dim,) if nvec == 1 else (b.dim, nvec)), dtype=dt, device="cuda")
+          for b in bs]
+    ys = [torch.empty_like(x) for x in xs]
     for _ in range(3):
-        h.apply(x, y)
+        if batched:
+            X.xdg_apply_batched([h.handle for h in hs], xs, ys)
+        else:
+            hs[0].apply(xs[0], ys[0])
     torch.cuda.synchronize()
+    del xs, ys
     a = torch.empty(256 << 20, dtype=torch.float32, device="cuda")
     c = torch.empty_like(a)
     c.copy_(a)
     torch.cuda.synchronize()
-    print(json.dumps({"workload": args.workload, "dim": b.dim, "nnz": h.nnz,
-                      "copy_bytes": a.numel() * 4}))
+    print(json.dumps({"workload": args.workload, "dims": [b.dim for b in bs][:4],
+                      "nnz": sum(h.nnz for h in hs), "nvec": nvec, "copy_bytes": a.numel() * 4}))
 
 
 def summarize_issue(args):
@@ -377,7 +498,7 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=None)
     ap.add_argument("--warmup", type=int, default=None)
-    ap.add_argument("--workload", default="chain32_k0_kpi",
+    ap.add_argument("--workload", default=DEFAULT_WORKLOAD,
                     choices=sorted(E0_ITERS))
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--e0-iters", type=int, default=None)
@@ -413,9 +534,8 @@ def main():
     elif w == "square36_j1j2_A1":
         r = run_standard(c, X.XDG_PREC_F32VEC_REORTH, X.XDG_PREC_F64,
                          "one Lanczos iteration, FP32 vectors with FP64 full reorthogonalisation "
-                         "(reference form: FP64, no reorthogonalisation)")
-        e_r2 = [q[1][0] for q in c.lanczos(X.XDG_PREC_F64_REORTH, args.e0_iters)]
-        r["e0"]["fp64_reorth"] = e_r2
+                         "(reference form: FP64, no reorthogonalisation)",
+                         extra_ref=X.XDG_PREC_F64_REORTH)
         dtype = "f32"
     elif w == "chain16_u1":
         r = run_standard(c, X.XDG_PREC_F64, X.XDG_PREC_F32VEC,
@@ -433,7 +553,8 @@ def main():
         ref = {"bethe": bethe_energy(16, 8)}
     if ref:
         r["e0"]["exact"] = ref
-    roof = c.apply_roofline(nvec=8 if w == "chain32_allk" else 1)
+    batched = w == "chain32_allk"
+    roof = c.apply_roofline(nvec=8 if batched else 1, batched=batched, reps=5 if batched else 20)
     line = {
         "metric": METRIC,
         "value": r["value"],
@@ -458,9 +579,9 @@ def main():
         "basis_build_s": c.t_build,
         "roofline": roof,
     }
-    # the oracle enumerates bases by brute force: feasible for the rings only
-    if not args.no_cpu_baseline and w in ("chain16_u1", "chain32_k0_kpi"):
-        line["cpu_baseline"] = cpu_baseline(c.models)
+    if not args.no_cpu_baseline:
+        log("cpu baseline (oracle, sampled rows) ...")
+        line["cpu_baseline"] = cpu_baseline(c.models, nvec=8 if batched else 1)
     print(json.dumps(line), flush=True)
 
 

@@ -31,6 +31,14 @@
  *   - All device work runs on the current HIP device.  Functions that take
  *     a `stream` (hipStream_t passed as void*; NULL = default stream) only
  *     enqueue work; the others synchronise before returning.
+ *   - The C ABI cannot see the size of a device buffer: a vector shorter
+ *     than the block's dim * nvec (complex counted twice) is read or written
+ *     out of bounds.  The Python binding checks tensor sizes and dtypes
+ *     against xdg_ham_dim / xdg_basis_dim before every call.
+ *   - Thread safety: handles may be used from several host threads; the
+ *     launch-shape caches inside a Hamiltonian and the batched-grid cache
+ *     are locked.  Calls that write the same output vector concurrently race
+ *     like any two writers.
  */
 #ifndef XDG_H
 #define XDG_H
@@ -190,6 +198,11 @@ void xdg_destroy_hamiltonian(xdg_ham h);
  * dim (the diagonal, counted once per row) plus the off-diagonal (row, bond)
  * terms whose target lies in the block.  Computed on the GPU once, cached. */
 int xdg_ham_nnz(xdg_ham h, int64_t *nnz);
+
+/* Dimension of the Hamiltonian's block and whether it is complex (so that
+ * callers holding only the Hamiltonian can size vectors; size(block),
+ * Sec. 3.1).  Either pointer may be NULL.  Host only. */
+int xdg_ham_dim(xdg_ham h, int64_t *dim, int *is_complex);
 
 /* y = H x, matrix-free (apply, Sec. 3.6 and Sec. 5.1: elements are computed
  * on the fly; several vectors at once as for a matrix of coefficients).

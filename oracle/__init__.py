@@ -56,6 +56,11 @@ def _load():
         lib.orc_apply_rows.restype = C.c_int
         lib.orc_apply_rows.argtypes = [C.c_int, C.c_int, P, P, C.c_int, P, P, P, P, C.c_int64,
                                        P, C.c_int64, C.c_int64, P, P]
+        lib.orc_rep_many.restype = C.c_int
+        lib.orc_rep_many.argtypes = [C.c_int, C.c_int, P, P, P, C.c_int64, P, P]
+        lib.orc_rows_terms.restype = C.c_int
+        lib.orc_rows_terms.argtypes = [C.c_int, C.c_int, C.c_int, P, P, C.c_int, P, P, P, P,
+                                       C.c_int64, P, P, P, P, P]
         lib.orc_tridiag_eigvals.restype = C.c_int
         lib.orc_tridiag_eigvals.argtypes = [C.c_int, P, P, C.c_int, P]
         lib.orc_lanczos.restype = C.c_int
@@ -191,6 +196,96 @@ def apply_rows(m, basis_list: np.ndarray, rows: np.ndarray, x: np.ndarray) -> np
     if rc != 0:
         raise RuntimeError("orc_apply_rows failed")
     return y[:, 0] if squeeze else y
+
+
+def rep_many(m, states):
+    """(representatives uint64 [n], in_basis bool [n]) of host states."""
+    perm, chi, *_ = _model_arrays(m)
+    s = np.ascontiguousarray(states, dtype=np.uint64)
+    n_sym = m.n_sym
+    if chi is None and n_sym:
+        chi = np.zeros((n_sym, 2))
+        chi[:, 0] = 1.0
+    reps = np.zeros(len(s), np.uint64)
+    inb = np.zeros(len(s), np.int32)
+    _load().orc_rep_many(m.n_sites, n_sym, _p(perm), _p(chi), _p(s), len(s), _p(reps), _p(inb))
+    return reps, inb.astype(bool)
+
+
+def sample_basis_states(m, n: int, seed: int) -> np.ndarray:
+    """n distinct basis states of the model's sector, ascending, drawn without
+    any basis list: random states with n_up up spins (numpy, seeded), mapped
+    to their representatives, kept when the orbit carries a symmetric state.
+    (Orbit-weighted, not uniform over the basis.)"""
+    rng = np.random.default_rng(seed)
+    out = np.zeros(0, np.uint64)
+    while len(out) < n:
+        k = max(64, 4 * (n - len(out)))
+        bits = rng.random((k, m.n_sites)).argsort(axis=1)[:, :m.n_up].astype(np.uint64)
+        states = (np.uint64(1) << bits).sum(axis=1, dtype=np.uint64)
+        reps, inb = rep_many(m, states)
+        out = np.unique(np.concatenate([out, reps[inb]]))
+    rng.shuffle(out)
+    return np.sort(out[:n])
+
+
+def rows_terms(m, states):
+    """Terms of several rows given by their states (no basis list needed).
+    Returns (diag [n], in_basis bool [n], targets list of uint64 arrays,
+    amps list of complex128 arrays)."""
+    perm, chi, sites, jz, jxy = _model_arrays(m)
+    s = np.ascontiguousarray(states, dtype=np.uint64)
+    n, nb = len(s), len(jz)
+    diag = np.zeros(n, np.float64)
+    cnt = np.zeros(n, np.int32)
+    inb = np.zeros(n, np.int32)
+    tg = np.zeros((n, nb), np.uint64)
+    am = np.zeros((n, nb, 2), np.float64)
+    n_sym = m.n_sym
+    if chi is None and n_sym:
+        chi = np.zeros((n_sym, 2))
+        chi[:, 0] = 1.0
+    rc = _load().orc_rows_terms(m.n_sites, m.n_up, n_sym, _p(perm), _p(chi), nb, _p(sites),
+                                _p(jz), _p(jxy), _p(s), n, _p(diag), _p(cnt), _p(inb), _p(tg),
+                                _p(am))
+    if rc != 0:
+        raise ValueError("orc_rows_terms: a row state has the wrong number of up spins")
+    amps = am[..., 0] + 1j * am[..., 1]
+    return diag, inb.astype(bool), cnt, tg, amps
+
+
+def apply_keyed(m, states, seed: int, nvec: int = 1, complex_: bool = False,
+                round_to_f32: bool = False) -> np.ndarray:
+    """(H x) at the rows whose basis states are `states`, for the vector whose
+    entry at basis state s is a fixed function of s alone
+    (``workloads.keyed_values``: seeded SplitMix64 of the state, U[-1, 1]).
+
+    Because x is keyed by the state and not by its position, the oracle needs
+    no basis list: each row is the diagonal plus the pull-form terms of
+    ``orc_row_terms`` weighted by x at the target states.  A device apply of
+    the same x (built from the device's own basis order) must agree at every
+    row; a wrong position anywhere in the device index gathers another
+    state's value.  Every row state must be a basis state (checked here).
+    round_to_f32: the keyed values are rounded to FP32 first (the vector as
+    an FP32 device vector holds it).  Returns [n] or [n, nvec] complex128."""
+    import workloads as W
+    s = np.ascontiguousarray(states, dtype=np.uint64)
+    diag, inb, cnt, tg, amps = rows_terms(m, s)
+    if not np.all(inb):
+        raise ValueError(f"{int(np.sum(~inb))} row states are not basis states of {m.name}")
+
+    def f(q):
+        v = W.keyed_values(seed, q, nvec=nvec, complex_=complex_)
+        if round_to_f32:
+            v = (v.astype(np.complex64) if complex_ else v.astype(np.float32)).astype(v.dtype)
+        return v.astype(np.complex128).reshape(len(q), nvec)
+
+    nb = tg.shape[1]
+    valid = np.arange(nb)[None, :] < cnt[:, None]
+    xt = np.zeros((len(s), nb, nvec), np.complex128)
+    xt[valid] = f(tg[valid])
+    y = diag[:, None] * f(s) + np.einsum("kq,kqv->kv", np.where(valid, amps, 0), xt)
+    return y[:, 0] if nvec == 1 else y
 
 
 def tridiag_eigvals(alpha, beta, k: int) -> np.ndarray:

@@ -356,6 +356,47 @@ int orc_apply_rows(int n_sites, int n_sym, const int32_t *perm, const double *ch
     return err ? -1 : 0;
 }
 
+/* Representatives of n states (orc_rep for each, OpenMP over states) and
+   whether each representative is a basis state (its orbit carries a
+   symmetric state). */
+int orc_rep_many(int n_sites, int n_sym, const int32_t *perm, const double *chi,
+                 const uint64_t *states, int64_t n, uint64_t *reps, int32_t *in_basis) {
+#pragma omp parallel for schedule(dynamic, 64)
+    for (int64_t k = 0; k < n; ++k) {
+        const uint64_t r = n_sym > 0 ? orc_rep(n_sites, n_sym, perm, states[k], NULL, NULL)
+                                     : states[k];
+        reps[k] = r;
+        in_basis[k] = n_sym == 0 || in_sym_basis(n_sites, n_sym, perm, chi, r);
+    }
+    return 0;
+}
+
+/* orc_row_terms for each of n_rows row states (OpenMP over rows), plus the
+   membership of each row state in the sector basis (a representative of an
+   orbit that carries a symmetric state; always 1 without a group).
+   Row k's terms occupy slots [k * n_bonds, k * n_bonds + cnt[k]) of targets
+   and amps (complex interleaved); diag[k] is its Sz Sz part.  Nothing here
+   needs the basis list: targets are states, not positions.  Returns 0, or
+   -1 if a row state has the wrong number of sites set. */
+int orc_rows_terms(int n_sites, int n_up, int n_sym, const int32_t *perm, const double *chi,
+                   int n_bonds, const int32_t *sites, const double *jz, const double *jxy,
+                   const uint64_t *rows, int64_t n_rows, double *diag, int32_t *cnt,
+                   int32_t *in_basis, uint64_t *targets, double *amps) {
+    int err = 0;
+#pragma omp parallel for schedule(dynamic, 16)
+    for (int64_t k = 0; k < n_rows; ++k) {
+        const uint64_t r = rows[k];
+        if (popcount64(r) != n_up) { err = 1; cnt[k] = 0; in_basis[k] = 0; continue; }
+        in_basis[k] = n_sym == 0 || in_sym_basis(n_sites, n_sym, perm, chi, r);
+        int nt = orc_row_terms(n_sites, n_sym, perm, chi, n_bonds, sites, jz, jxy, r,
+                               diag + k, targets + (size_t)k * n_bonds,
+                               amps + 2 * (size_t)k * n_bonds, n_bonds);
+        if (nt < 0) { err = 1; nt = 0; }
+        cnt[k] = nt;
+    }
+    return err ? -1 : 0;
+}
+
 /* ------------------------------------------------------------------------ */
 /* Symmetric tridiagonal eigenvalues by Sturm-sequence bisection.            */
 /* T has diagonal a[0..m) and off-diagonal b[0..m-1) (b[i] couples i, i+1).  */

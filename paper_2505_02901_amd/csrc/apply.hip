@@ -195,8 +195,13 @@ int apply_launch(xdg_ham_s *h, const void *x, void *y, int64_t nvec, int dtype, 
 // for every candidate, so the timing runs also leave the right y behind.
 int apply_tuned(xdg_ham_s *h, const void *x, void *y, int64_t nvec, int dtype, hipStream_t st) {
     TuneKey key{dtype, nvec};
+    std::unique_lock<std::mutex> lock(h->tune_mu);
     auto it = h->tuned.find(key);
-    if (it != h->tuned.end()) return apply_launch(h, x, y, nvec, dtype, st, &it->second);
+    if (it != h->tuned.end()) {
+        const LaunchCfg c = it->second;
+        lock.unlock();
+        return apply_launch(h, x, y, nvec, dtype, st, &c);
+    }
     const xdg_basis_s *b = h->basis;
     Form f;
     XDG_RETURN_IF(form_of(b, dtype, nvec, &f));

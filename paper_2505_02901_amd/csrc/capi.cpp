@@ -277,6 +277,18 @@ int xdg_ham_nnz(xdg_ham h, int64_t *nnz) {
     });
 }
 
+int xdg_ham_dim(xdg_ham h, int64_t *dim, int *is_complex) {
+    return guarded([&]() -> int {
+        if (!h) {
+            set_error("null hamiltonian");
+            return XDG_EINVAL;
+        }
+        if (dim) *dim = h->basis->dim;
+        if (is_complex) *is_complex = h->basis->is_complex ? 1 : 0;
+        return XDG_OK;
+    });
+}
+
 int xdg_apply(xdg_ham h, const void *x, void *y, int64_t nvec, int dtype, void *stream) {
     return guarded([&]() -> int {
         if (!h) {

@@ -929,6 +929,8 @@ int lanczos_batched(int n, xdg_ham_s *const *hams, const void *const *v0s, int64
     // choose the persistent grid once per set of blocks (outside capture):
     // a few sizes, timed; remembered for later calls on the same blocks
     static std::map<std::vector<const void *>, int> grid_cache;
+    static std::mutex grid_mu;   // held while the grid is looked up or tuned
+    std::unique_lock<std::mutex> grid_lock(grid_mu);
     std::vector<const void *> gkey;
     for (int i = 0; i < n; ++i) {
         gkey.push_back(hams[i]);
@@ -962,6 +964,7 @@ int lanczos_batched(int n, xdg_ham_s *const *hams, const void *const *v0s, int64
         (void)hipEventDestroy(e1);
         grid_cache[gkey] = best_grid;
     }
+    grid_lock.unlock();
     auto enqueue_step = [&](int p, bool first) -> int {
         XDG_RETURN_IF(batch_launch(plans[p], best_grid, 8, st));
         for (int i = 0; i < n; ++i) {

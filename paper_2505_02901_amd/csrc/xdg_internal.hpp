@@ -7,6 +7,7 @@
 #include <cstdint>
 #include <map>
 #include <memory>
+#include <mutex>
 #include <string>
 #include <tuple>
 #include <vector>
@@ -189,6 +190,7 @@ struct xdg_ham_s {
     xdg::DevBuf bonds_d;        // BondD [n_bonds]
     xdg::DevBuf bonds_f;        // BondF [n_bonds]
     int64_t nnz = -1;
+    std::mutex tune_mu;         // guards `tuned` (and the tuning runs that fill it)
     std::map<xdg::TuneKey, xdg::LaunchCfg> tuned;
 };
 

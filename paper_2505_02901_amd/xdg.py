@@ -73,6 +73,7 @@ def lib():
             "xdg_create_hamiltonian": (I, [P, I, P, P, P, P]),
             "xdg_destroy_hamiltonian": (None, [P]),
             "xdg_ham_nnz": (I, [P, P]),
+            "xdg_ham_dim": (I, [P, P, P]),
             "xdg_apply": (I, [P, P, P, I64, I, P]),
             "xdg_apply_batched": (I, [I, P, P, P, I64, I, P]),
             "xdg_random_state": (I, [I64, I64, U64, I, I, P, P]),
@@ -99,7 +100,8 @@ def exported_names():
             "xdg_basis_is_complex", "xdg_basis_search_kind", "xdg_basis_index_kind",
             "xdg_basis_copy_states",
             "xdg_basis_copy_stabilisers", "xdg_basis_index", "xdg_create_hamiltonian",
-            "xdg_destroy_hamiltonian", "xdg_ham_nnz", "xdg_apply", "xdg_apply_batched",
+            "xdg_destroy_hamiltonian", "xdg_ham_nnz", "xdg_ham_dim", "xdg_apply",
+            "xdg_apply_batched",
             "xdg_random_state", "xdg_lanczos_eigval", "xdg_lanczos_eigval_batched",
             "xdg_last_lanczos_timing", "xdg_lanczos_eigvec", "xdg_expect_szsz",
             "xdg_ftlm_thermo", "xdg_apply_sz_transfer", "xdg_spectral_cf"]
@@ -155,6 +157,42 @@ def _stream(stream) -> Optional[int]:
     if isinstance(stream, int):
         return stream
     return stream.cuda_stream
+
+
+def _is_tensor(t) -> bool:
+    return t is not None and not isinstance(t, int)
+
+
+def _check_vec(name: str, t, dim: int, nvec: int, dtype: Optional[int] = None) -> None:
+    """Refuse (ValueError, before any launch) a tensor that does not hold a
+    [dim][nvec] block of the expected dtype.  Raw integer pointers are passed
+    through unchecked: their size is the caller's responsibility."""
+    if not _is_tensor(t):
+        return
+    need = dim * nvec
+    if t.numel() != need:
+        raise ValueError(f"{name} has {t.numel()} elements; the block needs dim {dim} x "
+                         f"nvec {nvec} = {need}")
+    if t.dim() > 2 or (t.dim() == 2 and int(t.shape[1]) != nvec):
+        raise ValueError(f"{name} must have shape [dim] or [dim, nvec={nvec}], got "
+                         f"{tuple(t.shape)}")
+    if dtype is not None and _dtype_code(t) != dtype:
+        raise ValueError(f"{name} has dtype {t.dtype}; this call needs "
+                         f"{_DTYPE_NAMES[dtype]}")
+
+
+_DTYPE_NAMES = {XDG_F64: "float64", XDG_F32: "float32", XDG_C128: "complex128",
+                XDG_C64: "complex64"}
+
+
+def _prec_dtype(prec: int, cplx: bool) -> int:
+    single = prec in (XDG_PREC_F32VEC, XDG_PREC_F32VEC_REORTH)
+    return {(False, False): XDG_F64, (True, False): XDG_F32, (False, True): XDG_C128,
+            (True, True): XDG_C64}[(single, cplx)]
+
+
+def _same_storage(a, b) -> bool:
+    return _is_tensor(a) and _is_tensor(b) and a.data_ptr() == b.data_ptr()
 
 
 def _dtype_code(t) -> int:
@@ -284,21 +322,41 @@ def xdg_ham_nnz(h) -> int:
     return n.value
 
 
+def xdg_ham_dim(h) -> Tuple[int, bool]:
+    """(dimension of the Hamiltonian's block, whether the block is complex)."""
+    d, c = C.c_int64(), C.c_int()
+    _check(lib().xdg_ham_dim(h, C.byref(d), C.byref(c)))
+    return d.value, bool(c.value)
+
+
+def _check_apply_vectors(h, x, y, nvec: int, dtype: int, where: str = "") -> None:
+    dim, _ = xdg_ham_dim(h)
+    _check_vec(f"x{where}", x, dim, nvec, dtype)
+    _check_vec(f"y{where}", y, dim, nvec, dtype)
+    if _same_storage(x, y):
+        raise ValueError(f"x{where} and y{where} must be distinct buffers")
+
+
 def xdg_apply(h, x, y, nvec: Optional[int] = None, dtype: Optional[int] = None, stream=None):
     if nvec is None:
         nvec = 1 if x.dim() == 1 else int(x.shape[1])
     if dtype is None:
         dtype = _dtype_code(x)
+    _check_apply_vectors(h, x, y, nvec, dtype)
     _check(lib().xdg_apply(h, _ptr(x), _ptr(y), nvec, dtype, _stream(stream)))
 
 
 def xdg_apply_batched(hams: Sequence, xs: Sequence, ys: Sequence, nvec: Optional[int] = None,
                       dtype: Optional[int] = None, stream=None):
     n = len(hams)
+    if len(xs) != n or len(ys) != n:
+        raise ValueError("hams, xs and ys must have the same length")
     if nvec is None:
         nvec = 1 if xs[0].dim() == 1 else int(xs[0].shape[1])
     if dtype is None:
         dtype = _dtype_code(xs[0])
+    for i in range(n):
+        _check_apply_vectors(hams[i], xs[i], ys[i], nvec, dtype, f"[{i}]")
     H = (C.c_void_p * n)(*[h.value if isinstance(h, C.c_void_p) else h for h in hams])
     X = (C.c_void_p * n)(*[_ptr(x) for x in xs])
     Y = (C.c_void_p * n)(*[_ptr(y) for y in ys])
@@ -315,6 +373,9 @@ def xdg_random_state(out, seed: int, kind: int = 1, nvec: Optional[int] = None, 
 def xdg_lanczos_eigval(h, k: int = 1, tol: float = 1e-12, max_iter: int = 300, seed: int = 0,
                        prec: int = XDG_PREC_F64, v0=None, stream=None):
     """Returns (status, evals, alpha, beta)."""
+    if _is_tensor(v0):
+        dim, cplx = xdg_ham_dim(h)
+        _check_vec("v0", v0, dim, 1, _prec_dtype(prec, cplx))
     ev = np.zeros(k, np.float64)
     al = np.zeros(max_iter, np.float64)
     be = np.zeros(max_iter, np.float64)
@@ -332,6 +393,13 @@ def xdg_lanczos_eigval_batched(hams: Sequence, nvec: int, n_iter: int, seed: int
                                prec: int = XDG_PREC_F32VEC, v0s=None, stream=None):
     """Returns (evals [n, nvec], alpha [n, nvec, n_iter], beta [...])."""
     n = len(hams)
+    if v0s is not None:
+        if len(v0s) != n:
+            raise ValueError("one start block per Hamiltonian")
+        info = [xdg_ham_dim(h) for h in hams]
+        dt = _prec_dtype(prec, any(c for _, c in info))
+        for i, (dim, _) in enumerate(info):
+            _check_vec(f"v0s[{i}]", v0s[i], dim, nvec, dt)
     ev = np.zeros(n * nvec, np.float64)
     al = np.zeros(n * nvec * n_iter, np.float64)
     be = np.zeros(n * nvec * n_iter, np.float64)
@@ -351,6 +419,12 @@ def xdg_lanczos_eigvec(h, alpha, beta, psi, seed: int = 0, prec: int = XDG_PREC_
     be = np.ascontiguousarray(beta, dtype=np.float64)
     if len(be) < len(al):
         raise ValueError("beta needs as many entries as alpha")
+    dim, cplx = xdg_ham_dim(h)
+    dt = _prec_dtype(prec, cplx)
+    _check_vec("psi", psi, dim, 1, dt)
+    _check_vec("v0", v0, dim, 1, dt)
+    if _same_storage(psi, v0):
+        raise ValueError("psi may not alias v0")
     r = C.c_double()
     _check(lib().xdg_lanczos_eigvec(h, _ptr(v0), seed, prec, len(al),
                                     al.ctypes.data_as(C.c_void_p), be.ctypes.data_as(C.c_void_p),
@@ -364,6 +438,7 @@ def xdg_expect_szsz(b, psi, pairs, dtype: Optional[int] = None, stream=None) -> 
     out = np.zeros(len(p), np.float64)
     if dtype is None:
         dtype = _dtype_code(psi)
+    _check_vec("psi", psi, xdg_basis_dim(b), 1, dtype)
     _check(lib().xdg_expect_szsz(b, _ptr(psi), dtype, len(p), p.ctypes.data_as(C.c_void_p),
                                  out.ctypes.data_as(C.c_void_p), _stream(stream)))
     return out
@@ -394,6 +469,10 @@ def xdg_apply_sz_transfer(b_in, b_out, coef, x, y, dtype: Optional[int] = None, 
     ci[:, 0], ci[:, 1] = c.real, c.imag
     if dtype is None:
         dtype = _dtype_code(x)
+    _check_vec("x", x, xdg_basis_dim(b_in), 1, dtype)
+    _check_vec("y", y, xdg_basis_dim(b_out), 1, dtype)
+    if _same_storage(x, y):
+        raise ValueError("x and y must be distinct buffers")
     _check(lib().xdg_apply_sz_transfer(b_in, b_out, ci.ctypes.data_as(C.c_void_p), _ptr(x),
                                        _ptr(y), dtype, _stream(stream)))
     return y

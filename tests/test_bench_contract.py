@@ -21,19 +21,36 @@ def test_more_than_one_gpu_is_refused():
     assert r.stdout == ""
 
 
-def test_algorithmic_bytes_of_the_ring_apply():
-    # N = 32 ring, k = 0: 18,784,170 rows, 329,026,186 nonzeros per vector
-    # (diagonal included).  Per row: 4-byte state, 2-byte stabiliser, x[r]
-    # read and y[r] written (FP32); per off-diagonal term: the gathered x
-    # value and one index entry (4-byte key word + 4-byte position).
-    dim, nnz = 18784170, 329026186
-    per_row = 4 + 2 + 2 * 4
-    per_term = 4 + (4 + 4)
-    want = dim * per_row + (nnz - dim) * per_term
-    assert want == 3985882572
-    assert bench.alg_bytes(dim, nnz, 4, 4, 1, True) == want
-    # U(1) blocks read no stabiliser and no index entry from memory
-    assert bench.alg_bytes(10, 30, 4, 8, 2, False) == 10 * (4 + 2 * 2 * 8) + 20 * (2 * 8)
+def test_algorithmic_bytes_model():
+    """B = D (b_r + b_n + 2 nvec b_v) + T (nvec b_v + [sym] (b_p + n_probe b_k))
+    with T = D x the full-space mean number of unequal-spin bonds."""
+    # 6x6 J1-J2, Gamma A1: D = 31,566,122, 144 bonds, N = 36, n_up = 18:
+    # T/D = 144 * 2 * 18 * 18 / (36 * 35) = 74.057...; FP32: 66.0 GB
+    D = 31566122
+    tbar = 144 * 2 * 18 * 18 / (36 * 35)
+    assert abs(bench.mean_terms_full_space(36, 18, 144) - tbar) < 1e-12
+    want = D * (8 + 1 + 2 * 4) + D * tbar * (4 + 4 + 5 * 4)
+    assert bench.alg_bytes(D, 36, 18, 144, 4, 1, True) == round(want)
+    assert abs(want / 1e9 - 66.0) < 0.1
+    # N = 32 ring sector, FP32: 8.9 GB; FP64: 10.3 GB
+    assert abs(bench.alg_bytes(18784170, 32, 16, 32, 4, 1, True) / 1e9 - 8.9) < 0.1
+    assert abs(bench.alg_bytes(18784170, 32, 16, 32, 8, 1, True) / 1e9 - 10.3) < 0.1
+    # U(1) blocks read no stabiliser class ... no index entry from memory
+    assert bench.alg_bytes(10, 4, 2, 4, 8, 2, False) == round(
+        10 * (4 + 1 + 2 * 2 * 8) + 10 * (4 * 2 * 2 * 2 / 12) * (2 * 8))
+
+
+def test_roofline_bound_names_the_limiter():
+    issue = {"valu_wave_insts": 0.9 * bench.VALU_PEAK_WAVE_INSTS * 1e-3, "frac_of_launch": 0.9}
+    r = bench.roofline_entry(4e9, 1e-3, 4.0e9, issue)      # traffic 0.5 of peak, VALU 0.9
+    assert r["bound"] == "alu" and r["unit"] == "Tops/s"
+    assert abs(r["frac"] - 0.9) < 1e-9
+    assert abs(r["hbm"]["frac"] - 0.5) < 1e-9
+    issue2 = dict(issue, frac_of_launch=0.3)
+    r = bench.roofline_entry(4e9, 1e-3, 7.2e9, issue2)    # traffic 0.9 of peak, VALU 0.3
+    assert r["bound"] == "hbm" and r["unit"] == "GB/s" and abs(r["frac"] - 0.5) < 1e-9
+    r = bench.roofline_entry(4e9, 1e-3, None, None)
+    assert r["bound"] == "hbm" and r["limiter"].startswith("unknown")
 
 
 def test_counter_summaries_apply_only_to_their_sources():

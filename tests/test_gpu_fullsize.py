@@ -12,7 +12,20 @@ compute one by one, and properties that hold at any size check the rest:
 * sampled columns H e_r: the nonzeros, mapped to states through the GPU basis,
   equal the oracle's row r (Hermitian conjugate), to 1e-12 (FP64) / 2e-6 (FP32);
 * Hermiticity <w, Hx> = conj <x, Hw>, the ferromagnetic bound lambda_max =
-  sum J / 4 in the trivial sector, batched = single launches bitwise.
+  sum J / 4 in the trivial sector, batched = single launches bitwise;
+* N = 32 ring, k = 0: the oracle enumerates the whole sector; its basis equals
+  the GPU basis bit for bit, and H x on more than 1e6 random rows equals the
+  oracle's rows (FP64 to 1e-12, FP32 vectors to one FP32 rounding);
+* every other full-size sector (a complex N = 32 momentum, 6x6 J1-J2, 40-site
+  tilted): rows sampled at random are compared with the oracle through a
+  vector keyed by the basis state (``workloads.keyed_values``), which the
+  oracle evaluates without a basis list, so a wrong index position anywhere
+  shows up as a wrong row;
+* the FP32-vector ground-state energy is within |dE0| / |E0| <= 1e-7 of FP64
+  from the same start vector at 6x6 (FP64 reorthogonalisation, 200
+  iterations) and at 40 sites (100 iterations), and the batched FP32 energies
+  of all 32 momenta of the N = 32 ring against sector-by-sector FP64 and the
+  Bethe ansatz.
 """
 import numpy as np
 import pytest
@@ -129,6 +142,58 @@ def check_columns(X, m, b, H, seed, n_cols, dtypes):
                 assert abs(got[s] - np.conj(v)) <= tol * scale, (r, s, got[s], v)
 
 
+def keyed_device(b, seed, rows, cplx, dtype, nvec=1, chunk=1 << 25):
+    """Device vector whose entry at basis position i is
+    keyed_values(seed, state_i), built chunk by chunk from the device basis,
+    and the host states at `rows` (sorted positions)."""
+    D = b.dim
+    x = torch.empty((D,) if nvec == 1 else (D, nvec), dtype=dtype, device="cuda")
+    rows = np.asarray(rows, np.int64)
+    picked = np.zeros(len(rows), np.uint64)
+    for c0 in range(0, D, chunk):
+        n = min(chunk, D - c0)
+        st = b.states(c0, n)
+        sel = (rows >= c0) & (rows < c0 + n)
+        picked[sel] = st[rows[sel] - c0]
+        v = W.keyed_values_torch(seed, torch.from_numpy(st.view(np.int64)).cuda(), nvec, cplx)
+        x[c0:c0 + n] = v.to(dtype)
+        del v
+    return x, picked
+
+
+def check_keyed_rows(X, m, b, H, seed, n_rows, single_too=True):
+    """H x at sampled rows (the first and last included) against the oracle,
+    x keyed by state: FP64 to 1e-12 of the largest row, FP32 vectors (FP64
+    accumulation, one rounding on store) to 1.2e-7 of each row."""
+    D = b.dim
+    rng = np.random.default_rng(seed)
+    rows = np.unique(np.concatenate([[0, D - 1], rng.integers(0, D, n_rows)]))
+    cplx = b.is_complex
+    forms = [(torch.complex128 if cplx else torch.float64, False)]
+    if single_too:
+        forms.append((torch.complex64 if cplx else torch.float32, True))
+    want_states = None
+    for dt, f32 in forms:
+        print(f"keyed rows: {m.name} dim {D} rows {len(rows)} dtype {dt}", flush=True)
+        x, states = keyed_device(b, seed, rows, cplx, dt)
+        if want_states is None:
+            want_states = states
+        assert np.array_equal(states, want_states)
+        y = torch.empty_like(x)
+        H.apply(x, y)
+        torch.cuda.synchronize()
+        got = y[torch.from_numpy(rows).cuda()].cpu().numpy().astype(np.complex128)
+        del x, y
+        torch.cuda.empty_cache()
+        want = oracle.apply_keyed(m, states, seed, complex_=cplx, round_to_f32=f32)
+        scale = np.max(np.abs(want))
+        bound = (1.2e-7 * np.abs(want) + 1e-12 * scale) if f32 else np.full(len(want), 1e-12 * scale)
+        err = np.abs(got - want)
+        k = int(np.argmax(err / bound))
+        assert np.all(err <= bound), (m.name, dt, int(rows[k]), got[k], want[k], err[k] / scale)
+    return rows
+
+
 def test_c1_full_oracle_parity(X):
     m = W.workload("chain16_u1")[0]
     b = X.Basis.from_model(m)
@@ -155,6 +220,45 @@ def test_c2_fullsize(X, i):
     check_membership(X, m, b, 20 + i)
     check_columns(X, m, b, H, 30 + i, 4, [(torch.float64, 1e-12), (torch.float32, 2e-6)])
     check_hermitian(b, H, 60 + i)
+
+
+def test_c2_full_oracle_basis_and_rows(X):
+    """The k = 0 sector of the N = 32 ring, whole: the oracle's basis (brute
+    force over all C(32, 16) states) equals the GPU's bit for bit, and H x on
+    more than 1e6 random rows equals orc_apply_rows on that basis."""
+    m, b, H = built(X, "chain32_k0_kpi", 0)
+    print("oracle basis of chain32 k = 0 ...", flush=True)
+    basis = oracle.basis(m)
+    assert len(basis) == b.dim == 18784170
+    got = b.states()
+    assert np.array_equal(got, basis)
+    del got
+    rng = np.random.default_rng(12)
+    rows = np.unique(np.concatenate([[0, b.dim - 1], rng.integers(0, b.dim, 1_050_000)]))
+    assert len(rows) >= 1_000_000
+    x = W.random_vector(2, b.dim, kind="gauss")
+    for dt in (torch.float64, torch.float32):
+        xv = x if dt == torch.float64 else x.astype(np.float32).astype(np.float64)
+        xt = torch.from_numpy(x).to("cuda", dt)
+        yt = torch.empty_like(xt)
+        H.apply(xt, yt)
+        torch.cuda.synchronize()
+        got = yt[torch.from_numpy(rows).cuda()].double().cpu().numpy()
+        del xt, yt
+        want = oracle.apply_rows(m, basis, rows, xv).real
+        scale = np.max(np.abs(want))
+        bound = 1e-12 * scale if dt == torch.float64 else 1.2e-7 * np.abs(want) + 1e-12 * scale
+        assert np.all(np.abs(got - want) <= bound), dt
+
+
+def test_c2_complex_sector_rows(X):
+    """A complex momentum sector of the N = 32 ring (l = 5) at full size:
+    dimension, basis windows, and 2e5 random rows against the oracle."""
+    m, b, H = built(X, "chain32_allk", 5)
+    assert b.is_complex
+    assert b.dim == dimension_formula(m)
+    check_windows(m, b, 70, n_windows=2, width=1500)
+    check_keyed_rows(X, m, b, H, 71, 200_000)
 
 
 def check_hermitian(b, H, seed, fp32=True):
@@ -190,6 +294,27 @@ def test_c3_fullsize(X):
     del x, w, hx, hw
 
 
+def test_c3_sampled_rows(X):
+    """6x6 J1-J2, Gamma A1: 1e5 random rows against the oracle (FP64 and FP32)."""
+    m, b, H = built(X, "square36_j1j2_A1")
+    check_keyed_rows(X, m, b, H, 43, 100_000)
+
+
+def test_c3_fp32_ground_state(X):
+    """FP32 vectors with FP64 reorthogonalisation against FP64, same start
+    vector, 200 iterations: |dE0| / |E0| <= 1e-7."""
+    m, b, H = built(X, "square36_j1j2_A1")
+    e = {}
+    for prec in (X.XDG_PREC_F32VEC_REORTH, X.XDG_PREC_F64, X.XDG_PREC_F64_REORTH):
+        st, ev, al, be = H.lanczos(k=1, tol=0.0, max_iter=200, seed=3, prec=prec)
+        assert len(al) == 200
+        e[prec] = ev[0]
+    print("C3 E0", e, flush=True)
+    ref = e[X.XDG_PREC_F64]
+    assert abs(e[X.XDG_PREC_F32VEC_REORTH] - ref) <= 1e-7 * abs(ref), e
+    assert abs(e[X.XDG_PREC_F64_REORTH] - ref) <= 1e-9 * abs(ref), e
+
+
 def test_c3_ferromagnetic_bound(X):
     m, b, _ = built(X, "square36_j1j2_A1")
     Hn = X.Hamiltonian(b, m.sites, -m.jz, -m.jxy)
@@ -220,6 +345,63 @@ def test_c5_fullsize(X):
     check_membership(X, m, b, 51, n_members=600, n_random=600)
     check_columns(X, m, b, H, 52, 2, [(torch.float64, 1e-12)])
     check_hermitian(b, H, 53, fp32=False)
+
+
+def test_c5_sampled_rows(X):
+    """40-site tilted XXZ, T x C4: 1e5 random rows against the oracle."""
+    m, b, H = built(X, "tilted40_xxz")
+    check_keyed_rows(X, m, b, H, 54, 100_000)
+
+
+@pytest.mark.timeout(1200)
+def test_c5_fp32_ground_state(X):
+    """FP32 vectors (FP64 scalars) against FP64, same start vector, 100
+    iterations: |dE0| / |E0| <= 1e-7."""
+    m, b, H = built(X, "tilted40_xxz")
+    e = {}
+    for prec in (X.XDG_PREC_F32VEC, X.XDG_PREC_F64):
+        print(f"C5 Lanczos prec {prec}", flush=True)
+        st, ev, al, be = H.lanczos(k=1, tol=0.0, max_iter=100, seed=5, prec=prec)
+        assert len(al) == 100
+        e[prec] = ev[0]
+    print("C5 E0", e, flush=True)
+    ref = e[X.XDG_PREC_F64]
+    assert abs(e[X.XDG_PREC_F32VEC] - ref) <= 1e-7 * abs(ref), e
+
+
+@pytest.mark.timeout(1200)
+def test_c4_batched_fp32_ground_states(X):
+    """All 32 momenta x 8 vectors in the batched FP32 form (100 iterations):
+    per sector the lowest Ritz value against the sector's own single-vector
+    FP64 run (|dE0| / |E0| <= 1e-7), and k = 0 and pi against the Bethe
+    ansatz."""
+    from test_oracle_pins import bethe_energy
+    _built.clear()
+    torch.cuda.empty_cache()
+    ms = W.workload("chain32_allk")
+    bs = [X.Basis.from_model(m) for m in ms]
+    hs = [X.Hamiltonian.from_model(b, m) for b, m in zip(bs, ms)]
+    print("C4 batched FP32 Lanczos", flush=True)
+    ev, _, _ = X.xdg_lanczos_eigval_batched([h.handle for h in hs], nvec=8, n_iter=100, seed=4,
+                                            prec=X.XDG_PREC_F32VEC)
+    e_b = ev.min(axis=1)
+    torch.cuda.empty_cache()
+    e64 = []
+    for l, h in enumerate(hs):
+        st, e, al, be = h.lanczos(k=1, tol=0.0, max_iter=100, seed=400 + l, prec=X.XDG_PREC_F64)
+        e64.append(e[0])
+    e64 = np.array(e64)
+    print("C4 E0 batched FP32", e_b.tolist(), "FP64", e64.tolist(), flush=True)
+    rel = np.abs(e_b - e64) / np.abs(e64)
+    assert np.all(rel <= 1e-7), (int(np.argmax(rel)), rel.max())
+    for l, M in ((0, 16), (16, 15)):
+        exact = bethe_energy(32, M)
+        assert abs(e64[l] - exact) <= 1e-10 * abs(exact), (l, e64[l], exact)
+        assert abs(e_b[l] - exact) <= 1e-7 * abs(exact), (l, e_b[l], exact)
+    # k and -k have the same spectrum
+    assert np.max(np.abs(e64[1:16] - e64[31:16:-1])) <= 1e-9 * np.max(np.abs(e64))
+    del hs, bs
+    torch.cuda.empty_cache()
 
 
 def test_c2_ground_state_correlations(X):

@@ -338,6 +338,42 @@ def test_apply_argument_errors(X):
         X.Basis(8, 9)
 
 
+def test_binding_refuses_mismatched_tensors(X):
+    """Sizes and dtypes are checked against the block before any launch: a
+    tensor from a larger sector or an FP32 y for an FP64 x raises ValueError."""
+    m = W.chain_model(10, l=0)
+    b = X.Basis.from_model(m)
+    H = X.Hamiltonian.from_model(b, m)
+    big = X.Basis.from_model(W.chain_model(12, l=0))
+    assert X.xdg_ham_dim(H.handle) == (b.dim, False)
+    x = torch.zeros(b.dim, dtype=torch.float64, device="cuda")
+    y = torch.zeros_like(x)
+    H.apply(x, y)                                        # the right sizes pass
+    bad = [
+        (x, torch.zeros(big.dim, dtype=torch.float64, device="cuda")),   # y too long
+        (torch.zeros(b.dim - 1, dtype=torch.float64, device="cuda"), y),  # x too short
+        (x, torch.zeros(b.dim, dtype=torch.float32, device="cuda")),     # dtype mismatch
+        (torch.zeros(b.dim, 3, dtype=torch.float64, device="cuda"), y),  # nvec mismatch
+        (x, x.view(b.dim)),                                               # aliasing
+    ]
+    for xx, yy in bad:
+        with pytest.raises(ValueError):
+            H.apply(xx, yy)
+    with pytest.raises(ValueError):
+        X.xdg_apply_batched([H.handle], [x], [torch.zeros(3, dtype=torch.float64, device="cuda")])
+    with pytest.raises(ValueError):                      # start vector of the wrong form
+        H.lanczos(k=1, tol=0.0, max_iter=5, prec=X.XDG_PREC_F32VEC, v0=x)
+    with pytest.raises(ValueError):
+        H.lanczos(k=1, tol=0.0, max_iter=5, prec=X.XDG_PREC_F64, v0=x[:-1])
+    with pytest.raises(ValueError):
+        X.xdg_expect_szsz(b.handle, torch.zeros(big.dim, dtype=torch.float64, device="cuda"),
+                          [(0, 1)])
+    st, ev, al, be = H.lanczos(k=1, tol=0.0, max_iter=5, prec=X.XDG_PREC_F64)
+    with pytest.raises(ValueError):
+        X.xdg_lanczos_eigvec(H.handle, al, be, torch.zeros(b.dim, dtype=torch.float32,
+                                                           device="cuda"))
+
+
 @pytest.mark.parametrize("prec,tol", [(0, 1e-12), (1, 1e-7)])
 def test_lanczos_chain16_bethe(X, prec, tol):
     m = W.chain_model(16)
@@ -372,11 +408,16 @@ def test_lanczos_reorth_and_breakdown(X):
     want = np.linalg.eigvalsh(Hd)
     b = X.Basis.from_model(m)
     H = X.Hamiltonian.from_model(b, m)
+    got = {}
     for prec in (3, 2):
         st, ev, al, be = H.lanczos(k=3, tol=1e-14, max_iter=min(len(basis), 120), seed=4,
                                    prec=prec)
         tol = 1e-10 if prec == 3 else 1e-5
         assert np.max(np.abs(ev - want[:3])) < tol, (prec, ev, want[:3])
+        got[prec] = ev
+    # FP32 vectors (FP64 reorthogonalisation) against FP64 from the same start
+    # vector: the ground-state bound |dE0| / |E0| <= 1e-7
+    assert abs(got[2][0] - got[3][0]) <= 1e-7 * abs(got[3][0]), got
     # ferromagnetic state in the fully polarised sector: H v = E v at once,
     # beta_1 = 0 terminates after one step
     m2 = W.chain_model(8, n_up=8, l=0)
@@ -392,10 +433,15 @@ def test_batched_lanczos_matches_single(X):
     hs = [X.Hamiltonian.from_model(b, m) for b, m in zip(bs, ms)]
     ev, al, be = X.xdg_lanczos_eigval_batched([h.handle for h in hs], nvec=4, n_iter=60, seed=9,
                                               prec=1)
+    ev64, _, _ = X.xdg_lanczos_eigval_batched([h.handle for h in hs], nvec=4, n_iter=60, seed=9,
+                                              prec=0)
     for i, (m, b) in enumerate(zip(ms, bs)):
         basis = oracle_basis(m)
         e0 = np.linalg.eigvalsh(oracle.apply(m, basis, np.eye(len(basis), dtype=complex)))[0]
         assert np.max(np.abs(ev[i] - e0)) < 1e-6 * max(1, abs(e0)), (i, ev[i], e0)
+        assert np.max(np.abs(ev64[i] - e0)) < 1e-11 * max(1, abs(e0)), (i, ev64[i], e0)
+        # FP32 vectors against FP64 from the same start vectors: |dE0|/|E0| <= 1e-7
+        assert abs(ev[i].min() - ev64[i].min()) <= 1e-7 * abs(e0), (i, ev[i], ev64[i])
 
 
 # ------------------------------------------ second Lanczos pass, measurements

@@ -544,3 +544,90 @@ def test_dynamical_sum_rule_matches_static_correlations(oracle_lib):
     # q = 0: S^z_tot |0> = 0 at Sz = 0, so no weight at all
     E0, dE, w = oracle_lib.dense_sz_spectrum(m_u1, np.ones(N) / np.sqrt(N))
     assert w.sum() < 1e-24
+
+
+# ------------------------------------------------- row-sampled oracle forms --
+
+def row_sample_models():
+    """A real ring sector, a complex momentum sector, a dihedral sector, the
+    4x4 J1-J2 torus (non-abelian T x C4v, two irreps) and a complex
+    3-sublattice lattice."""
+    perm = W.chain_dihedral(10)
+    chi = np.array([1.0] * 10 + [-1.0] * 10, dtype=np.complex128)
+    return [W.chain_model(14, l=0), W.chain_model(14, l=5),
+            W.chain_model(10).with_sector(perm, chi, "dihedral10_odd"),
+            W.torus_model((4, 0), (0, 4), 1.0, 0.5, "A1"),
+            W.torus_model((4, 0), (0, 4), 1.0, 0.5, "B2"),
+            W.sublattice_model("triangle3", (4, -2), (2, 2), rot_char=np.exp(1j * np.pi / 3),
+                               name="triangle3_12_E"),
+            W.chain_model(12)]
+
+
+@pytest.mark.parametrize("idx", range(len(row_sample_models())))
+@pytest.mark.parametrize("nvec", [1, 3])
+def test_apply_rows_equals_apply(oracle_lib, idx, nvec):
+    """orc_apply_rows (the form the CPU baseline times) against orc_apply,
+    which the projected-Hamiltonian tests pin to the definition."""
+    m = row_sample_models()[idx]
+    b = oracle_lib.basis(m)
+    rng = np.random.default_rng(idx)
+    x = W.random_vector(11 + idx, len(b), nvec, kind="gauss", complex_=True)
+    full = oracle_lib.apply(m, b, x)
+    rows = np.sort(rng.choice(len(b), size=min(len(b), 97), replace=False))
+    rows = np.concatenate([[0], rows, [len(b) - 1]])
+    got = oracle_lib.apply_rows(m, b, rows, x)
+    assert np.max(np.abs(got - full[rows])) <= 1e-14 * np.max(np.abs(full))
+
+
+@pytest.mark.parametrize("idx", range(len(row_sample_models())))
+@pytest.mark.parametrize("nvec,cplx,f32", [(1, False, False), (1, True, False), (3, True, True),
+                                           (2, False, True)])
+def test_apply_keyed_equals_apply(oracle_lib, idx, nvec, cplx, f32):
+    """The basis-free form (x keyed by state, rows given by their states)
+    against orc_apply on the same vector laid out in basis order."""
+    m = row_sample_models()[idx]
+    if m.is_complex and not cplx:
+        pytest.skip("complex sector needs a complex vector")
+    b = oracle_lib.basis(m)
+    x = W.keyed_values(21, b, nvec=nvec, complex_=cplx)
+    if f32:
+        x = (x.astype(np.complex64) if cplx else x.astype(np.float32)).astype(x.dtype)
+    full = oracle_lib.apply(m, b, x)
+    rng = np.random.default_rng(100 + idx)
+    rows = np.sort(rng.choice(len(b), size=min(len(b), 80), replace=False))
+    got = oracle_lib.apply_keyed(m, b[rows], 21, nvec=nvec, complex_=cplx, round_to_f32=f32)
+    assert got.shape == full[rows].shape
+    assert np.max(np.abs(got - full[rows])) <= 1e-14 * np.max(np.abs(full))
+
+
+def test_apply_keyed_rejects_non_basis_rows(oracle_lib):
+    m = W.chain_model(12, l=0)
+    b = oracle_lib.basis(m)
+    full = oracle_lib.full_states(12, 6)
+    nonrep = np.setdiff1d(full, b)[:3]
+    with pytest.raises(ValueError):
+        oracle_lib.apply_keyed(m, nonrep, 1)
+    with pytest.raises(ValueError):          # wrong number of up spins
+        oracle_lib.apply_keyed(m, np.array([7], np.uint64), 1)
+
+
+def test_rep_many_and_sampled_states(oracle_lib):
+    """The batched representative search equals the single-state one, and the
+    basis-free row sampler returns basis states only."""
+    for m in (W.torus_model((4, 0), (0, 4), 1.0, 0.5, "B1"), W.chain_model(14, l=5),
+              W.chain_model(12)):
+        rng = np.random.default_rng(3)
+        full = oracle_lib.full_states(m.n_sites, m.n_up)
+        states = full[rng.integers(0, len(full), 300)]
+        reps, inb = oracle_lib.rep_many(m, states)
+        b = oracle_lib.basis(m)
+        for t, r, ok in zip(states, reps, inb):
+            if m.perm is None:
+                assert r == t and ok
+                continue
+            assert r == oracle_lib.rep(m.n_sites, m.perm, int(t))[0]
+            assert ok == (abs(oracle_lib.stabiliser_character_sum(m, int(r))) > 0.5)
+            assert ok == (oracle_lib.index(b, int(r)) >= 0)
+        got = oracle_lib.sample_basis_states(m, min(50, len(b)), 7)
+        assert len(got) == min(50, len(b)) and np.all(np.diff(got.astype(np.int64)) > 0)
+        assert all(oracle_lib.index(b, int(s)) >= 0 for s in got)

@@ -438,3 +438,65 @@ def random_vector(seed: int, dim: int, nvec: int = 1, kind: str = "gauss",
         v = s
     v = v.reshape(dim, nvec)
     return v[:, 0].copy() if nvec == 1 else v
+
+
+# --------------------------------------------------------------------------
+# Vectors keyed by basis state.  Entry v (column) of the vector at the basis
+# state s is scalar q = (s * nvec + v) * C + c of the seeded stream above
+# (C = 2 for complex, c = 0 re / 1 im), drawn as U[-1, 1]: 2 u(2q+1) - 1.
+# The value depends on the state, not on its position in a basis, so a
+# checker that knows only states (no basis list) can evaluate x anywhere.
+# --------------------------------------------------------------------------
+
+def keyed_values(seed: int, states, nvec: int = 1, complex_: bool = False) -> np.ndarray:
+    """Keyed vector entries for host states: [n] (nvec == 1) or [n, nvec],
+    float64 or complex128."""
+    s = np.ascontiguousarray(states, dtype=np.uint64).reshape(-1)
+    C = 2 if complex_ else 1
+    q = ((s[:, None] * np.uint64(nvec) + np.arange(nvec, dtype=np.uint64)[None, :])
+         * np.uint64(C))
+    if complex_:
+        re = 2.0 * _uniform53(seed, 2 * q + 1) - 1.0
+        im = 2.0 * _uniform53(seed, 2 * (q + np.uint64(1)) + 1) - 1.0
+        v = re + 1j * im
+    else:
+        v = 2.0 * _uniform53(seed, 2 * q + 1) - 1.0
+    return v[:, 0].copy() if nvec == 1 else v
+
+
+_I64 = 1 << 64
+
+
+def _signed(c: int) -> int:
+    return c - _I64 if c >= 1 << 63 else c
+
+
+def keyed_values_torch(seed: int, states, nvec: int = 1, complex_: bool = False):
+    """The same keyed entries for a torch int64 tensor of states (on any
+    device), as float64 / complex128 [n] or [n, nvec].  Two's-complement
+    int64 arithmetic gives the uint64 products modulo 2^64; right shifts are
+    made logical by masking."""
+    import torch
+    s = states.to(torch.int64).reshape(-1)
+    dev = s.device
+    C = 2 if complex_ else 1
+    v = torch.arange(nvec, dtype=torch.int64, device=dev)
+
+    def srl(z, k):
+        return (z >> k) & ((1 << (64 - k)) - 1)
+
+    def u53(n):
+        z = n * _signed(int(_GAMMA)) + _signed(seed & (_I64 - 1))
+        z = z ^ srl(z, 30)
+        z = z * _signed(int(_M1))
+        z = z ^ srl(z, 27)
+        z = z * _signed(int(_M2))
+        z = z ^ srl(z, 31)
+        return srl(z, 11).to(torch.float64) * (1.0 / 9007199254740992.0)
+
+    q = (s[:, None] * nvec + v[None, :]) * C
+    if complex_:
+        out = torch.complex(2.0 * u53(2 * q + 1) - 1.0, 2.0 * u53(2 * (q + 1) + 1) - 1.0)
+    else:
+        out = 2.0 * u53(2 * q + 1) - 1.0
+    return out[:, 0].contiguous() if nvec == 1 else out
