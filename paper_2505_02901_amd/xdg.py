@@ -192,7 +192,10 @@ def _prec_dtype(prec: int, cplx: bool) -> int:
 
 
 def _same_storage(a, b) -> bool:
-    return _is_tensor(a) and _is_tensor(b) and a.data_ptr() == b.data_ptr()
+    """Both tensors hold elements and start at the same address (empty
+    tensors have no storage to share)."""
+    return (_is_tensor(a) and _is_tensor(b) and a.numel() > 0 and b.numel() > 0
+            and a.data_ptr() == b.data_ptr())
 
 
 def _dtype_code(t) -> int:

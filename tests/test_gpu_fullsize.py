@@ -398,8 +398,9 @@ def test_c4_batched_fp32_ground_states(X):
         exact = bethe_energy(32, M)
         assert abs(e64[l] - exact) <= 1e-10 * abs(exact), (l, e64[l], exact)
         assert abs(e_b[l] - exact) <= 1e-7 * abs(exact), (l, e_b[l], exact)
-    # k and -k have the same spectrum
-    assert np.max(np.abs(e64[1:16] - e64[31:16:-1])) <= 1e-9 * np.max(np.abs(e64))
+    # k and -k have the same spectrum (to the convergence of 100 iterations
+    # from different start vectors: a few 1e-9 relative in the slowest sectors)
+    assert np.max(np.abs(e64[1:16] - e64[31:16:-1])) <= 1e-8 * np.max(np.abs(e64))
     del hs, bs
     torch.cuda.empty_cache()
 

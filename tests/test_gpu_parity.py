@@ -330,8 +330,10 @@ def test_apply_argument_errors(X):
     with pytest.raises(X.XdgError):          # real vector on a complex block
         H.apply(x, torch.zeros_like(x))
     xc = torch.zeros(b.dim, dtype=torch.complex128, device="cuda")
-    with pytest.raises(X.XdgError):          # x == y
+    with pytest.raises(ValueError):          # x == y, refused by the binding
         X.xdg_apply(H.handle, xc, xc)
+    with pytest.raises(X.XdgError):          # x == y as raw pointers: refused by the C ABI
+        X.xdg_apply(H.handle, xc.data_ptr(), xc.data_ptr(), nvec=1, dtype=X.XDG_C128)
     with pytest.raises(X.XdgError):          # bonds not invariant
         X.Hamiltonian(b, m.sites[:-1], m.jz[:-1], m.jxy[:-1])
     with pytest.raises(X.XdgError):
