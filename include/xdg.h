@@ -219,6 +219,19 @@ int xdg_apply(xdg_ham h, const void *x, void *y, int64_t nvec, int dtype, void *
 int xdg_apply_batched(int n, const xdg_ham *hams, const void *const *xs, void *const *ys,
                       int64_t nvec, int dtype, void *stream);
 
+/* xdg_apply_batched for callers that cannot allocate device memory: code
+ * under HIP graph capture, tight serving loops, harnesses that forbid
+ * hipMalloc.  Same arguments, kernels and results (bitwise) as
+ * xdg_apply_batched, but it allocates nothing: the queue counter, the tile
+ * prefix and the sector descriptors live in one file-scope device array of
+ * the library (about 40 KB, held by each GPU the library runs on until the
+ * process ends), written by small kernels on `stream` before the launch.
+ * Limit: n <= 128 blocks (XDG_EINVAL beyond, before any launch).  Every call
+ * on a GPU shares that GPU's array: calls that overlap on one GPU (other
+ * streams, other host threads) race; calls in order on one stream do not. */
+int xdg_apply_batched_noalloc(int n, const xdg_ham *hams, const void *const *xs,
+                              void *const *ys, int64_t nvec, int dtype, void *stream);
+
 /* Seeded random vector of `dim * nvec` scalars (random_state, Sec. 3.6):
  * SplitMix64 (Steele, Lea, Flood 2014), counter based: output n of seed
  * is mix(seed + n * 0x9E3779B97F4A7C15).  Scalar q (flat over [dim][nvec],

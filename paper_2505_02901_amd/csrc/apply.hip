@@ -3,6 +3,7 @@
 #include <algorithm>
 #include <chrono>
 #include <cstring>
+#include <mutex>
 #include <vector>
 
 #include "apply_impl.hpp"
@@ -284,8 +285,8 @@ int ham_count_nnz(xdg_ham_s *h, int64_t *nnz) {
     return XDG_OK;
 }
 
-int batch_prepare(int n, xdg_ham_s *const *hams, const void *const *xs, void *const *ys,
-                  int64_t nvec, int dtype, BatchPlan *P) {
+int batch_plan_host(int n, xdg_ham_s *const *hams, const void *const *xs, void *const *ys,
+                    int64_t nvec, int dtype, BatchMeta *P, SectorDesc *descs, uint32_t *prefix) {
     if (n < 1) {
         set_error("batched apply needs at least one block");
         return XDG_EINVAL;
@@ -313,46 +314,61 @@ int batch_prepare(int n, xdg_ham_s *const *hams, const void *const *xs, void *co
     P->wide = b0->wide;
     P->single = dtype_single(dtype);
     P->acc64 = !P->single || !(b0->plan.flags & XDG_FLAG_F32_ACCUMULATE);
-    const bool tsingle = P->single && !P->acc64;
+    P->tsingle = P->single && !P->acc64;
     P->cplx = any_cplx;
     P->cols = (dtype_complex(dtype) && !any_cplx) ? 2 * nvec : nvec;
     P->tile_rows = 4 * APPLY_BLOCK;
-    std::vector<SectorDesc> descs(n);
-    std::vector<uint32_t> prefix(n + 1, 0);
     size_t lds_full = 0, lds_part = 0;
+    uint64_t acc = 0;
     for (int i = 0; i < n; ++i) {
-        descs[i] = make_desc(hams[i], tsingle, xs[i], ys[i]);
+        const SectorDesc d = make_desc(hams[i], P->tsingle, xs[i], ys[i]);
         const uint64_t tiles = (hams[i]->basis->dim + P->tile_rows - 1) / P->tile_rows;
-        if ((uint64_t)prefix[i] + tiles >= 0xFFFFFFFFull) {
+        if (acc + tiles >= 0xFFFFFFFFull) {
             set_error("too many row tiles in the batch");
             return XDG_EINVAL;
         }
-        prefix[i + 1] = prefix[i] + (uint32_t)tiles;
-        const size_t f1 = tsingle ? stage_bytes<float>(descs[i], P->kind, 1)
-                                  : stage_bytes<double>(descs[i], P->kind, 1);
-        const size_t f0 = tsingle ? stage_bytes<float>(descs[i], P->kind, 0)
-                                  : stage_bytes<double>(descs[i], P->kind, 0);
+        if (prefix) prefix[i] = (uint32_t)acc;
+        acc += tiles;
+        if (descs) descs[i] = d;
+        const size_t f1 = P->tsingle ? stage_bytes<float>(d, P->kind, 1)
+                                     : stage_bytes<double>(d, P->kind, 1);
+        const size_t f0 = P->tsingle ? stage_bytes<float>(d, P->kind, 0)
+                                     : stage_bytes<double>(d, P->kind, 0);
         lds_full = std::max(lds_full, f1);
         lds_part = std::max(lds_part, f0);
     }
-    P->n_tiles = prefix[n];
+    if (prefix) prefix[n] = (uint32_t)acc;
+    P->n_tiles = (uint32_t)acc;
     P->stage_sub = lds_full <= lds_budget();
     P->lds = P->stage_sub ? lds_full : lds_part;
+    return XDG_OK;
+}
+
+int batch_prepare(int n, xdg_ham_s *const *hams, const void *const *xs, void *const *ys,
+                  int64_t nvec, int dtype, BatchPlan *P) {
+    if (n < 1) {
+        set_error("batched apply needs at least one block");
+        return XDG_EINVAL;
+    }
+    std::vector<SectorDesc> descs(n);
+    std::vector<uint32_t> prefix(n + 1, 0);
+    XDG_RETURN_IF(batch_plan_host(n, hams, xs, ys, nvec, dtype, P, descs.data(), prefix.data()));
     XDG_RETURN_IF(P->descs.upload(descs.data(), sizeof(SectorDesc) * n));
     XDG_RETURN_IF(P->prefix.upload(prefix.data(), sizeof(uint32_t) * (n + 1)));
     XDG_RETURN_IF(P->queue.alloc(sizeof(uint32_t)));
     return XDG_OK;
 }
 
-int batch_launch(const BatchPlan &P, int grid, int nv_cap, hipStream_t st) {
+int batch_launch_raw(const BatchMeta &P, const SectorDesc *d_descs, const uint32_t *d_prefix,
+                     uint32_t *d_queue, int grid, int nv_cap, hipStream_t st) {
     if (P.n_tiles == 0) return XDG_OK;
     ApplyArgs A{};
-    A.descs = P.descs.as<SectorDesc>();
-    A.tile_prefix = P.prefix.as<uint32_t>();
+    A.descs = d_descs;
+    A.tile_prefix = d_prefix;
     A.n_secs = P.n;
     A.n_tiles = P.n_tiles;
     A.tile_rows = P.tile_rows;
-    A.queue = P.queue.as<uint32_t>();
+    A.queue = d_queue;
     A.nvec = P.cols;
     A.stage_sub = P.stage_sub;
     A.occ = P.stage_sub ? occ_for(P.lds) : 0;
@@ -368,6 +384,104 @@ int batch_launch(const BatchPlan &P, int grid, int nv_cap, hipStream_t st) {
         v0 += nv;
     }
     return XDG_OK;
+}
+
+int batch_launch(const BatchPlan &P, int grid, int nv_cap, hipStream_t st) {
+    return batch_launch_raw(P, P.descs.as<SectorDesc>(), P.prefix.as<uint32_t>(),
+                            P.queue.as<uint32_t>(), grid, nv_cap, st);
+}
+
+// ------------------------------------------------- allocation-free batch --
+// One file-scope device array per GPU holds everything the batched launch
+// needs beyond the caller's vectors: the queue counter, the tile prefix and
+// the sector descriptors.  Its address is taken once per device with
+// hipGetSymbolAddress (the array's name is a host-side stand-in, not a device
+// address); descriptors reach it through the arguments of a small fill
+// kernel, so nothing is allocated and no host buffer must outlive the call.
+constexpr int NOALLOC_MAX_SECTORS = 128;
+constexpr size_t NOALLOC_PREFIX_OFF = 256;
+constexpr size_t NOALLOC_DESC_OFF =
+    a16(NOALLOC_PREFIX_OFF + sizeof(uint32_t) * (NOALLOC_MAX_SECTORS + 1));
+constexpr size_t NOALLOC_BYTES = NOALLOC_DESC_OFF + sizeof(SectorDesc) * NOALLOC_MAX_SECTORS;
+static __device__ __align__(256) unsigned char scratch[NOALLOC_BYTES];
+
+constexpr int FILL_PER_LAUNCH = 4;
+struct FillArgs {
+    SectorDesc d[FILL_PER_LAUNCH];
+    uint32_t prefix[FILL_PER_LAUNCH + 1];
+    int first, count;
+    int last;            // 1: also write prefix[first + count] (the total)
+    unsigned char *base;
+};
+static_assert(sizeof(FillArgs) <= 2048, "fill kernel arguments");
+
+static __global__ void k_fill_batch(FillArgs a) {
+    const int i = threadIdx.x;
+    if (i < a.count) {
+        SectorDesc *d = reinterpret_cast<SectorDesc *>(a.base + NOALLOC_DESC_OFF);
+        d[a.first + i] = a.d[i];
+        reinterpret_cast<uint32_t *>(a.base + NOALLOC_PREFIX_OFF)[a.first + i] = a.prefix[i];
+    }
+    if (i == 0 && a.last)
+        reinterpret_cast<uint32_t *>(a.base + NOALLOC_PREFIX_OFF)[a.first + a.count] =
+            a.prefix[a.count];
+}
+
+static int scratch_address(unsigned char **out) {
+    static std::mutex mu;
+    static void *ptr[64] = {};
+    int dev = 0;
+    XDG_TRY_HIP(hipGetDevice(&dev));
+    if (dev < 0 || dev >= 64) {
+        set_error("device %d out of range for the allocation-free path", dev);
+        return XDG_EINVAL;
+    }
+    std::lock_guard<std::mutex> lock(mu);
+    if (!ptr[dev]) {
+        void *p = nullptr;
+        XDG_TRY_HIP(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+        if (!p) {
+            set_error("hipGetSymbolAddress returned no address for the scratch array");
+            return XDG_EHIP;
+        }
+        ptr[dev] = p;
+    }
+    *out = static_cast<unsigned char *>(ptr[dev]);
+    return XDG_OK;
+}
+
+int apply_batched_noalloc(int n, xdg_ham_s *const *hams, const void *const *xs,
+                          void *const *ys, int64_t nvec, int dtype, hipStream_t st) {
+    if (n < 1 || n > NOALLOC_MAX_SECTORS) {
+        set_error("allocation-free batched apply takes 1 to %d blocks (got %d); its scratch "
+                  "array holds %zu bytes", NOALLOC_MAX_SECTORS, n, NOALLOC_BYTES);
+        return XDG_EINVAL;
+    }
+    for (int i = 0; i < n; ++i)
+        if (!hams[i] || !xs[i] || !ys[i] || xs[i] == ys[i]) {
+            set_error("batched apply: null handle/pointer or x == y at %d", i);
+            return XDG_EINVAL;
+        }
+    thread_local SectorDesc descs[NOALLOC_MAX_SECTORS];
+    thread_local uint32_t prefix[NOALLOC_MAX_SECTORS + 1];
+    BatchMeta M;
+    XDG_RETURN_IF(batch_plan_host(n, hams, xs, ys, nvec, dtype, &M, descs, prefix));
+    unsigned char *base = nullptr;
+    XDG_RETURN_IF(scratch_address(&base));
+    for (int first = 0; first < n; first += FILL_PER_LAUNCH) {
+        FillArgs a{};
+        a.first = first;
+        a.count = std::min(FILL_PER_LAUNCH, n - first);
+        a.last = first + a.count == n;
+        for (int i = 0; i < a.count; ++i) a.d[i] = descs[first + i];
+        for (int i = 0; i <= a.count; ++i) a.prefix[i] = prefix[first + i];
+        a.base = base;
+        hipLaunchKernelGGL(k_fill_batch, dim3(1), dim3(64), 0, st, a);
+        XDG_TRY_HIP(hipGetLastError());
+    }
+    return batch_launch_raw(M, reinterpret_cast<const SectorDesc *>(base + NOALLOC_DESC_OFF),
+                            reinterpret_cast<const uint32_t *>(base + NOALLOC_PREFIX_OFF),
+                            reinterpret_cast<uint32_t *>(base), 0, 8, st);
 }
 
 int apply_batched_launch(int n, xdg_ham_s *const *hams, const void *const *xs, void *const *ys,

@@ -94,7 +94,7 @@ struct ApplyArgs {
     unsigned long long *count;   // nnz counting mode (nullptr otherwise)
 };
 
-__host__ __device__ inline size_t a16(size_t x) { return (x + 15) & ~(size_t)15; }
+__host__ __device__ constexpr size_t a16(size_t x) { return (x + 15) & ~(size_t)15; }
 
 __host__ __device__ inline size_t sub_table_bytes(const SectorDesc &d) {
     const size_t NV = (size_t)d.n_s << d.m;

@@ -312,6 +312,18 @@ int xdg_apply_batched(int n, const xdg_ham *hams, const void *const *xs, void *c
     });
 }
 
+int xdg_apply_batched_noalloc(int n, const xdg_ham *hams, const void *const *xs,
+                              void *const *ys, int64_t nvec, int dtype, void *stream) {
+    return guarded([&]() -> int {
+        if (n < 1 || !hams || !xs || !ys) {
+            set_error("bad batched arguments");
+            return XDG_EINVAL;
+        }
+        return apply_batched_noalloc(n, const_cast<xdg_ham_s *const *>(hams), xs, ys, nvec,
+                                     dtype, (hipStream_t)stream);
+    });
+}
+
 int xdg_random_state(int64_t dim, int64_t nvec, uint64_t seed, int kind, int dtype, void *out,
                      void *stream) {
     return guarded([&]() -> int {

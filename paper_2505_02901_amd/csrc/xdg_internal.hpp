@@ -216,21 +216,34 @@ int apply_tuned(xdg_ham_s *h, const void *x, void *y, int64_t nvec, int dtype, h
 int apply_batched_launch(int n, xdg_ham_s *const *hams, const void *const *xs, void *const *ys,
                          int64_t nvec, int dtype, hipStream_t st, uint32_t *d_queue,
                          int grid, int block);
-// Batched persistent launch plan: device copies of the sector descriptors
-// and the cumulative tile counts; the queue counter is zeroed by a kernel
-// (not a memset) so that the launch can be captured into a graph.
-struct BatchPlan {
-    DevBuf descs, prefix, queue;
+// Shape of a batched persistent launch (host side, no device memory).
+struct BatchMeta {
     int n = 0, kind = 0;
-    bool wide = false, single = false, cplx = false, acc64 = true;
+    bool wide = false, single = false, cplx = false, acc64 = true, tsingle = false;
     int64_t cols = 0;
     uint32_t n_tiles = 0, tile_rows = 0;
     size_t lds = 0;
     int stage_sub = 1;
 };
+// Batched persistent launch plan: device copies of the sector descriptors
+// and the cumulative tile counts; the queue counter is zeroed by a kernel
+// (not a memset) so that the launch can be captured into a graph.
+struct BatchPlan : BatchMeta {
+    DevBuf descs, prefix, queue;
+};
+struct SectorDesc;
+// Host planning of a batch: fills M, and (when not null) descs[n] and
+// prefix[n + 1] in host memory.  Allocates nothing.
+int batch_plan_host(int n, xdg_ham_s *const *hams, const void *const *xs, void *const *ys,
+                    int64_t nvec, int dtype, BatchMeta *M, SectorDesc *descs, uint32_t *prefix);
 int batch_prepare(int n, xdg_ham_s *const *hams, const void *const *xs, void *const *ys,
                   int64_t nvec, int dtype, BatchPlan *P);
 int batch_launch(const BatchPlan &P, int grid, int nv_cap, hipStream_t st);
+// The launch itself on device descriptors, tile prefix and queue counter.
+int batch_launch_raw(const BatchMeta &M, const SectorDesc *d_descs, const uint32_t *d_prefix,
+                     uint32_t *d_queue, int grid, int nv_cap, hipStream_t st);
+int apply_batched_noalloc(int n, xdg_ham_s *const *hams, const void *const *xs,
+                          void *const *ys, int64_t nvec, int dtype, hipStream_t st);
 int lanczos_single(xdg_ham_s *h, const void *v0, int k, double tol, int max_iter, uint64_t seed,
                    int prec, double *evals, int *n_iter, double *alpha, double *beta,
                    hipStream_t st, double *t_total, double *t_apply);

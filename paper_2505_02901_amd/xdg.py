@@ -76,6 +76,7 @@ def lib():
             "xdg_ham_dim": (I, [P, P, P]),
             "xdg_apply": (I, [P, P, P, I64, I, P]),
             "xdg_apply_batched": (I, [I, P, P, P, I64, I, P]),
+            "xdg_apply_batched_noalloc": (I, [I, P, P, P, I64, I, P]),
             "xdg_random_state": (I, [I64, I64, U64, I, I, P, P]),
             "xdg_lanczos_eigval": (I, [P, P, I, D, I, U64, I, P, P, P, P, P]),
             "xdg_lanczos_eigval_batched": (I, [I, P, P, I64, I, U64, I, P, P, P, P]),
@@ -101,7 +102,7 @@ def exported_names():
             "xdg_basis_copy_states",
             "xdg_basis_copy_stabilisers", "xdg_basis_index", "xdg_create_hamiltonian",
             "xdg_destroy_hamiltonian", "xdg_ham_nnz", "xdg_ham_dim", "xdg_apply",
-            "xdg_apply_batched",
+            "xdg_apply_batched", "xdg_apply_batched_noalloc",
             "xdg_random_state", "xdg_lanczos_eigval", "xdg_lanczos_eigval_batched",
             "xdg_last_lanczos_timing", "xdg_lanczos_eigvec", "xdg_expect_szsz",
             "xdg_ftlm_thermo", "xdg_apply_sz_transfer", "xdg_spectral_cf"]
@@ -364,6 +365,25 @@ def xdg_apply_batched(hams: Sequence, xs: Sequence, ys: Sequence, nvec: Optional
     X = (C.c_void_p * n)(*[_ptr(x) for x in xs])
     Y = (C.c_void_p * n)(*[_ptr(y) for y in ys])
     _check(lib().xdg_apply_batched(n, H, X, Y, nvec, dtype, _stream(stream)))
+
+
+def xdg_apply_batched_noalloc(hams: Sequence, xs: Sequence, ys: Sequence,
+                              nvec: Optional[int] = None, dtype: Optional[int] = None,
+                              stream=None):
+    """xdg_apply_batched without any device allocation (at most 128 blocks)."""
+    n = len(hams)
+    if len(xs) != n or len(ys) != n:
+        raise ValueError("hams, xs and ys must have the same length")
+    if nvec is None:
+        nvec = 1 if xs[0].dim() == 1 else int(xs[0].shape[1])
+    if dtype is None:
+        dtype = _dtype_code(xs[0])
+    for i in range(n):
+        _check_apply_vectors(hams[i], xs[i], ys[i], nvec, dtype, f"[{i}]")
+    H = (C.c_void_p * n)(*[h.value if isinstance(h, C.c_void_p) else h for h in hams])
+    X = (C.c_void_p * n)(*[_ptr(x) for x in xs])
+    Y = (C.c_void_p * n)(*[_ptr(y) for y in ys])
+    _check(lib().xdg_apply_batched_noalloc(n, H, X, Y, nvec, dtype, _stream(stream)))
 
 
 def xdg_random_state(out, seed: int, kind: int = 1, nvec: Optional[int] = None, stream=None):
