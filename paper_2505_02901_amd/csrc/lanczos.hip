@@ -197,69 +197,176 @@ __global__ void k_set_scalars(int *jdev, double *prev_beta, int nv) {
     if (threadIdx.x == 0) *jdev = 0;
 }
 
-// Reorthogonalisation, single vector.  c_i = <V_i, w> (complex when C = 2)
-// for i < k, accumulated in FP64 over contiguous row ranges per block.
+// Reorthogonalisation of one vector against the stored Krylov vectors V_i,
+// i < k (classical Gram-Schmidt: the coefficients c_i = <V_i, w> first, then
+// w -= sum_i c_i V_i; complex when C = 2, conj(V_i) in the product).  Both
+// kernels stream row tiles: each thread owns RU 16-byte chunks of a tile
+// (L = 16 / sizeof(T) scalars each, consecutive threads on consecutive
+// chunks), so a block covers RB * RU * L scalars and a column is read with
+// RU independent 16-byte loads per thread; G columns are in flight at once.
+// Sums are FP64 in a fixed order (bitwise reproducible).
+constexpr int RU = 4;   // 16-byte chunks per thread and column
+constexpr int RG = 4;   // columns per step
+
+template <class T> struct Chunk16;
+template <> struct Chunk16<float> {
+    typedef float type __attribute__((ext_vector_type(4)));
+};
+template <> struct Chunk16<double> {
+    typedef double type __attribute__((ext_vector_type(2)));
+};
+
+template <class T>
+constexpr int tile_scalars() { return RB * RU * (16 / (int)sizeof(T)); }
+
+// scalars [q, q + L) of column `col` (zero beyond n): one 16-byte load when
+// the chunk is whole, scalar loads at the ragged end
+template <class T>
+__device__ __forceinline__ void load_chunk(const T *col, uint64_t q, uint64_t n, T *out) {
+    constexpr int L = 16 / (int)sizeof(T);
+    if (q + L <= n) {
+        typedef typename Chunk16<T>::type V16;
+        const V16 v = *(const __attribute__((address_space(1))) V16 *)(col + q);
+#pragma unroll
+        for (int e = 0; e < L; ++e) out[e] = v[e];
+    } else {
+#pragma unroll
+        for (int e = 0; e < L; ++e) out[e] = q + e < n ? col[q + e] : T(0);
+    }
+}
+
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+    for (int o = 32; o >= 1; o >>= 1) v += __shfl_xor(v, o, 64);
+    return v;
+}
+
+// partials[(i C + c) nb + block] = the block's share of Re / Im <V_i, w>
 template <class T, int C>
 __global__ __launch_bounds__(RB) void k_reorth_dots(const T *V, uint64_t ld, int k, const T *w,
-                                                    uint64_t n_rows, double *partials) {
-    __shared__ double sh[RB];
-    const uint64_t per = (n_rows + gridDim.x - 1) / gridDim.x;
-    const uint64_t r0 = (uint64_t)blockIdx.x * per;
-    const uint64_t r1 = r0 + per < n_rows ? r0 + per : n_rows;
-    for (int i = 0; i < k; ++i) {
-        const T *Vi = V + (size_t)i * ld;
-        double re = 0.0, im = 0.0;
-        for (uint64_t r = r0 + threadIdx.x; r < r1; r += RB) {
-            if (C == 1) {
-                re += (double)Vi[r] * (double)w[r];
-            } else {
-                const double a = Vi[2 * r], b = Vi[2 * r + 1], x = w[2 * r], y = w[2 * r + 1];
-                re += a * x + b * y;     // conj(V) w
-                im += a * y - b * x;
+                                                    uint64_t nsc, double *partials) {
+    constexpr int L = 16 / (int)sizeof(T), S = RU * L;
+    __shared__ double sh[RB / 64][RG * C];
+    const int nb = gridDim.x, t = threadIdx.x, wave = t >> 6, lane = t & 63;
+    const uint64_t tile0 = (uint64_t)blockIdx.x * tile_scalars<T>();
+    T wr[S];
+#pragma unroll
+    for (int u = 0; u < RU; ++u)
+        load_chunk<T>(w, tile0 + ((uint64_t)u * RB + t) * L, nsc, wr + u * L);
+    for (int i0 = 0; i0 < k; i0 += RG) {
+        T vr[RG][S];
+#pragma unroll
+        for (int g = 0; g < RG; ++g) {
+            const int i = i0 + g < k ? i0 + g : k - 1;   // a repeated column is discarded
+#pragma unroll
+            for (int u = 0; u < RU; ++u)
+                load_chunk<T>(V + (size_t)i * ld, tile0 + ((uint64_t)u * RB + t) * L, nsc,
+                              vr[g] + u * L);
+        }
+#pragma unroll
+        for (int g = 0; g < RG; ++g) {
+            double re = 0.0, im = 0.0;
+#pragma unroll
+            for (int e = 0; e < S; e += C) {
+                if (C == 1) {
+                    re = fma((double)vr[g][e], (double)wr[e], re);
+                } else {
+                    const double a = vr[g][e], b = vr[g][e + 1], x = wr[e], y = wr[e + 1];
+                    re = fma(a, x, fma(b, y, re));       // conj(V) w
+                    im = fma(a, y, fma(-b, x, im));
+                }
+            }
+            re = wave_sum(re);
+            if (C == 2) im = wave_sum(im);
+            if (lane == 0) {
+                sh[wave][g * C] = re;
+                if (C == 2) sh[wave][g * C + 1] = im;
             }
         }
-        sh[threadIdx.x] = re;
-        block_col_reduce(sh, 1);
-        if (threadIdx.x == 0) partials[((size_t)blockIdx.x * k + i) * 2] = sh[0];
         __syncthreads();
-        if (C == 2) {
-            sh[threadIdx.x] = im;
-            block_col_reduce(sh, 1);
-            if (threadIdx.x == 0) partials[((size_t)blockIdx.x * k + i) * 2 + 1] = sh[0];
-            __syncthreads();
+        if (t < RG * C && i0 + t / C < k) {
+            double s = 0.0;
+#pragma unroll
+            for (int q = 0; q < RB / 64; ++q) s += sh[q][t];
+            partials[((size_t)(i0 + t / C) * C + t % C) * nb + blockIdx.x] = s;
         }
+        __syncthreads();
     }
 }
 
+// coef[2 i + c] = sum over blocks (fixed order) of the partials; one block
+// per (i, c); coef[2 i + 1] = 0 for real vectors
+template <int C>
 __global__ __launch_bounds__(RB) void k_reorth_finalize(const double *partials, int n_blocks,
-                                                        int k, double *coef) {
-    for (int e = threadIdx.x; e < 2 * k; e += RB) {
-        double s = 0.0;
-        for (int b = 0; b < n_blocks; ++b) s += partials[(size_t)b * 2 * k + e];
-        coef[e] = s;
+                                                        double *coef) {
+    __shared__ double sh[RB];
+    const int e = blockIdx.x;   // i C + c
+    double s = 0.0;
+    for (int b = threadIdx.x; b < n_blocks; b += RB) s += partials[(size_t)e * n_blocks + b];
+    sh[threadIdx.x] = s;
+    block_col_reduce(sh, 1);
+    if (threadIdx.x == 0) {
+        const int i = e / C, c = e % C;
+        coef[2 * i + c] = sh[0];
+        if (C == 1) coef[2 * i + 1] = 0.0;
     }
 }
 
-// w -= sum_i c_i V_i
+// w -= sum_i c_i V_i, accumulated in FP64 and rounded once on store
 template <class T, int C>
 __global__ __launch_bounds__(RB) void k_reorth_sub(const T *V, uint64_t ld, int k,
-                                                   const double *coef, T *w, uint64_t n_rows) {
-    const uint64_t stride = (uint64_t)gridDim.x * RB;
-    for (uint64_t r = (uint64_t)blockIdx.x * RB + threadIdx.x; r < n_rows; r += stride) {
-        if (C == 1) {
-            double x = w[r];
-            for (int i = 0; i < k; ++i) x -= coef[2 * i] * (double)V[(size_t)i * ld + r];
-            w[r] = (T)x;
-        } else {
-            double x = w[2 * r], y = w[2 * r + 1];
-            for (int i = 0; i < k; ++i) {
-                const double a = V[(size_t)i * ld + 2 * r], b = V[(size_t)i * ld + 2 * r + 1];
-                const double cr = coef[2 * i], ci = coef[2 * i + 1];
-                x -= cr * a - ci * b;
-                y -= cr * b + ci * a;
+                                                   const double *coef, T *w, uint64_t nsc) {
+    constexpr int L = 16 / (int)sizeof(T), S = RU * L;
+    const int t = threadIdx.x;
+    const uint64_t tile0 = (uint64_t)blockIdx.x * tile_scalars<T>();
+    double acc[S];
+    {
+        T w0[S];
+#pragma unroll
+        for (int u = 0; u < RU; ++u)
+            load_chunk<T>(w, tile0 + ((uint64_t)u * RB + t) * L, nsc, w0 + u * L);
+#pragma unroll
+        for (int e = 0; e < S; ++e) acc[e] = (double)w0[e];
+    }
+    for (int i0 = 0; i0 < k; i0 += RG) {
+        T vr[RG][S];
+#pragma unroll
+        for (int g = 0; g < RG; ++g) {
+            const int i = i0 + g < k ? i0 + g : k - 1;
+#pragma unroll
+            for (int u = 0; u < RU; ++u)
+                load_chunk<T>(V + (size_t)i * ld, tile0 + ((uint64_t)u * RB + t) * L, nsc,
+                              vr[g] + u * L);
+        }
+#pragma unroll
+        for (int g = 0; g < RG; ++g) {
+            if (i0 + g >= k) break;
+            const double cr = coef[2 * (i0 + g)], ci = coef[2 * (i0 + g) + 1];
+#pragma unroll
+            for (int e = 0; e < S; e += C) {
+                if (C == 1) {
+                    acc[e] = fma(-cr, (double)vr[g][e], acc[e]);
+                } else {
+                    const double a = vr[g][e], b = vr[g][e + 1];
+                    acc[e] = fma(-cr, a, fma(ci, b, acc[e]));
+                    acc[e + 1] = fma(-cr, b, fma(-ci, a, acc[e + 1]));
+                }
             }
-            w[2 * r] = (T)x;
-            w[2 * r + 1] = (T)y;
+        }
+    }
+#pragma unroll
+    for (int u = 0; u < RU; ++u) {
+        const uint64_t q = tile0 + ((uint64_t)u * RB + t) * L;
+        if (q + L <= nsc) {
+            typedef typename Chunk16<T>::type V16;
+            V16 v;
+#pragma unroll
+            for (int e = 0; e < L; ++e) v[e] = (T)acc[u * L + e];
+            *(__attribute__((address_space(1))) V16 *)(w + q) = v;
+        } else {
+#pragma unroll
+            for (int e = 0; e < L; ++e)
+                if (q + e < nsc) w[q + e] = (T)acc[u * L + e];
         }
     }
 }
@@ -515,8 +622,11 @@ int lanczos_single(xdg_ham_s *h, const void *v0, int k, double tol, int max_iter
     VecOps ops{single, C, C, nsc, vec_grid(nsc), nullptr, st};
     XDG_RETURN_IF(parts.alloc(sizeof(double) * (size_t)ops.grid * MAXC));
     ops.partials = parts.as<double>();
-    const int rgrid = (int)std::min<int64_t>(std::max<int64_t>(1, D / 4096), device_cu_count() * 2);
-    if (reorth) XDG_RETURN_IF(rparts.alloc(sizeof(double) * 2 * (size_t)rgrid * (max_iter + 1)));
+    // reorthogonalisation: one block per row tile; partial sums per (column, block)
+    const int rtile = single ? tile_scalars<float>() : tile_scalars<double>();
+    const int rgrid = (int)((nsc + rtile - 1) / rtile);
+    if (reorth)
+        XDG_RETURN_IF(rparts.alloc(sizeof(double) * (size_t)C * rgrid * (max_iter + 1)));
 
     auto vec = [&](int i) -> char * { return bufs.as<char>() + vstride * i; };
     char *w = wbuf.as<char>();
@@ -559,46 +669,43 @@ int lanczos_single(xdg_ham_s *h, const void *v0, int k, double tol, int max_iter
         if (reorth) {
             const int kk = j + 1;
             for (int pass = 0; pass < 2; ++pass) {
+                double *rp = rparts.as<double>();
                 if (single) {
-                    if (C == 1)
+                    const float *Vf = (const float *)vec(0);
+                    float *wf = (float *)w;
+                    if (C == 1) {
                         hipLaunchKernelGGL((k_reorth_dots<float, 1>), dim3(rgrid), dim3(RB), 0, st,
-                                           (const float *)vec(0), ld, kk,
-                                           (const float *)w, (uint64_t)D, rparts.as<double>());
-                    else
+                                           Vf, ld, kk, wf, nsc, rp);
+                        hipLaunchKernelGGL(k_reorth_finalize<1>, dim3(kk), dim3(RB), 0, st, rp,
+                                           rgrid, coef);
+                        hipLaunchKernelGGL((k_reorth_sub<float, 1>), dim3(rgrid), dim3(RB), 0, st,
+                                           Vf, ld, kk, coef, wf, nsc);
+                    } else {
                         hipLaunchKernelGGL((k_reorth_dots<float, 2>), dim3(rgrid), dim3(RB), 0, st,
-                                           (const float *)vec(0), ld, kk,
-                                           (const float *)w, (uint64_t)D, rparts.as<double>());
+                                           Vf, ld, kk, wf, nsc, rp);
+                        hipLaunchKernelGGL(k_reorth_finalize<2>, dim3(2 * kk), dim3(RB), 0, st,
+                                           rp, rgrid, coef);
+                        hipLaunchKernelGGL((k_reorth_sub<float, 2>), dim3(rgrid), dim3(RB), 0, st,
+                                           Vf, ld, kk, coef, wf, nsc);
+                    }
                 } else {
-                    if (C == 1)
+                    const double *Vd = (const double *)vec(0);
+                    double *wd = (double *)w;
+                    if (C == 1) {
                         hipLaunchKernelGGL((k_reorth_dots<double, 1>), dim3(rgrid), dim3(RB), 0,
-                                           st, (const double *)vec(0), ld, kk,
-                                           (const double *)w, (uint64_t)D, rparts.as<double>());
-                    else
+                                           st, Vd, ld, kk, wd, nsc, rp);
+                        hipLaunchKernelGGL(k_reorth_finalize<1>, dim3(kk), dim3(RB), 0, st, rp,
+                                           rgrid, coef);
+                        hipLaunchKernelGGL((k_reorth_sub<double, 1>), dim3(rgrid), dim3(RB), 0,
+                                           st, Vd, ld, kk, coef, wd, nsc);
+                    } else {
                         hipLaunchKernelGGL((k_reorth_dots<double, 2>), dim3(rgrid), dim3(RB), 0,
-                                           st, (const double *)vec(0), ld, kk,
-                                           (const double *)w, (uint64_t)D, rparts.as<double>());
-                }
-                hipLaunchKernelGGL(k_reorth_finalize, dim3(1), dim3(RB), 0, st,
-                                   rparts.as<double>(), rgrid, kk, coef);
-                const int sgrid = vec_grid((uint64_t)D);
-                if (single) {
-                    if (C == 1)
-                        hipLaunchKernelGGL((k_reorth_sub<float, 1>), dim3(sgrid), dim3(RB), 0, st,
-                                           (const float *)vec(0), ld, kk, coef,
-                                           (float *)w, (uint64_t)D);
-                    else
-                        hipLaunchKernelGGL((k_reorth_sub<float, 2>), dim3(sgrid), dim3(RB), 0, st,
-                                           (const float *)vec(0), ld, kk, coef,
-                                           (float *)w, (uint64_t)D);
-                } else {
-                    if (C == 1)
-                        hipLaunchKernelGGL((k_reorth_sub<double, 1>), dim3(sgrid), dim3(RB), 0, st,
-                                           (const double *)vec(0), ld, kk, coef,
-                                           (double *)w, (uint64_t)D);
-                    else
-                        hipLaunchKernelGGL((k_reorth_sub<double, 2>), dim3(sgrid), dim3(RB), 0, st,
-                                           (const double *)vec(0), ld, kk, coef,
-                                           (double *)w, (uint64_t)D);
+                                           st, Vd, ld, kk, wd, nsc, rp);
+                        hipLaunchKernelGGL(k_reorth_finalize<2>, dim3(2 * kk), dim3(RB), 0, st,
+                                           rp, rgrid, coef);
+                        hipLaunchKernelGGL((k_reorth_sub<double, 2>), dim3(rgrid), dim3(RB), 0,
+                                           st, Vd, ld, kk, coef, wd, nsc);
+                    }
                 }
                 XDG_TRY_HIP(hipGetLastError());
             }
