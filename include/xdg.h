@@ -213,6 +213,26 @@ int xdg_ham_dim(xdg_ham h, int64_t *dim, int *is_complex);
  * Enqueued on `stream`. */
 int xdg_apply(xdg_ham h, const void *x, void *y, int64_t nvec, int dtype, void *stream);
 
+/* Launch shape of the apply kernel (what the autotuner chooses). */
+typedef struct xdg_launch_cfg {
+    int grid;          /* workgroups of 1024 lanes looping over the rows; 0 = one row per lane */
+    int nv;            /* vectors per pass: 1, 2, 4 or 8 (0 = 8), capped by nvec */
+    int occ;           /* 1: the copy limited to 64 VGPRs, 8 waves per SIMD (used only when
+                          two workgroups' LDS tables fit a compute unit); 0: 4 waves; -1: auto */
+    int compact;       /* sublattice / table searches: 1 = wave-compacted term loop (terms of
+                          64 rows packed into full passes), 0 or -1 = row loop */
+    int reserved[4];   /* must be zero */
+} xdg_launch_cfg;
+
+/* xdg_apply in a given launch shape (tuning and tests: every shape computes
+ * bitwise the same y).  Errors: XDG_EINVAL for a shape outside the ranges. */
+int xdg_apply_with_config(xdg_ham h, const void *x, void *y, int64_t nvec, int dtype,
+                          const xdg_launch_cfg *cfg, void *stream);
+
+/* The launch shape the autotuner chose for (dtype, nvec) on this Hamiltonian
+ * (after a first xdg_apply with them; XDG_EINVAL before).  Host only. */
+int xdg_apply_tuned_config(xdg_ham h, int dtype, int64_t nvec, xdg_launch_cfg *out);
+
 /* Several blocks (of possibly different dimension) in one persistent fused
  * launch: y_i = H_i x_i for i < n, all with the same nvec and dtype.  Work
  * items are (block, row tile) pairs drawn from one queue. */

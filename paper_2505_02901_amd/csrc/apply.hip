@@ -2,6 +2,8 @@
 // shapes, the autotuner, the batched persistent launch and nnz counting.
 #include <algorithm>
 #include <chrono>
+#include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <mutex>
 #include <vector>
@@ -179,7 +181,8 @@ int apply_launch(xdg_ham_s *h, const void *x, void *y, int64_t nvec, int dtype, 
         lds = f.tsingle ? stage_bytes<float>(A.one, b->plan.kind, 0)
                         : stage_bytes<double>(A.one, b->plan.kind, 0);
     }
-    A.occ = A.stage_sub ? occ_for(lds) : 0;
+    A.occ = A.stage_sub ? (c.occ >= 0 ? (c.occ && occ_for(lds)) : occ_for(lds)) : 0;
+    A.compact = c.compact > 0 ? 1 : 0;
     const int cap = c.nv > 0 ? c.nv : 8;
     for (int64_t v0 = 0; v0 < f.cols;) {
         const int nv = pick_nv(f.cols - v0, cap);
@@ -191,9 +194,23 @@ int apply_launch(xdg_ham_s *h, const void *x, void *y, int64_t nvec, int dtype, 
     return XDG_OK;
 }
 
-// Launch-shape autotuner: times a few grid sizes and vectors-per-pass on
-// the first call for a (dtype, nvec) pair; the result is bitwise identical
-// for every candidate, so the timing runs also leave the right y behind.
+// Launch-shape autotuner, run on the first call for a (dtype, nvec) pair:
+// first the persistent grid (1, 2, 4 or 8 workgroups per compute unit, or
+// one row per lane) and, with several columns, the vectors per pass; then,
+// at the best of those, the 8- or 4-waves-per-SIMD copy of the kernel (when
+// two workgroups' LDS fit a CU) and, for the table searches, the row loop
+// or the wave-compacted term loop.  Every candidate computes bitwise the
+// same y, so the timing runs also leave the right y behind.  XDG_TUNE_LOG=1
+// prints the timings to stderr.
+static bool tune_log() {
+    static int on = -1;
+    if (on < 0) {
+        const char *e = getenv("XDG_TUNE_LOG");
+        on = e && atoi(e) > 0;
+    }
+    return on;
+}
+
 int apply_tuned(xdg_ham_s *h, const void *x, void *y, int64_t nvec, int dtype, hipStream_t st) {
     TuneKey key{dtype, nvec};
     std::unique_lock<std::mutex> lock(h->tune_mu);
@@ -212,6 +229,25 @@ int apply_tuned(xdg_ham_s *h, const void *x, void *y, int64_t nvec, int dtype, h
         h->tuned[key] = c;
         return apply_launch(h, x, y, nvec, dtype, st, &c);
     }
+    hipEvent_t e0, e1;
+    XDG_TRY_HIP(hipEventCreate(&e0));
+    XDG_TRY_HIP(hipEventCreate(&e1));
+    // one warm launch, then the mean of `reps` timed launches (one for large blocks)
+    const int reps = b->dim > (int64_t)200000000 ? 1 : 2;
+    auto time_cfg = [&](const LaunchCfg &c, float *ms) -> int {
+        XDG_RETURN_IF(apply_launch(h, x, y, nvec, dtype, st, &c));
+        XDG_TRY_HIP(hipEventRecord(e0, st));
+        for (int r = 0; r < reps; ++r) XDG_RETURN_IF(apply_launch(h, x, y, nvec, dtype, st, &c));
+        XDG_TRY_HIP(hipEventRecord(e1, st));
+        XDG_TRY_HIP(hipEventSynchronize(e1));
+        XDG_TRY_HIP(hipEventElapsedTime(ms, e0, e1));
+        *ms /= reps;
+        if (tune_log())
+            fprintf(stderr, "[xdg tune] dim %lld dtype %d nvec %lld: grid %d nv %d occ %d "
+                    "compact %d: %.3f ms\n", (long long)b->dim, dtype, (long long)nvec, c.grid,
+                    c.nv, c.occ, c.compact, *ms);
+        return XDG_OK;
+    };
     std::vector<LaunchCfg> cands;
     const int cu = device_cu_count();
     for (int mult : {1, 2, 4, 8}) {
@@ -220,28 +256,55 @@ int apply_tuned(xdg_ham_s *h, const void *x, void *y, int64_t nvec, int dtype, h
         if (f.cols > 1) cands.push_back({APPLY_BLOCK, g, (int)std::max<int64_t>(1, f.cols / 2)});
     }
     cands.push_back({APPLY_BLOCK, (int)std::min<int64_t>(need, 1 << 30), 8});
-    hipEvent_t e0, e1;
-    XDG_TRY_HIP(hipEventCreate(&e0));
-    XDG_TRY_HIP(hipEventCreate(&e1));
     float best = 1e30f;
     LaunchCfg bestc = cands[0];
+    int rc = XDG_OK;
     for (const LaunchCfg &c : cands) {
-        XDG_RETURN_IF(apply_launch(h, x, y, nvec, dtype, st, &c));   // warm
-        XDG_TRY_HIP(hipEventRecord(e0, st));
-        for (int r = 0; r < 2; ++r) XDG_RETURN_IF(apply_launch(h, x, y, nvec, dtype, st, &c));
-        XDG_TRY_HIP(hipEventRecord(e1, st));
-        XDG_TRY_HIP(hipEventSynchronize(e1));
         float ms = 0;
-        XDG_TRY_HIP(hipEventElapsedTime(&ms, e0, e1));
+        if ((rc = time_cfg(c, &ms)) != XDG_OK) break;
         if (ms < best) {
             best = ms;
             bestc = c;
         }
     }
+    // second phase: kernel copy (occupancy) and, for table searches, the loop form
+    if (rc == XDG_OK) {
+        std::vector<LaunchCfg> more;
+        const bool table = b->plan.kind == K_SUB || b->plan.kind == K_TAB;
+        for (int occ : {0, 1})
+            for (int cmp : {0, 1}) {
+                if (cmp && !table) continue;
+                LaunchCfg c = bestc;
+                c.occ = occ;
+                c.compact = cmp;
+                more.push_back(c);
+            }
+        for (const LaunchCfg &c : more) {
+            float ms = 0;
+            if ((rc = time_cfg(c, &ms)) != XDG_OK) break;
+            if (ms < best) {
+                best = ms;
+                bestc = c;
+            }
+        }
+    }
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
+    XDG_RETURN_IF(rc);
     h->tuned[key] = bestc;
     return apply_launch(h, x, y, nvec, dtype, st, &bestc);
+}
+
+int apply_tuned_config(xdg_ham_s *h, int dtype, int64_t nvec, LaunchCfg *out) {
+    std::lock_guard<std::mutex> lock(h->tune_mu);
+    auto it = h->tuned.find(TuneKey{dtype, nvec});
+    if (it == h->tuned.end()) {
+        set_error("no tuned launch shape yet for dtype %d, nvec %lld (apply once first)", dtype,
+                  (long long)nvec);
+        return XDG_EINVAL;
+    }
+    *out = it->second;
+    return XDG_OK;
 }
 
 int ham_count_nnz(xdg_ham_s *h, int64_t *nnz) {

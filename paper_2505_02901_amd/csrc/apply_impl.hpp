@@ -91,6 +91,7 @@ struct ApplyArgs {
     int v0;                      // first vector of this pass
     int stage_sub;               // copy sublattice tables into LDS
     int occ;                     // use the 8-waves-per-SIMD variant
+    int compact;                 // table searches: wave-compacted term loop
     unsigned long long *count;   // nnz counting mode (nullptr otherwise)
 };
 
@@ -318,6 +319,190 @@ __device__ __forceinline__ void process_row(const SectorDesc &d, const Staged<A>
     }
 }
 
+// ------------------------------------------------ wave-compacted term loop --
+// For the table searches (sublattice coding, byte tables) the row loop above
+// takes every bond with all lanes of the wave at once, so on each bond only
+// the lanes whose spins differ there (about half) do a term.  Here a wave
+// owns 64 consecutive rows, one per lane, and packs their unequal-spin
+// (row, bond) terms into full passes of 64, in bond-major order: a pass holds
+// the terms of one or a few consecutive bonds, so neighbouring lanes still
+// search neighbouring targets with the same bond.  Terms move between lanes
+// with cross-lane permutes (no LDS): each owner pushes its lane number to the
+// lane that will do its term, that lane pulls the row state, computes the
+// term, and the owner pulls the amplitude and the gathered x back and adds
+// them in bond order with the same fused multiply-adds as the row loop, so
+// both loops give bitwise identical rows.
+__device__ __forceinline__ int lane_id() { return (int)__lane_id(); }
+
+__device__ __forceinline__ int rank_below(uint64_t m) {
+    return (int)__builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32),
+                                          __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
+}
+
+__device__ __forceinline__ int pull32(int src_lane, int v) {
+    return __builtin_amdgcn_ds_bpermute(src_lane << 2, v);
+}
+
+template <class V>
+__device__ __forceinline__ V pull(int src_lane, V v) {
+    if constexpr (sizeof(V) == 4) {
+        return __builtin_bit_cast(V, pull32(src_lane, __builtin_bit_cast(int, v)));
+    } else {
+        static_assert(sizeof(V) == 8, "8-byte value");
+        const uint64_t u = __builtin_bit_cast(uint64_t, v);
+        const int lo = pull32(src_lane, (int)(uint32_t)u);
+        const int hi = pull32(src_lane, (int)(uint32_t)(u >> 32));
+        return __builtin_bit_cast(V, ((uint64_t)(uint32_t)hi << 32) | (uint32_t)lo);
+    }
+}
+
+template <class W, int KIND, class T, class A, bool CPLX, int NV>
+__device__ __forceinline__ void process_wave_compact(const SectorDesc &d, const Staged<A> &S,
+                                                     int64_t row, bool valid, int64_t nvec,
+                                                     int v0) {
+    using B = typename BondT<A>::type;
+    constexpr int C = CPLX ? 2 : 1;
+    const int lane = lane_id();
+    const W s = valid ? gld(reinterpret_cast<const W *>(d.reps) + row) : W(0);
+    const T *X = reinterpret_cast<const T *>(d.x);
+    T *Y = reinterpret_cast<T *>(d.y);
+    const int nb = d.n_bonds;
+    A acc[NV * C];
+#pragma unroll
+    for (int v = 0; v < NV * C; ++v) acc[v] = 0;
+    auto unequal = [&](const B &bd) -> bool {
+        return valid && ((((uint32_t)(s >> bd.i)) ^ ((uint32_t)(s >> bd.j))) & 1u);
+    };
+    int b_cur = 0, off_cur = 0;    // next term: bond b_cur, after its first off_cur terms
+    while (b_cur < nb) {
+        // -- fill a pass: term lane k gets the row lane my_slot and the bond my_bond
+        int filled = 0, nseg = 0;
+        int my_slot = lane, my_bond = 0;
+        int seg_b = 0, seg_pos = 0;    // lane q: bond and packed (start, off, take) of segment q
+        while (filled < 64 && b_cur < nb) {
+            const B bd = S.bonds[b_cur];
+            const bool act = unequal(bd);
+            const uint64_t M = __ballot(act);
+            const int n = __popcll(M) - off_cur;
+            const int take = n < 64 - filled ? n : 64 - filled;
+            if (take > 0) {
+                // owners of terms off_cur .. off_cur + take - 1 push their lane to
+                // lanes filled .. filled + take - 1; every other lane pushes to one
+                // of the remaining lanes, so that the permute is a bijection
+                const int r = rank_below(M);
+                const bool mine = act && r >= off_cur && r < off_cur + take;
+                const uint64_t other = __ballot(!mine);
+                const int dest = mine ? filled + r - off_cur
+                                      : (filled + take + rank_below(other)) & 63;
+                const int got = __builtin_amdgcn_ds_permute(dest << 2, lane);
+                const bool in_seg = lane >= filled && lane < filled + take;
+                my_slot = in_seg ? got : my_slot;
+                my_bond = in_seg ? b_cur : my_bond;
+                if (lane == nseg) {
+                    seg_b = b_cur;
+                    seg_pos = filled | (off_cur << 8) | (take << 16);
+                }
+                ++nseg;
+                filled += take;
+            }
+            if (take == n) {
+                ++b_cur;
+                off_cur = 0;
+            } else {
+                off_cur += take;
+            }
+        }
+        // -- the pass: lane k < filled computes the term (my_slot, my_bond)
+        const W rs = pull<W>(my_slot, s);
+        bool ok = false;
+        A ar = 0, ai = 0;
+        T xv[NV * C];
+#pragma unroll
+        for (int v = 0; v < NV * C; ++v) xv[v] = T(0);
+        if (lane < filled) {
+            const B bd = S.bonds[my_bond];
+            const W t = rs ^ ((W(1) << bd.i) | (W(1) << bd.j));
+            int u, cnt;
+            const auto idx = locate<W, KIND, A>(d, S, t, u, cnt);
+            if (idx >= 0) {
+                ok = true;
+                const A f = bd.h * S.sq[cnt];
+                const auto c = S.chi[u];
+                ar = f * c.x;
+                if constexpr (CPLX) ai = f * c.y;
+                const size_t xb = sizeof(W) == 4
+                                      ? (uint64_t)(uint32_t)idx * (uint32_t)(nvec * C) +
+                                            (uint64_t)(v0 * C)
+                                      : ((size_t)idx * nvec + v0) * C;
+#pragma unroll
+                for (int v = 0; v < NV * C; ++v) xv[v] = gld(X + xb + v);
+            }
+        }
+        // -- owners pull their terms back, segment by segment (bond order)
+        for (int q = 0; q < nseg; ++q) {
+            const int bq = __builtin_amdgcn_readlane(seg_b, q);
+            const int pk = __builtin_amdgcn_readlane(seg_pos, q);
+            const int start = pk & 0xFF, off = (pk >> 8) & 0xFF, take = pk >> 16;
+            const bool act = unequal(S.bonds[bq]);
+            const uint64_t M = __ballot(act);
+            const int r = rank_below(M);
+            const bool mine = act && r >= off && r < off + take;
+            const int src = mine ? start + r - off : lane;
+            const bool okq = pull32(src, (int)ok) != 0;
+            const A arq = pull<A>(src, ar);
+            A aiq = 0;
+            if constexpr (CPLX) aiq = pull<A>(src, ai);
+            T xq[NV * C];
+#pragma unroll
+            for (int v = 0; v < NV * C; ++v) xq[v] = pull<T>(src, xv[v]);
+            if (mine && okq) {
+#pragma unroll
+                for (int v = 0; v < NV; ++v) {
+                    if constexpr (CPLX) {
+                        const A xr = xq[2 * v], xi = xq[2 * v + 1];
+                        acc[2 * v] = fmadd<A>(-aiq, xi, fmadd<A>(arq, xr, acc[2 * v]));
+                        acc[2 * v + 1] = fmadd<A>(aiq, xr, fmadd<A>(arq, xi, acc[2 * v + 1]));
+                    } else {
+                        acc[v] = fmadd<A>(arq, (A)xq[v], acc[v]);
+                    }
+                }
+            }
+        }
+    }
+    if (!valid) return;
+    // the diagonal: (1/4) sum_b Jz_b - (1/2) sum over the unequal-spin bonds,
+    // summed in bond order as in the row loop
+    A junq = 0;
+    for (int b = 0; b < nb; ++b) {
+        const B bd = S.bonds[b];
+        if (unequal(bd)) junq += bd.jz;
+    }
+    const A rn = S.rsq[gld(d.stab + row)];
+    const size_t base = ((size_t)row * nvec + v0) * C;
+    const A diag = (A)d.jz_quarter - A(0.5) * junq;
+#pragma unroll
+    for (int v = 0; v < NV * C; ++v)
+        gst(Y + base + v, (T)fmadd<A>(diag, (A)gld(X + base + v), rn * acc[v]));
+}
+
+// rows [r0, r1) of a sector, a wave at a time for the compacted loop (CMP:
+// every lane of a wave takes part in its permutes), a lane at a time otherwise
+template <class W, int KIND, class T, class A, bool CPLX, int NV, bool CMP>
+__device__ __forceinline__ void process_range(const SectorDesc &d, const Staged<A> &S, int64_t r0,
+                                              int64_t r1, int64_t first, int64_t stride,
+                                              int64_t nvec, int v0) {
+    if constexpr (CMP) {
+        const int64_t wave0 = first - lane_id();
+        for (int64_t rb = r0 + wave0; rb < r1; rb += stride) {
+            const int64_t row = rb + lane_id();
+            process_wave_compact<W, KIND, T, A, CPLX, NV>(d, S, row, row < r1, nvec, v0);
+        }
+    } else {
+        for (int64_t row = r0 + first; row < r1; row += stride)
+            process_row<W, KIND, T, A, CPLX, NV>(d, S, row, nvec, v0);
+    }
+}
+
 // count of the off-diagonal terms of a row that land in the block
 template <class W, int KIND>
 __device__ __forceinline__ uint32_t count_row(const SectorDesc &d, const Staged<double> &S,
@@ -334,7 +519,8 @@ __device__ __forceinline__ uint32_t count_row(const SectorDesc &d, const Staged<
     return n;
 }
 
-template <class W, int KIND, class T, class AC, bool CPLX, int NV, bool STAGE, bool OCC>
+template <class W, int KIND, class T, class AC, bool CPLX, int NV, bool STAGE, bool OCC,
+          bool CMP>
 __global__ __launch_bounds__(APPLY_BLOCK, OCC ? OCC_WAVES : 1) void k_apply(ApplyArgs A) {
     extern __shared__ __align__(16) unsigned char smem[];
     __shared__ uint32_t s_tile;
@@ -345,8 +531,9 @@ __global__ __launch_bounds__(APPLY_BLOCK, OCC ? OCC_WAVES : 1) void k_apply(Appl
         stage<KIND, AC, STAGE>(d, smem, S);
         __syncthreads();
         const int64_t stride = (int64_t)gridDim.x * blockDim.x;
-        for (int64_t row = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; row < d.dim; row += stride)
-            process_row<W, KIND, T, AC, CPLX, NV>(d, S, row, A.nvec, A.v0);
+        process_range<W, KIND, T, AC, CPLX, NV, CMP>(d, S, 0, d.dim,
+                                                (int64_t)blockIdx.x * blockDim.x + threadIdx.x,
+                                                stride, A.nvec, A.v0);
         return;
     }
     // persistent: (sector, row tile) items from one queue
@@ -372,8 +559,8 @@ __global__ __launch_bounds__(APPLY_BLOCK, OCC ? OCC_WAVES : 1) void k_apply(Appl
         const int64_t r0 = (int64_t)(tile - A.tile_prefix[lo]) * A.tile_rows;
         int64_t r1 = r0 + A.tile_rows;
         r1 = r1 < d.dim ? r1 : d.dim;
-        for (int64_t row = r0 + threadIdx.x; row < r1; row += blockDim.x)
-            process_row<W, KIND, T, AC, CPLX, NV>(d, S, row, A.nvec, A.v0);
+        process_range<W, KIND, T, AC, CPLX, NV, CMP>(d, S, r0, r1, threadIdx.x, blockDim.x,
+                                                     A.nvec, A.v0);
         __syncthreads();
     }
 }
@@ -409,15 +596,31 @@ template <int KIND>
 int launch_count_kind(bool wide, const ApplyArgs &A, unsigned grid, unsigned block, size_t lds,
                       hipStream_t st);
 
-template <class W, int KIND, class T, class AC, bool CPLX, bool STAGE, bool OCC>
+template <class W, int KIND, class T, class AC, bool CPLX, bool STAGE, bool OCC, bool CMP>
 void (*apply_kernel(int nv))(ApplyArgs) {
     switch (nv) {
-        case 1: return k_apply<W, KIND, T, AC, CPLX, 1, STAGE, OCC>;
-        case 2: return k_apply<W, KIND, T, AC, CPLX, 2, STAGE, OCC>;
-        case 4: return k_apply<W, KIND, T, AC, CPLX, 4, STAGE, OCC>;
-        case 8: return k_apply<W, KIND, T, AC, CPLX, 8, STAGE, OCC>;
+        case 1: return k_apply<W, KIND, T, AC, CPLX, 1, STAGE, OCC, CMP>;
+        case 2: return k_apply<W, KIND, T, AC, CPLX, 2, STAGE, OCC, CMP>;
+    }
+    if constexpr (!CMP) {
+        switch (nv) {
+            case 4: return k_apply<W, KIND, T, AC, CPLX, 4, STAGE, OCC, false>;
+            case 8: return k_apply<W, KIND, T, AC, CPLX, 8, STAGE, OCC, false>;
+        }
     }
     return nullptr;
+}
+
+// The compacted term loop exists for the table searches (sublattice coding,
+// byte tables) with at most two vectors per pass.
+template <int KIND>
+constexpr bool has_compact() { return KIND == K_SUB || KIND == K_TAB; }
+
+template <class W, int KIND, class T, class AC, bool CPLX, bool STAGE, bool OCC>
+void (*apply_kernel_loop(int nv, bool compact))(ApplyArgs) {
+    if constexpr (has_compact<KIND>())
+        if (compact && nv <= 2) return apply_kernel<W, KIND, T, AC, CPLX, STAGE, OCC, true>(nv);
+    return apply_kernel<W, KIND, T, AC, CPLX, STAGE, OCC, false>(nv);
 }
 
 template <class W, int KIND, class T, class AC, bool CPLX>
@@ -428,11 +631,12 @@ int launch_nv(int nv, const ApplyArgs &A, unsigned grid, unsigned block, size_t 
     // the 64-VGPR copy only while a lane holds at most two accumulator
     // scalars: with more it spills them (complex 8-vector passes: 200 bytes)
     const bool occ = A.occ && nv * (CPLX ? 2 : 1) <= 2;
+    const bool cmp = A.compact != 0;
     if (KIND != K_SUB || A.stage_sub)
-        f = occ ? apply_kernel<W, KIND, T, AC, CPLX, true, true>(nv)
-                : apply_kernel<W, KIND, T, AC, CPLX, true, false>(nv);
+        f = occ ? apply_kernel_loop<W, KIND, T, AC, CPLX, true, true>(nv, cmp)
+                : apply_kernel_loop<W, KIND, T, AC, CPLX, true, false>(nv, cmp);
     else if constexpr (KIND == K_SUB)
-        f = apply_kernel<W, KIND, T, AC, CPLX, false, false>(nv);
+        f = apply_kernel_loop<W, KIND, T, AC, CPLX, false, false>(nv, cmp);
     if (!f) {
         set_error("vectors per pass %d not in {1, 2, 4, 8}", nv);
         return XDG_EINVAL;

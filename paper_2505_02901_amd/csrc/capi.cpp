@@ -243,11 +243,26 @@ int xdg_create_hamiltonian(xdg_basis b, int n_bonds, const int32_t *sites, const
         h->sites.assign(sites, sites + 2 * (size_t)n_bonds);
         h->jz.assign(jz, jz + n_bonds);
         h->jxy.assign(jxy, jxy + n_bonds);
+        // device bond order: for sublattice coding, bonds joining the same pair
+        // of blocks are kept together (stable), so that bonds taken one after
+        // the other change the same two blocks of a state
+        std::vector<int> order(n_bonds);
+        for (int i = 0; i < n_bonds; ++i) order[i] = i;
+        if (b->plan.kind == XDG_SEARCH_SUBLATTICE && b->plan.sub.m > 0) {
+            const int m = b->plan.sub.m;
+            auto key = [&](int k) {
+                const int p = sites[2 * k] / m, q = sites[2 * k + 1] / m;
+                return std::min(p, q) * 64 + std::max(p, q);
+            };
+            std::stable_sort(order.begin(), order.end(),
+                             [&](int a, int c) { return key(a) < key(c); });
+        }
         std::vector<BondD> bd(n_bonds);
         std::vector<BondF> bf(n_bonds);
-        for (int i = 0; i < n_bonds; ++i) {
-            bd[i] = BondD{(uint32_t)sites[2 * i], (uint32_t)sites[2 * i + 1], jz[i], 0.5 * jxy[i]};
-            bf[i] = BondF{bd[i].i, bd[i].j, (float)jz[i], (float)(0.5 * jxy[i])};
+        for (int e = 0; e < n_bonds; ++e) {
+            const int i = order[e];
+            bd[e] = BondD{(uint32_t)sites[2 * i], (uint32_t)sites[2 * i + 1], jz[i], 0.5 * jxy[i]};
+            bf[e] = BondF{bd[e].i, bd[e].j, (float)jz[i], (float)(0.5 * jxy[i])};
         }
         int rc = h->bonds_d.upload(bd.data(), sizeof(BondD) * std::max(n_bonds, 1));
         if (rc == XDG_OK) rc = h->bonds_f.upload(bf.data(), sizeof(BondF) * std::max(n_bonds, 1));
@@ -309,6 +324,50 @@ int xdg_apply_batched(int n, const xdg_ham *hams, const void *const *xs, void *c
         std::vector<xdg_ham_s *> hv(hams, hams + n);
         return apply_batched_launch(n, hv.data(), xs, ys, nvec, dtype, (hipStream_t)stream,
                                     nullptr, 0, 256);
+    });
+}
+
+int xdg_apply_with_config(xdg_ham h, const void *x, void *y, int64_t nvec, int dtype,
+                          const xdg_launch_cfg *cfg, void *stream) {
+    return guarded([&]() -> int {
+        if (!h || !cfg) {
+            set_error("null argument");
+            return XDG_EINVAL;
+        }
+        const bool nv_ok = cfg->nv == 0 || cfg->nv == 1 || cfg->nv == 2 || cfg->nv == 4 ||
+                           cfg->nv == 8;
+        bool res_ok = true;
+        for (int r : cfg->reserved) res_ok &= r == 0;
+        if (cfg->grid < 0 || !nv_ok || cfg->occ < -1 || cfg->occ > 1 || cfg->compact < -1 ||
+            cfg->compact > 1 || !res_ok) {
+            set_error("launch shape out of range (grid %d, nv %d, occ %d, compact %d)", cfg->grid,
+                      cfg->nv, cfg->occ, cfg->compact);
+            return XDG_EINVAL;
+        }
+        LaunchCfg c;
+        c.grid = cfg->grid > 0 ? cfg->grid
+                               : (int)std::max<int64_t>(1, (h->basis->dim + 1023) / 1024);
+        c.nv = cfg->nv > 0 ? cfg->nv : 8;
+        c.occ = cfg->occ;
+        c.compact = cfg->compact;
+        return apply_launch(h, x, y, nvec, dtype, (hipStream_t)stream, &c);
+    });
+}
+
+int xdg_apply_tuned_config(xdg_ham h, int dtype, int64_t nvec, xdg_launch_cfg *out) {
+    return guarded([&]() -> int {
+        if (!h || !out) {
+            set_error("null argument");
+            return XDG_EINVAL;
+        }
+        LaunchCfg c;
+        XDG_RETURN_IF(apply_tuned_config(h, dtype, nvec, &c));
+        *out = xdg_launch_cfg{};
+        out->grid = c.grid;
+        out->nv = c.nv;
+        out->occ = c.occ;
+        out->compact = c.compact;
+        return XDG_OK;
     });
 }
 

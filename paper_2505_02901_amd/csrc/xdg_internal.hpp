@@ -178,6 +178,8 @@ struct LaunchCfg {
     int block = 256;       // threads per workgroup
     int grid = 0;          // workgroups (persistent grid); 0 = one row per lane
     int nv = 1;            // vectors per pass (<= nvec)
+    int occ = -1;          // 64-VGPR copy at 8 waves per SIMD: 1 / 0 / -1 = when the LDS allows
+    int compact = -1;      // table searches: 1 = wave-compacted term loop, 0 / -1 = row loop
 };
 }  // namespace xdg
 
@@ -213,6 +215,7 @@ int ham_count_nnz(xdg_ham_s *h, int64_t *nnz);
 int apply_launch(xdg_ham_s *h, const void *x, void *y, int64_t nvec, int dtype, hipStream_t st,
                  const LaunchCfg *cfg);
 int apply_tuned(xdg_ham_s *h, const void *x, void *y, int64_t nvec, int dtype, hipStream_t st);
+int apply_tuned_config(xdg_ham_s *h, int dtype, int64_t nvec, LaunchCfg *out);
 int apply_batched_launch(int n, xdg_ham_s *const *hams, const void *const *xs, void *const *ys,
                          int64_t nvec, int dtype, hipStream_t st, uint32_t *d_queue,
                          int grid, int block);

@@ -33,6 +33,11 @@ class XdgError(RuntimeError):
         self.code = code
 
 
+class LaunchCfg(C.Structure):
+    _fields_ = [("grid", C.c_int), ("nv", C.c_int), ("occ", C.c_int), ("compact", C.c_int),
+                ("reserved", C.c_int * 4)]
+
+
 class BasisOpts(C.Structure):
     _fields_ = [("search", C.c_int), ("n_sublattices", C.c_int), ("flags", C.c_int),
                 ("reserved", C.c_int * 5)]
@@ -77,6 +82,8 @@ def lib():
             "xdg_apply": (I, [P, P, P, I64, I, P]),
             "xdg_apply_batched": (I, [I, P, P, P, I64, I, P]),
             "xdg_apply_batched_noalloc": (I, [I, P, P, P, I64, I, P]),
+            "xdg_apply_with_config": (I, [P, P, P, I64, I, P, P]),
+            "xdg_apply_tuned_config": (I, [P, I, I64, P]),
             "xdg_random_state": (I, [I64, I64, U64, I, I, P, P]),
             "xdg_lanczos_eigval": (I, [P, P, I, D, I, U64, I, P, P, P, P, P]),
             "xdg_lanczos_eigval_batched": (I, [I, P, P, I64, I, U64, I, P, P, P, P]),
@@ -102,7 +109,8 @@ def exported_names():
             "xdg_basis_copy_states",
             "xdg_basis_copy_stabilisers", "xdg_basis_index", "xdg_create_hamiltonian",
             "xdg_destroy_hamiltonian", "xdg_ham_nnz", "xdg_ham_dim", "xdg_apply",
-            "xdg_apply_batched", "xdg_apply_batched_noalloc",
+            "xdg_apply_batched", "xdg_apply_batched_noalloc", "xdg_apply_with_config",
+            "xdg_apply_tuned_config",
             "xdg_random_state", "xdg_lanczos_eigval", "xdg_lanczos_eigval_batched",
             "xdg_last_lanczos_timing", "xdg_lanczos_eigvec", "xdg_expect_szsz",
             "xdg_ftlm_thermo", "xdg_apply_sz_transfer", "xdg_spectral_cf"]
@@ -348,6 +356,26 @@ def xdg_apply(h, x, y, nvec: Optional[int] = None, dtype: Optional[int] = None, 
         dtype = _dtype_code(x)
     _check_apply_vectors(h, x, y, nvec, dtype)
     _check(lib().xdg_apply(h, _ptr(x), _ptr(y), nvec, dtype, _stream(stream)))
+
+
+def xdg_apply_with_config(h, x, y, grid: int = 0, nv: int = 0, occ: int = -1, compact: int = -1,
+                          nvec: Optional[int] = None, dtype: Optional[int] = None, stream=None):
+    """xdg_apply in an explicit launch shape (every shape gives the same y)."""
+    if nvec is None:
+        nvec = 1 if x.dim() == 1 else int(x.shape[1])
+    if dtype is None:
+        dtype = _dtype_code(x)
+    _check_apply_vectors(h, x, y, nvec, dtype)
+    cfg = LaunchCfg(grid, nv, occ, compact)
+    _check(lib().xdg_apply_with_config(h, _ptr(x), _ptr(y), nvec, dtype, C.byref(cfg),
+                                       _stream(stream)))
+
+
+def xdg_apply_tuned_config(h, dtype: int, nvec: int = 1) -> dict:
+    """The autotuner's launch shape for (dtype, nvec) on this Hamiltonian."""
+    cfg = LaunchCfg()
+    _check(lib().xdg_apply_tuned_config(h, dtype, nvec, C.byref(cfg)))
+    return {"grid": cfg.grid, "nv": cfg.nv, "occ": cfg.occ, "compact": cfg.compact}
 
 
 def xdg_apply_batched(hams: Sequence, xs: Sequence, ys: Sequence, nvec: Optional[int] = None,

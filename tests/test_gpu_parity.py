@@ -340,6 +340,48 @@ def test_apply_argument_errors(X):
         X.Basis(8, 9)
 
 
+SHAPE_CASES = [
+    (W.torus_model((6, 0), (0, 6), 1.0, 0.5, "A1", n_up=7), 0),          # sublattice, 4 blocks
+    (W.sublattice_model("triangle3", (4, -2), (2, 2), rot_char=np.exp(1j * np.pi / 3),
+                        name="triangle3_12_E"), 0),                    # sublattice, 3 blocks
+    (W.torus_model((4, 2), (-2, 4), 1.0, 0.0, "A1", reflections=False, n_up=8),
+     4),                                                               # forced byte tables
+    (W.chain_model(24, l=5), 0),                                       # ring search
+]
+
+
+@pytest.mark.parametrize("case", range(len(SHAPE_CASES)))
+def test_every_launch_shape_gives_the_same_y(X, case):
+    """The autotuner's candidates (grid, vectors per pass, occupancy copy,
+    row or compacted term loop) compute bitwise the same y."""
+    m, search = SHAPE_CASES[case]
+    b = X.Basis.from_model(m, search=search)
+    H = X.Hamiltonian.from_model(b, m)
+    cdt = torch.complex128 if b.is_complex else torch.float64
+    for dt in ((cdt, torch.complex64) if b.is_complex else (torch.float64, torch.float32)):
+        g = torch.Generator(device="cuda").manual_seed(case)
+        x = torch.randn(b.dim, 2, dtype=dt, device="cuda", generator=g)
+        ref = torch.empty_like(x)
+        H.apply(x, ref)
+        for grid in (0, 1, 5, 256):
+            for nv in (1, 2, 8):
+                for occ in (-1, 0, 1):
+                    for compact in (0, 1):
+                        y = torch.full_like(x, float("nan"))
+                        X.xdg_apply_with_config(H.handle, x, y, grid=grid, nv=nv, occ=occ,
+                                                compact=compact)
+                        torch.cuda.synchronize()
+                        assert torch.equal(y, ref), (m.name, dt, grid, nv, occ, compact)
+        code = {torch.float64: X.XDG_F64, torch.float32: X.XDG_F32,
+                torch.complex128: X.XDG_C128, torch.complex64: X.XDG_C64}[dt]
+        cfg = X.xdg_apply_tuned_config(H.handle, code, 2)
+        assert cfg["nv"] in (1, 2, 4, 8) and cfg["grid"] >= 1
+    with pytest.raises(X.XdgError):
+        X.xdg_apply_with_config(H.handle, x, torch.empty_like(x), nv=3)
+    with pytest.raises(X.XdgError):                  # not tuned for this (dtype, nvec)
+        X.xdg_apply_tuned_config(H.handle, code, 7)
+
+
 def test_binding_refuses_mismatched_tensors(X):
     """Sizes and dtypes are checked against the block before any launch: a
     tensor from a larger sector or an FP32 y for an FP64 x raises ValueError."""
