@@ -76,10 +76,7 @@ SectorDesc make_desc(const xdg_ham_s *h, bool single, const void *x, void *y) {
     d.rwords = b->n_rwords ? b->rwords.as<uint2>() : nullptr;
     d.n_rwords = b->n_rwords;
     d.rtab = b->rtab.p;
-    d.rcb = b->rank_cb;
-    d.rnc = b->rank_nc;
-    d.rrows = b->rank_rows;
-    d.resz = b->wide ? 8 : 4;
+    d.rl = b->rank;
     d.n_up = b->n_up;
     d.n_sites = b->n_sites;
     d.n_sym = b->n_sym;

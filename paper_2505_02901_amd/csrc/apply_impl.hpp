@@ -52,8 +52,8 @@ struct SectorDesc {
     uint64_t empty;
     const uint2 *rwords;         // rank index (null: hash)
     uint64_t n_rwords;
-    const void *rtab;            // colex chunk tables: rrows rows of 2^rcb entries of resz bytes
-    int rcb, rnc, rrows, resz;
+    const void *rtab;            // colex chunk tables (layout rl)
+    RankLayout rl;
     int n_up;
     const uint32_t *lin;         // Lin tables (U(1))
     int nlo;
@@ -105,7 +105,7 @@ __host__ __device__ inline size_t sub_table_bytes(const SectorDesc &d) {
 }
 
 __host__ __device__ inline size_t rank_table_bytes(const SectorDesc &d) {
-    return d.rwords ? ((size_t)d.rrows << d.rcb) * d.resz : 0;
+    return d.rwords ? ((size_t)d.rl.rows << d.rl.cb) * (d.rl.e32 ? 4 : 8) : 0;
 }
 
 // LDS bytes needed to stage a sector's tables.
@@ -213,13 +213,17 @@ __device__ __forceinline__ typename IndexT<W>::type locate(const SectorDesc &d, 
             tab_search<W>(d.bytetab, d.n_bchunks, d.n_sym, t, rep, u, cnt);
         }
         if (d.rwords) {
-            const uint64_t r =
-                colex_rank<W>(static_cast<const typename RankEntry<W>::type *>(S.rtab), d.n_sites,
-                              d.n_up, d.rcb, d.rnc, rep);
-            if constexpr (sizeof(W) == 4)
+            const uint64_t r = colex_rank<W>(S.rtab, d.rl, rep);
+            if constexpr (sizeof(W) == 4) {
                 return rank_find32(d.rwords, (uint32_t)d.n_rwords, (uint32_t)r);
-            else
+            } else {
+                // 4-byte entries: every basis state's rank is below 2^32 - 1
+                if (d.rl.e32)
+                    return r >= 0xFFFFFFFFull
+                               ? -1
+                               : rank_find_r32(d.rwords, (uint32_t)d.n_rwords, (uint32_t)r);
                 return rank_find(d.rwords, d.n_rwords, r);
+            }
         }
         return (I)hash_find<W>(d.hash, d.n_lines, (W)d.empty, rep);
     }
@@ -323,15 +327,18 @@ __device__ __forceinline__ void process_row(const SectorDesc &d, const Staged<A>
 // For the table searches (sublattice coding, byte tables) the row loop above
 // takes every bond with all lanes of the wave at once, so on each bond only
 // the lanes whose spins differ there (about half) do a term.  Here a wave
-// owns 64 consecutive rows, one per lane, and packs their unequal-spin
-// (row, bond) terms into full passes of 64, in bond-major order: a pass holds
-// the terms of one or a few consecutive bonds, so neighbouring lanes still
-// search neighbouring targets with the same bond.  Terms move between lanes
-// with cross-lane permutes (no LDS): each owner pushes its lane number to the
+// owns a window of 64 + CMP_EXTRA consecutive rows (a second row on the
+// first CMP_EXTRA lanes) and, bond by bond, packs the unequal-spin terms of
+// the window into passes of up to 64: every lane of a pass takes the same
+// bond, as in the row loop, but most lanes have a term.  Terms move between
+// lanes with cross-lane permutes (no LDS): each owner pushes its row to the
 // lane that will do its term, that lane pulls the row state, computes the
 // term, and the owner pulls the amplitude and the gathered x back and adds
-// them in bond order with the same fused multiply-adds as the row loop, so
-// both loops give bitwise identical rows.
+// them with the same fused multiply-adds, in bond order, so that both loops
+// give bitwise identical rows.
+constexpr int CMP_EXTRA = 48;
+constexpr int CMP_ROWS = 64 + CMP_EXTRA;   // rows per wave window
+
 __device__ __forceinline__ int lane_id() { return (int)__lane_id(); }
 
 __device__ __forceinline__ int rank_below(uint64_t m) {
@@ -356,147 +363,143 @@ __device__ __forceinline__ V pull(int src_lane, V v) {
     }
 }
 
+// Lanes with `mine` send `val` to lane `dest` (dest distinct, all inside the
+// range [lo, hi)); every other lane sends to one of the lanes outside that
+// range, so that the permute is a bijection (a lane that is not a
+// destination of any sender would receive an undefined value).  Returns what
+// this lane received.
+__device__ __forceinline__ int push_range(bool mine, int dest, int lo, int hi, int val) {
+    const uint64_t other = __ballot(!mine);
+    const int d = mine ? dest : ((hi + rank_below(other)) & 63);
+    (void)lo;
+    return __builtin_amdgcn_ds_permute(d << 2, val);
+}
+
 template <class W, int KIND, class T, class A, bool CPLX, int NV>
-__device__ __forceinline__ void process_wave_compact(const SectorDesc &d, const Staged<A> &S,
-                                                     int64_t row, bool valid, int64_t nvec,
-                                                     int v0) {
+__device__ __forceinline__ void process_window(const SectorDesc &d, const Staged<A> &S,
+                                               int64_t w0, int64_t r1, int64_t nvec, int v0) {
     using B = typename BondT<A>::type;
     constexpr int C = CPLX ? 2 : 1;
     const int lane = lane_id();
-    const W s = valid ? gld(reinterpret_cast<const W *>(d.reps) + row) : W(0);
+    const int64_t row0 = w0 + lane, row1 = w0 + 64 + lane;
+    const bool ok0 = row0 < r1, ok1 = lane < CMP_EXTRA && row1 < r1;
+    const W *R = reinterpret_cast<const W *>(d.reps);
+    const W s0 = ok0 ? gld(R + row0) : W(0);
+    const W s1 = ok1 ? gld(R + row1) : W(0);
     const T *X = reinterpret_cast<const T *>(d.x);
     T *Y = reinterpret_cast<T *>(d.y);
     const int nb = d.n_bonds;
-    A acc[NV * C];
+    A acc0[NV * C], acc1[NV * C];
 #pragma unroll
-    for (int v = 0; v < NV * C; ++v) acc[v] = 0;
-    auto unequal = [&](const B &bd) -> bool {
-        return valid && ((((uint32_t)(s >> bd.i)) ^ ((uint32_t)(s >> bd.j))) & 1u);
+    for (int v = 0; v < NV * C; ++v) acc0[v] = acc1[v] = 0;
+    auto unequal = [](W s, const B &bd) -> bool {
+        return (((uint32_t)(s >> bd.i)) ^ ((uint32_t)(s >> bd.j))) & 1u;
     };
-    int b_cur = 0, off_cur = 0;    // next term: bond b_cur, after its first off_cur terms
-    while (b_cur < nb) {
-        // -- fill a pass: term lane k gets the row lane my_slot and the bond my_bond
-        int filled = 0, nseg = 0;
-        int my_slot = lane, my_bond = 0;
-        int seg_b = 0, seg_pos = 0;    // lane q: bond and packed (start, off, take) of segment q
-        while (filled < 64 && b_cur < nb) {
-            const B bd = S.bonds[b_cur];
-            const bool act = unequal(bd);
-            const uint64_t M = __ballot(act);
-            const int n = __popcll(M) - off_cur;
-            const int take = n < 64 - filled ? n : 64 - filled;
-            if (take > 0) {
-                // owners of terms off_cur .. off_cur + take - 1 push their lane to
-                // lanes filled .. filled + take - 1; every other lane pushes to one
-                // of the remaining lanes, so that the permute is a bijection
-                const int r = rank_below(M);
-                const bool mine = act && r >= off_cur && r < off_cur + take;
-                const uint64_t other = __ballot(!mine);
-                const int dest = mine ? filled + r - off_cur
-                                      : (filled + take + rank_below(other)) & 63;
-                const int got = __builtin_amdgcn_ds_permute(dest << 2, lane);
-                const bool in_seg = lane >= filled && lane < filled + take;
-                my_slot = in_seg ? got : my_slot;
-                my_bond = in_seg ? b_cur : my_bond;
-                if (lane == nseg) {
-                    seg_b = b_cur;
-                    seg_pos = filled | (off_cur << 8) | (take << 16);
-                }
-                ++nseg;
-                filled += take;
-            }
-            if (take == n) {
-                ++b_cur;
-                off_cur = 0;
+    auto add = [&](A *acc, A ar, A ai, const T *xq) {
+#pragma unroll
+        for (int v = 0; v < NV; ++v) {
+            if constexpr (CPLX) {
+                const A xr = xq[2 * v], xi = xq[2 * v + 1];
+                acc[2 * v] = fmadd<A>(-ai, xi, fmadd<A>(ar, xr, acc[2 * v]));
+                acc[2 * v + 1] = fmadd<A>(ai, xr, fmadd<A>(ar, xi, acc[2 * v + 1]));
             } else {
-                off_cur += take;
+                acc[v] = fmadd<A>(ar, (A)xq[v], acc[v]);
             }
         }
-        // -- the pass: lane k < filled computes the term (my_slot, my_bond)
-        const W rs = pull<W>(my_slot, s);
-        bool ok = false;
-        A ar = 0, ai = 0;
-        T xv[NV * C];
-#pragma unroll
-        for (int v = 0; v < NV * C; ++v) xv[v] = T(0);
-        if (lane < filled) {
-            const B bd = S.bonds[my_bond];
-            const W t = rs ^ ((W(1) << bd.i) | (W(1) << bd.j));
-            int u, cnt;
-            const auto idx = locate<W, KIND, A>(d, S, t, u, cnt);
-            if (idx >= 0) {
-                ok = true;
-                const A f = bd.h * S.sq[cnt];
-                const auto c = S.chi[u];
-                ar = f * c.x;
-                if constexpr (CPLX) ai = f * c.y;
-                const size_t xb = sizeof(W) == 4
-                                      ? (uint64_t)(uint32_t)idx * (uint32_t)(nvec * C) +
-                                            (uint64_t)(v0 * C)
-                                      : ((size_t)idx * nvec + v0) * C;
-#pragma unroll
-                for (int v = 0; v < NV * C; ++v) xv[v] = gld(X + xb + v);
-            }
-        }
-        // -- owners pull their terms back, segment by segment (bond order)
-        for (int q = 0; q < nseg; ++q) {
-            const int bq = __builtin_amdgcn_readlane(seg_b, q);
-            const int pk = __builtin_amdgcn_readlane(seg_pos, q);
-            const int start = pk & 0xFF, off = (pk >> 8) & 0xFF, take = pk >> 16;
-            const bool act = unequal(S.bonds[bq]);
-            const uint64_t M = __ballot(act);
-            const int r = rank_below(M);
-            const bool mine = act && r >= off && r < off + take;
-            const int src = mine ? start + r - off : lane;
-            const bool okq = pull32(src, (int)ok) != 0;
-            const A arq = pull<A>(src, ar);
-            A aiq = 0;
-            if constexpr (CPLX) aiq = pull<A>(src, ai);
-            T xq[NV * C];
-#pragma unroll
-            for (int v = 0; v < NV * C; ++v) xq[v] = pull<T>(src, xv[v]);
-            if (mine && okq) {
-#pragma unroll
-                for (int v = 0; v < NV; ++v) {
-                    if constexpr (CPLX) {
-                        const A xr = xq[2 * v], xi = xq[2 * v + 1];
-                        acc[2 * v] = fmadd<A>(-aiq, xi, fmadd<A>(arq, xr, acc[2 * v]));
-                        acc[2 * v + 1] = fmadd<A>(aiq, xr, fmadd<A>(arq, xi, acc[2 * v + 1]));
-                    } else {
-                        acc[v] = fmadd<A>(arq, (A)xq[v], acc[v]);
-                    }
-                }
-            }
-        }
-    }
-    if (!valid) return;
-    // the diagonal: (1/4) sum_b Jz_b - (1/2) sum over the unequal-spin bonds,
-    // summed in bond order as in the row loop
-    A junq = 0;
+    };
     for (int b = 0; b < nb; ++b) {
         const B bd = S.bonds[b];
-        if (unequal(bd)) junq += bd.jz;
-    }
-    const A rn = S.rsq[gld(d.stab + row)];
-    const size_t base = ((size_t)row * nvec + v0) * C;
-    const A diag = (A)d.jz_quarter - A(0.5) * junq;
+        const bool a0 = ok0 && unequal(s0, bd), a1 = ok1 && unequal(s1, bd);
+        const uint64_t M0 = __ballot(a0), M1 = __ballot(a1);
+        const int n0 = __popcll(M0), n = n0 + __popcll(M1);
+        // term index of this lane's row-0 and row-1 terms (row 0 terms first)
+        const int e0 = rank_below(M0), e1 = n0 + rank_below(M1);
+        const W flip = (W(1) << bd.i) | (W(1) << bd.j);
+        for (int p = 0; p < n; p += 64) {
+            const int take = n - p < 64 ? n - p : 64;
+            // pass lanes [lo0, hi0) take row-0 terms, [hi0, take) row-1 terms
+            const int lo0 = 0, hi0 = n0 - p < 0 ? 0 : (n0 - p < take ? n0 - p : take);
+            const bool m0 = a0 && e0 >= p && e0 < p + take;
+            const bool m1 = a1 && e1 >= p && e1 < p + take;
+            const int g0 = push_range(m0, e0 - p, lo0, hi0, lane);
+            const int g1 = push_range(m1, e1 - p, hi0, take, lane);
+            const bool has = lane < take;
+            const bool second = lane >= hi0;
+            const int src = second ? g1 : g0;   // owner lane of this pass lane's term
+            const W t0 = pull<W>(src, s0), t1 = pull<W>(src, s1);
+            bool ok = false;
+            A ar = 0, ai = 0;
+            T xv[NV * C];
 #pragma unroll
-    for (int v = 0; v < NV * C; ++v)
-        gst(Y + base + v, (T)fmadd<A>(diag, (A)gld(X + base + v), rn * acc[v]));
+            for (int v = 0; v < NV * C; ++v) xv[v] = T(0);
+            if (has) {
+                const W t = (second ? t1 : t0) ^ flip;
+                int u, cnt;
+                const auto idx = locate<W, KIND, A>(d, S, t, u, cnt);
+                if (idx >= 0) {
+                    ok = true;
+                    const A f = bd.h * S.sq[cnt];
+                    const auto c = S.chi[u];
+                    ar = f * c.x;
+                    if constexpr (CPLX) ai = f * c.y;
+                    const size_t xb = sizeof(W) == 4
+                                          ? (uint64_t)(uint32_t)idx * (uint32_t)(nvec * C) +
+                                                (uint64_t)(v0 * C)
+                                          : ((size_t)idx * nvec + v0) * C;
+#pragma unroll
+                    for (int v = 0; v < NV * C; ++v) xv[v] = gld(X + xb + v);
+                }
+            }
+            // owners pull their terms back: row 0, then row 1
+#pragma unroll
+            for (int h = 0; h < 2; ++h) {
+                const bool mine = h == 0 ? m0 : m1;
+                const int from = mine ? (h == 0 ? e0 : e1) - p : lane;
+                const bool okq = pull32(from, (int)ok) != 0;
+                const A arq = pull<A>(from, ar);
+                A aiq = 0;
+                if constexpr (CPLX) aiq = pull<A>(from, ai);
+                T xq[NV * C];
+#pragma unroll
+                for (int v = 0; v < NV * C; ++v) xq[v] = pull<T>(from, xv[v]);
+                if (mine && okq) add(h == 0 ? acc0 : acc1, arq, aiq, xq);
+            }
+        }
+    }
+    // the diagonal, (1/4) sum_b Jz_b - (1/2) sum over the unequal-spin bonds
+    // (bond order, as in the row loop), and the stores
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+        const bool okh = h == 0 ? ok0 : ok1;
+        if (!okh) continue;
+        const W sh = h == 0 ? s0 : s1;
+        const int64_t row = h == 0 ? row0 : row1;
+        A junq = 0;
+        for (int b = 0; b < nb; ++b) {
+            const B bd = S.bonds[b];
+            if (unequal(sh, bd)) junq += bd.jz;
+        }
+        const A rn = S.rsq[gld(d.stab + row)];
+        const size_t base = ((size_t)row * nvec + v0) * C;
+        const A diag = (A)d.jz_quarter - A(0.5) * junq;
+        const A *acc = h == 0 ? acc0 : acc1;
+#pragma unroll
+        for (int v = 0; v < NV * C; ++v)
+            gst(Y + base + v, (T)fmadd<A>(diag, (A)gld(X + base + v), rn * acc[v]));
+    }
 }
 
-// rows [r0, r1) of a sector, a wave at a time for the compacted loop (CMP:
-// every lane of a wave takes part in its permutes), a lane at a time otherwise
+// rows [r0, r1) of a sector.  CMP: windows of CMP_ROWS rows per wave (every
+// lane of a wave takes part in its permutes; `first` and `stride` count
+// lanes, so wave w of the launch starts at window w); otherwise a lane per row
 template <class W, int KIND, class T, class A, bool CPLX, int NV, bool CMP>
 __device__ __forceinline__ void process_range(const SectorDesc &d, const Staged<A> &S, int64_t r0,
                                               int64_t r1, int64_t first, int64_t stride,
                                               int64_t nvec, int v0) {
     if constexpr (CMP) {
-        const int64_t wave0 = first - lane_id();
-        for (int64_t rb = r0 + wave0; rb < r1; rb += stride) {
-            const int64_t row = rb + lane_id();
-            process_wave_compact<W, KIND, T, A, CPLX, NV>(d, S, row, row < r1, nvec, v0);
-        }
+        const int64_t wave = (first - lane_id()) / 64, waves = stride / 64;
+        for (int64_t w0 = r0 + wave * CMP_ROWS; w0 < r1; w0 += waves * CMP_ROWS)
+            process_window<W, KIND, T, A, CPLX, NV>(d, S, w0, r1, nvec, v0);
     } else {
         for (int64_t row = r0 + first; row < r1; row += stride)
             process_row<W, KIND, T, A, CPLX, NV>(d, S, row, nvec, v0);

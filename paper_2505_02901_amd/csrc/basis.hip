@@ -320,16 +320,14 @@ __global__ __launch_bounds__(256) void k_hash_insert(const W *reps, uint64_t dim
 // are ascending and the colex rank preserves their order) writes its index
 // as the word's count.
 template <class W>
-__global__ __launch_bounds__(256) void k_rank_build(const W *reps, uint64_t dim,
-                                                    const typename RankEntry<W>::type *T, int N,
-                                                    int n_up, int cb, int nc, uint2 *words) {
+__global__ __launch_bounds__(256) void k_rank_build(const W *reps, uint64_t dim, const void *T,
+                                                    RankLayout L, uint2 *words) {
     const uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= dim) return;
-    const uint64_t r = colex_rank<W>(T, N, n_up, cb, nc, reps[i]);
+    const uint64_t r = colex_rank<W>(T, L, reps[i]);
     const uint64_t w = r >> 5;
     atomicOr(&words[w].y, 1u << (uint32_t)(r & 31));
-    if (i == 0 || (colex_rank<W>(T, N, n_up, cb, nc, reps[i - 1]) >> 5) != w)
-        words[w].x = (uint32_t)i;
+    if (i == 0 || (colex_rank<W>(T, L, reps[i - 1]) >> 5) != w) words[w].x = (uint32_t)i;
 }
 
 // index of arbitrary states (-1 when absent)
@@ -337,7 +335,7 @@ struct RankArgs {
     const uint2 *words;
     uint64_t n_words;   // 0: no rank index
     const void *tab;
-    int cb, nc;
+    RankLayout L;
 };
 
 template <class W>
@@ -355,9 +353,7 @@ __global__ __launch_bounds__(256) void k_lookup(const uint64_t *states, int64_t 
             const uint64_t lo = s & ((1ull << nlo) - 1), hi = s >> nlo;
             r = (int64_t)lin[(1ull << nlo) + hi] + (int64_t)lin[lo];
         } else if (R.n_words) {
-            r = rank_find(R.words, R.n_words,
-                          colex_rank<W>(static_cast<const typename RankEntry<W>::type *>(R.tab),
-                                        N, n_up, R.cb, R.nc, (W)s));
+            r = rank_find(R.words, R.n_words, colex_rank<W>(R.tab, R.L, (W)s));
         } else if (n_lines) {
             r = hash_find<W>(table, n_lines, empty, (W)s);
         }
@@ -552,25 +548,50 @@ int build_hash(xdg_basis_s *b) {
 // Chunk tables of the colex rank (the layout read by colex_rank): the entry
 // of chunk k, below set bits under it, chunk bits v is the sum over the set
 // bits of v, the i-th (from the bottom) at site p = k cb + q, of
-// C(p, below + i); sites beyond N contribute nothing.  32-bit states: four
-// chunks of 8 sites, rows only for below in [rank_lo, rank_hi], u32 entries.
-// Wider states: every row, the widest chunk whose table stays within 32 KiB
-// (it is staged in LDS by the apply kernels), u64 entries.
-int rank_rows(int N, int n_up, int cb, int nc, bool wide) {
-    if (wide) return nc * (n_up + 1);
-    int rows = 0;
-    for (int k = 0; k < nc; ++k) rows += rank_hi(n_up, cb, k) - rank_lo(N, n_up, cb, k) + 1;
-    return rows;
+// C(p, below + i); sites beyond N contribute nothing.  Rows only for below
+// in [rank_lo, rank_hi] of each chunk.  32-bit states: four chunks of 8
+// sites, u32 entries.  Wider states: the widest chunk (fewest reads) whose
+// table stays within 32 KiB (the apply kernels stage it in LDS), with u32
+// entries saturating at 2^32 - 1 when max_rank, the largest rank the block
+// must resolve, leaves room below that, u64 entries otherwise.
+RankLayout rank_layout(int N, int n_up, bool wide, uint64_t max_rank) {
+    RankLayout L{};
+    auto rows_of = [&](int cb, int nc) {
+        int rows = 0;
+        for (int k = 0; k < nc; ++k) rows += rank_hi(n_up, cb, k) - rank_lo(N, n_up, cb, k) + 1;
+        return rows;
+    };
+    if (!wide) {
+        L.cb = RANK_CB32;
+        L.nc = RANK_NC32;
+        L.e32 = 1;
+    } else {
+        L.e32 = max_rank < 0xFFFFFFFFull - 64 ? 1 : 0;
+        const size_t esz = L.e32 ? 4 : 8;
+        for (L.cb = 8; L.cb > 4; --L.cb) {
+            L.nc = (N + L.cb - 1) / L.cb;
+            if (((size_t)rows_of(L.cb, L.nc) << L.cb) * esz <= 32768) break;
+        }
+        L.nc = (N + L.cb - 1) / L.cb;
+    }
+    int row = 0;
+    for (int k = 0; k < L.nc; ++k) {
+        const int lo = rank_lo(N, n_up, L.cb, k);
+        L.rbase[k] = row - lo;
+        row += rank_hi(n_up, L.cb, k) - lo + 1;
+    }
+    L.rows = row;
+    return L;
 }
 
 template <class E>
-void rank_tables(int N, int n_up, int cb, int nc, bool wide, std::vector<E> &T) {
-    T.assign((size_t)rank_rows(N, n_up, cb, nc, wide) << cb, 0);
-    size_t row = 0;
-    for (int k = 0; k < nc; ++k) {
-        const int lo = wide ? 0 : rank_lo(N, n_up, cb, k);
-        const int hi = wide ? n_up : rank_hi(n_up, cb, k);
-        for (int below = lo; below <= hi; ++below, ++row)
+void rank_tables(int N, int n_up, const RankLayout &L, std::vector<E> &T) {
+    const int cb = L.cb;
+    T.assign((size_t)L.rows << cb, 0);
+    for (int k = 0; k < L.nc; ++k) {
+        const int lo = rank_lo(N, n_up, cb, k), hi = rank_hi(n_up, cb, k);
+        for (int below = lo; below <= hi; ++below) {
+            const size_t row = (size_t)(L.rbase[k] + below);
             for (uint32_t v = 0; v < (1u << cb); ++v) {
                 uint64_t r = 0;
                 int c = below;
@@ -580,22 +601,11 @@ void rank_tables(int N, int n_up, int cb, int nc, bool wide, std::vector<E> &T) 
                     const int p = k * cb + q;
                     if (p < N) r += binomial(p, c);
                 }
+                if (sizeof(E) == 4 && r > 0xFFFFFFFFull) r = 0xFFFFFFFFull;
                 T[(row << cb) | v] = (E)r;
             }
+        }
     }
-}
-
-void rank_shape(int N, int n_up, bool wide, int &cb, int &nc) {
-    if (!wide) {
-        cb = RANK_CB32;
-        nc = RANK_NC32;
-        return;
-    }
-    for (cb = 8; cb > 1; --cb) {
-        nc = (N + cb - 1) / cb;
-        if (((size_t)rank_rows(N, n_up, cb, nc, true) << cb) * 8 <= 32768) break;
-    }
-    nc = (N + cb - 1) / cb;
 }
 
 uint64_t colex_rank_host(uint64_t s) {
@@ -618,29 +628,35 @@ int build_rank(xdg_basis_s *b) {
     const int slots = sizeof(W) == 4 ? 8 : 5;
     const double hash_bytes = 64.0 * std::ceil((double)dim / (slots * 0.5));
     if ((double)n_words * 8.0 > 4.0 * hash_bytes + 64.0 * (1 << 20)) return XDG_OK;
-    using E = typename RankEntry<W>::type;
-    std::vector<E> T;
-    int cb = 0, nc = 0;
-    rank_shape(b->n_sites, b->n_up, sizeof(W) == 8, cb, nc);
-    rank_tables<E>(b->n_sites, b->n_up, cb, nc, sizeof(W) == 8, T);
+    const RankLayout L = rank_layout(b->n_sites, b->n_up, sizeof(W) == 8, colex_rank_host(last));
+    std::vector<uint32_t> T32;
+    std::vector<uint64_t> T64;
+    const void *T = nullptr;
+    size_t tbytes = 0;
+    if (L.e32) {
+        rank_tables<uint32_t>(b->n_sites, b->n_up, L, T32);
+        T = T32.data();
+        tbytes = T32.size() * 4;
+    } else {
+        rank_tables<uint64_t>(b->n_sites, b->n_up, L, T64);
+        T = T64.data();
+        tbytes = T64.size() * 8;
+    }
     // the table read of the device rank must give the plain colex rank
-    if (colex_rank<W>(T.data(), b->n_sites, b->n_up, cb, nc, (W)last) != colex_rank_host(last)) {
+    if (colex_rank<W>(T, L, (W)last) != colex_rank_host(last)) {
         set_error("internal: colex chunk tables disagree with the colex rank");
         return XDG_EINVAL;
     }
-    XDG_RETURN_IF(b->rtab.upload(T.data(), T.size() * sizeof(E)));
+    XDG_RETURN_IF(b->rtab.upload(T, tbytes));
     XDG_RETURN_IF(b->rwords.alloc(8 * n_words));
     XDG_TRY_HIP(hipMemset(b->rwords.p, 0, 8 * n_words));
     const int block = 256;
     hipLaunchKernelGGL(k_rank_build<W>, dim3((unsigned)((dim + block - 1) / block)), dim3(block), 0,
-                       0, b->reps.as<W>(), dim, b->rtab.as<E>(), b->n_sites, b->n_up, cb, nc,
-                       b->rwords.as<uint2>());
+                       0, b->reps.as<W>(), dim, b->rtab.p, L, b->rwords.as<uint2>());
     XDG_TRY_HIP(hipGetLastError());
     XDG_TRY_HIP(hipDeviceSynchronize());
     b->n_rwords = n_words;
-    b->rank_cb = cb;
-    b->rank_nc = nc;
-    b->rank_rows = rank_rows(b->n_sites, b->n_up, cb, nc, sizeof(W) == 8);
+    b->rank = L;
     return XDG_OK;
 }
 
@@ -753,7 +769,7 @@ int basis_lookup(xdg_basis_s *b, const uint64_t *d_states, int64_t n, int64_t *d
     const int block = 256;
     const unsigned grid = (unsigned)((n + block - 1) / block);
     const int u1 = b->plan.kind == K_U1;
-    const RankArgs R{b->rwords.as<uint2>(), b->n_rwords, b->rtab.p, b->rank_cb, b->rank_nc};
+    const RankArgs R{b->rwords.as<uint2>(), b->n_rwords, b->rtab.p, b->rank};
     if (b->wide) {
         const uint64_t empty = b->n_up == b->n_sites ? 0ull : ~0ull;
         hipLaunchKernelGGL(k_lookup<uint64_t>, dim3(grid), dim3(block), 0, st, d_states, n, d_idx,

@@ -80,13 +80,17 @@ __host__ __device__ __forceinline__ W rev_n(W t, int N) {
 // Colex rank of a state among the states of its popcount: the i-th set bit
 // (from the bottom, i = 1, 2, ...) at site p contributes C(p, i).  It is
 // summed per chunk of cb sites from tables indexed by (chunk k, below = set
-// bits under the chunk, v = the chunk's bits).
+// bits under the chunk, v = the chunk's bits).  For states of n_up set bits
+// on N sites, below lies in [rank_lo(k), rank_hi(k)] for chunk k, and only
+// those rows are stored, chunk after chunk: chunk k's row for `below` is
+// rbase[k] + below.
 //  * 32-bit states: four chunks of 8 sites and 4-byte entries (C(32, 16) <
-//    2^32).  For states of n_up set bits on N sites, below lies in
-//    [rank_lo, rank_hi] for chunk k, and only those rows are stored, chunk
-//    after chunk; the four reads are independent and issued together.
-//  * wider states: nc chunks of cb sites, every row below = 0 .. n_up,
-//    8-byte entries, read chunk after chunk.
+//    2^32); the four reads are independent and issued together.
+//  * wider states: nc chunks of cb sites (the widest whose table stays small
+//    enough for LDS), read chunk after chunk; 4-byte entries that saturate at
+//    2^32 - 1 when every rank of the block's basis states is below that (a
+//    rank read as >= 2^32 - 1 lies beyond every index word), 8-byte entries
+//    otherwise.
 constexpr int RANK_CB32 = 8, RANK_NC32 = 4;
 
 template <class W> struct RankEntry { using type = uint64_t; };
@@ -100,33 +104,42 @@ __host__ __device__ inline int rank_hi(int n_up, int cb, int k) {
     return k * cb < n_up ? k * cb : n_up;
 }
 
+// T: the table (u32 entries for 32-bit states or e32, u64 otherwise).
 template <class W>
-__host__ __device__ __forceinline__ uint64_t colex_rank(const typename RankEntry<W>::type *T,
-                                                        int N, int n_up, int cb, int nc, W s) {
+__host__ __device__ __forceinline__ uint64_t colex_rank(const void *T, const RankLayout &L, W s) {
     if constexpr (sizeof(W) == 4) {
-        (void)cb;
-        (void)nc;
+        const uint32_t *T32 = static_cast<const uint32_t *>(T);
         uint32_t e[RANK_NC32];
-        int row = 0;
         uint32_t below = 0;
 #pragma unroll
         for (int k = 0; k < RANK_NC32; ++k) {
-            const int lo = rank_lo(N, n_up, RANK_CB32, k);
             const uint32_t v = (s >> (k * RANK_CB32)) & 0xFFu;
-            e[k] = T[((uint32_t)(row + (int)below - lo) << RANK_CB32) | v];
+            e[k] = T32[((uint32_t)(L.rbase[k] + (int)below) << RANK_CB32) | v];
             below += (uint32_t)__builtin_popcount(v);
-            row += rank_hi(n_up, RANK_CB32, k) - lo + 1;
         }
         return (uint64_t)((e[0] + e[1]) + (e[2] + e[3]));
     } else {
-        const uint32_t nb = (uint32_t)n_up + 1;
+        // one chunk after the other (a loop the compiler keeps rolled: few
+        // live registers); 4-byte entries are summed in 64 bits, so a rank
+        // from 2^32 - 1 on reads as a value >= 2^32 - 1 (exact below)
+        const int cb = L.cb, nc = L.nc;
         const uint32_t mask = (1u << cb) - 1;
-        uint64_t r = 0;
         uint32_t below = 0;
-        for (int k = 0; k < nc; ++k) {
-            const uint32_t v = (uint32_t)(s >> (k * cb)) & mask;
-            r += T[(((uint32_t)k * nb + below) << cb) | v];
-            below += (uint32_t)__builtin_popcountll(v);
+        uint64_t r = 0;
+        if (L.e32) {
+            const uint32_t *T32 = static_cast<const uint32_t *>(T);
+            for (int k = 0; k < nc; ++k) {
+                const uint32_t v = (uint32_t)(s >> (k * cb)) & mask;
+                r += T32[((uint32_t)(L.rbase[k] + (int)below) << cb) | v];
+                below += (uint32_t)__builtin_popcount(v);
+            }
+        } else {
+            const uint64_t *T64 = static_cast<const uint64_t *>(T);
+            for (int k = 0; k < nc; ++k) {
+                const uint32_t v = (uint32_t)(s >> (k * cb)) & mask;
+                r += T64[((uint32_t)(L.rbase[k] + (int)below) << cb) | v];
+                below += (uint32_t)__builtin_popcount(v);
+            }
         }
         return r;
     }
@@ -145,6 +158,17 @@ __device__ __forceinline__ int64_t rank_find(const uint2 *words, uint64_t n_word
     const uint32_t b = (uint32_t)r & 31u;
     const int64_t idx = (int64_t)cnt + __popc(bits & ((1u << b) - 1u));
     return ((bits >> b) & 1u) ? idx : -1;
+}
+
+// The same for ranks below 2^32 in 32-bit arithmetic (positions below 2^32).
+__device__ __forceinline__ int64_t rank_find_r32(const uint2 *words, uint32_t n_words, uint32_t r) {
+    const uint32_t w = r >> 5;
+    if (w >= n_words) return -1;
+    const uint64_t e = gld(reinterpret_cast<const uint64_t *>(words) + w);
+    const uint32_t cnt = (uint32_t)e, bits = (uint32_t)(e >> 32);
+    const uint32_t b = r & 31u;
+    const uint32_t idx = cnt + __popc(bits & ((1u << b) - 1u));
+    return ((bits >> b) & 1u) ? (int64_t)idx : -1;
 }
 
 // The same for ranks and positions below 2^31 (32-bit states: every colex

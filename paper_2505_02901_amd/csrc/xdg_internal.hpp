@@ -126,6 +126,15 @@ struct DeviceSearch {
     uint32_t lds_sub_bytes = 0;   // bytes of mintop + cand_off + cand_list staged in LDS
 };
 
+// Layout of the colex-rank chunk tables of a block (see colex_rank).
+constexpr int RANK_MAXC = 16;   // chunks of a wide state (cb >= 4 for N <= 64)
+struct RankLayout {
+    int cb, nc;
+    int e32;                 // wide states: saturating 4-byte entries
+    int rows;                // rows of the whole table
+    int rbase[RANK_MAXC];    // chunk k, below b: row rbase[k] + b
+};
+
 struct HashIndex {
     uint64_t n_lines = 0;   // 64-byte lines
     int slots = 0;          // 8 (32-bit keys) or 5 (64-bit keys)
@@ -154,7 +163,7 @@ struct xdg_basis_s {
     xdg::DevBuf rwords;
     uint64_t n_rwords = 0;      // 0: the hash index is used
     xdg::DevBuf rtab;
-    int rank_cb = 0, rank_nc = 0, rank_rows = 0;
+    xdg::RankLayout rank{};     // layout of rtab (chunks, entry size, row bases)
     int lin_nlo = 0, lin_nhi = 0;
     // sublattice tables on the device: t_pid = u32 [n_sym][n_s], the offset of
     // the block permutation's tables in t_tperm << 8 | first bit of the source block

@@ -29,17 +29,26 @@ static uint64_t colex_plain(uint64_t s) {
     return r;
 }
 
+// one layout: 32-bit states; wide states with the layout chosen for the
+// largest rank of the sector, forced 8-byte entries, and forced saturating
+// 4-byte entries (ranks from 2^32 - 1 on must read as at least 2^32 - 1)
 template <class W>
-static int check_rank(int N, int n_up, std::mt19937_64 &g) {
-    using E = typename RankEntry<W>::type;
+static int check_rank_layout(int N, int n_up, uint64_t max_rank, std::mt19937_64 &g) {
     const bool wide = sizeof(W) == 8;
-    int cb = 0, nc = 0;
-    rank_shape(N, n_up, wide, cb, nc);
-    std::vector<E> T;
-    rank_tables<E>(N, n_up, cb, nc, wide, T);
+    const RankLayout L = rank_layout(N, n_up, wide, max_rank);
+    std::vector<uint32_t> T32;
+    std::vector<uint64_t> T64;
+    const void *T;
+    if (L.e32) {
+        rank_tables<uint32_t>(N, n_up, L, T32);
+        T = T32.data();
+    } else {
+        rank_tables<uint64_t>(N, n_up, L, T64);
+        T = T64.data();
+    }
     int bad = 0;
     std::vector<int> perm(N);
-    for (int it = 0; it < 300; ++it) {
+    for (int it = 0; it < 200; ++it) {
         for (int i = 0; i < N; ++i) perm[i] = i;
         for (int i = 0; i < n_up; ++i) std::swap(perm[i], perm[i + (int)(g() % (uint64_t)(N - i))]);
         uint64_t s = 0;
@@ -47,7 +56,25 @@ static int check_rank(int N, int n_up, std::mt19937_64 &g) {
         const uint64_t low = n_up ? (~0ull >> (64 - n_up)) : 0;
         if (it == 0) s = low;
         if (it == 1) s = low << (N - n_up);
-        if (colex_rank<W>(T.data(), N, n_up, cb, nc, (W)s) != colex_plain(s)) ++bad;
+        const uint64_t want = colex_plain(s), got = colex_rank<W>(T, L, (W)s);
+        // saturating 4-byte entries: exact below 2^32 - 1, at least that above
+        if (wide && L.e32 && want >= 0xFFFFFFFFull) {
+            if (got < 0xFFFFFFFFull) ++bad;
+        } else if (got != want) {
+            ++bad;
+        }
+    }
+    return bad;
+}
+
+template <class W>
+static int check_rank(int N, int n_up, std::mt19937_64 &g) {
+    const uint64_t low = n_up ? (~0ull >> (64 - n_up)) : 0;
+    const uint64_t top = colex_plain(low << (N - n_up));
+    int bad = check_rank_layout<W>(N, n_up, top, g);
+    if (sizeof(W) == 8) {
+        bad += check_rank_layout<W>(N, n_up, ~0ull, g);   // 8-byte entries
+        bad += check_rank_layout<W>(N, n_up, 0, g);       // saturating 4-byte entries
     }
     return bad;
 }
