@@ -114,6 +114,14 @@ typedef struct xdg_basis_opts {
 #define XDG_INDEX_HASH 2
 #define XDG_INDEX_RANK 3
 
+/* Limit on the device memory the library's own buffers (bases, indices,
+ * tables, Lanczos work vectors, batched plans) may hold together, in bytes;
+ * 0 removes it.  An allocation beyond it fails with XDG_ENOMEM as if the
+ * device were full (the caller's own vectors do not count).  Applies to
+ * every thread.  `in_use` (may be NULL) receives what the buffers hold now.
+ * Host only. */
+int xdg_set_device_memory_limit(int64_t bytes, int64_t *in_use);
+
 /* Version string of the library (cf. the version banner, Sec. 2). */
 const char *xdg_version(void);
 

@@ -14,11 +14,37 @@
 namespace xdg {
 
 // ------------------------------------------------------------------ utils --
+// Device memory held by the library's buffers, and the caller's limit on it
+// (0 = none), see xdg_set_device_memory_limit.
+static std::atomic<uint64_t> g_dev_bytes{0};
+static std::atomic<uint64_t> g_dev_limit{0};
+
+void set_device_memory_limit(uint64_t bytes) { g_dev_limit.store(bytes); }
+uint64_t device_memory_in_use() { return g_dev_bytes.load(); }
+
+void DevBuf::release() {
+    if (p) {
+        (void)hipFree(p);
+        g_dev_bytes.fetch_sub(bytes);
+    }
+    p = nullptr;
+    bytes = 0;
+}
+
 int DevBuf::alloc(size_t n) {
     release();
     if (n == 0) return XDG_OK;
+    const uint64_t limit = g_dev_limit.load();
+    const uint64_t held = g_dev_bytes.fetch_add(n) + n;
+    if (limit && held > limit) {
+        g_dev_bytes.fetch_sub(n);
+        set_error("device memory limit: %zu more bytes would bring the library to %llu of %llu",
+                  n, (unsigned long long)held, (unsigned long long)limit);
+        return XDG_ENOMEM;
+    }
     hipError_t e = hipMalloc(&p, n);
     if (e != hipSuccess) {
+        g_dev_bytes.fetch_sub(n);
         p = nullptr;
         (void)hipGetLastError();
         set_error("hipMalloc(%zu bytes) failed: %s", n, hipGetErrorString(e));

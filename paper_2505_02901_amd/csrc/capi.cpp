@@ -292,6 +292,16 @@ int xdg_ham_nnz(xdg_ham h, int64_t *nnz) {
     });
 }
 
+int xdg_set_device_memory_limit(int64_t bytes, int64_t *in_use) {
+    if (bytes < 0) {
+        set_error("memory limit must be >= 0");
+        return XDG_EINVAL;
+    }
+    set_device_memory_limit((uint64_t)bytes);
+    if (in_use) *in_use = (int64_t)device_memory_in_use();
+    return XDG_OK;
+}
+
 int xdg_ham_dim(xdg_ham h, int64_t *dim, int *is_complex) {
     return guarded([&]() -> int {
         if (!h) {

@@ -44,11 +44,7 @@ struct DevBuf {
     DevBuf(const DevBuf &) = delete;
     DevBuf &operator=(const DevBuf &) = delete;
     ~DevBuf() { release(); }
-    void release() {
-        if (p) (void)hipFree(p);
-        p = nullptr;
-        bytes = 0;
-    }
+    void release();
     int alloc(size_t n);                      // XDG_OK / XDG_ENOMEM
     int upload(const void *host, size_t n);   // alloc + copy
     template <class T> T *as() const { return static_cast<T *>(p); }
@@ -99,6 +95,11 @@ struct Plan {
     std::vector<int16_t> ring_gidx;
     int flags = 0;   // XDG_FLAG_*
 };
+
+// The library's device memory: a caller-set limit on what its buffers may
+// hold together (0 = none), and what they hold now.
+void set_device_memory_limit(uint64_t bytes);
+uint64_t device_memory_in_use();
 
 // Transfers between host memory and the device through a page-locked
 // staging buffer, complete on return.

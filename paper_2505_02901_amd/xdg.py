@@ -79,6 +79,7 @@ def lib():
             "xdg_destroy_hamiltonian": (None, [P]),
             "xdg_ham_nnz": (I, [P, P]),
             "xdg_ham_dim": (I, [P, P, P]),
+            "xdg_set_device_memory_limit": (I, [I64, P]),
             "xdg_apply": (I, [P, P, P, I64, I, P]),
             "xdg_apply_batched": (I, [I, P, P, P, I64, I, P]),
             "xdg_apply_batched_noalloc": (I, [I, P, P, P, I64, I, P]),
@@ -108,7 +109,8 @@ def exported_names():
             "xdg_basis_is_complex", "xdg_basis_search_kind", "xdg_basis_index_kind",
             "xdg_basis_copy_states",
             "xdg_basis_copy_stabilisers", "xdg_basis_index", "xdg_create_hamiltonian",
-            "xdg_destroy_hamiltonian", "xdg_ham_nnz", "xdg_ham_dim", "xdg_apply",
+            "xdg_destroy_hamiltonian", "xdg_ham_nnz", "xdg_ham_dim",
+            "xdg_set_device_memory_limit", "xdg_apply",
             "xdg_apply_batched", "xdg_apply_batched_noalloc", "xdg_apply_with_config",
             "xdg_apply_tuned_config",
             "xdg_random_state", "xdg_lanczos_eigval", "xdg_lanczos_eigval_batched",
@@ -217,6 +219,14 @@ def _dtype_code(t) -> int:
 
 
 # ------------------------------------------------------------------ C names --
+
+def xdg_set_device_memory_limit(bytes_: int) -> int:
+    """Cap the device memory of the library's own buffers (0 = no cap);
+    returns what they hold now."""
+    used = C.c_int64()
+    _check(lib().xdg_set_device_memory_limit(int(bytes_), C.byref(used)))
+    return used.value
+
 
 def xdg_version() -> str:
     return lib().xdg_version().decode()

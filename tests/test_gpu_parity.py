@@ -382,6 +382,73 @@ def test_every_launch_shape_gives_the_same_y(X, case):
         X.xdg_apply_tuned_config(H.handle, code, 7)
 
 
+def test_failure_paths(X):
+    """XDG_ENOMEM under a cap on the library's device memory (the call fails
+    cleanly and works again once the cap is lifted), XDG_ENOCONV with the
+    outputs written, and a negative cap refused."""
+    m = W.chain_model(24, l=0)
+    used = X.xdg_set_device_memory_limit(0)
+    try:
+        X.xdg_set_device_memory_limit(used + (64 << 10))
+        with pytest.raises(X.XdgError) as e:
+            X.Basis.from_model(m)
+        assert e.value.code == X.XDG_ENOMEM
+        assert "limit" in str(e.value)
+    finally:
+        X.xdg_set_device_memory_limit(0)
+    b = X.Basis.from_model(m)
+    H = X.Hamiltonian.from_model(b, m)
+    assert X.xdg_set_device_memory_limit(0) > used
+    rc, ev, al, be = H.lanczos(k=1, tol=1e-15, max_iter=3, seed=1)
+    assert rc == X.XDG_ENOCONV and len(al) == 3 and np.isfinite(ev[0])
+    rc, ev, al, be = H.lanczos(k=1, tol=0.0, max_iter=3, seed=1)
+    assert rc == X.XDG_OK
+    with pytest.raises(X.XdgError):
+        X.xdg_set_device_memory_limit(-1)
+
+
+def test_batched_plans_follow_new_pointers(X):
+    """Cached batched plans are keyed by the vectors: new tensors, then the
+    first ones again, all give the single-block results; batched Lanczos
+    runs from two different start blocks match single-vector runs from the
+    same columns."""
+    ms = [W.chain_model(14, l=l) for l in (0, 3, 7)]
+    bs = [X.Basis.from_model(m) for m in ms]
+    hs = [X.Hamiltonian.from_model(b, m) for b, m in zip(bs, ms)]
+    handles = [h.handle for h in hs]
+    g = torch.Generator(device="cuda").manual_seed(5)
+
+    def block():
+        return [torch.randn(b.dim, 2, dtype=torch.complex128, device="cuda", generator=g)
+                for b in bs]
+
+    def check(xs):
+        ys = [torch.full_like(x, float("nan")) for x in xs]
+        X.xdg_apply_batched(handles, xs, ys)
+        for h, x, y in zip(hs, xs, ys):
+            r = torch.empty_like(x)
+            h.apply(x, r)
+            torch.cuda.synchronize()
+            assert torch.equal(r, y)
+    xa, xb = block(), block()
+    check(xa)
+    check(xb)
+    check(xa)
+    for v0s in (block(), block()):
+        # a real block gets a real start block (the complex recurrence then
+        # stays real and equals the real one)
+        v0s = [v if b.is_complex else torch.complex(v.real, torch.zeros_like(v.real))
+               for v, b in zip(v0s, bs)]
+        ev, al, be = X.xdg_lanczos_eigval_batched(handles, nvec=2, n_iter=25, prec=0, v0s=v0s)
+        for i, h in enumerate(hs):
+            for c in range(2):
+                col = v0s[i][:, c]
+                col = (col if bs[i].is_complex else col.real).contiguous()
+                st, e1, a1, b1 = h.lanczos(k=1, tol=0.0, max_iter=25, prec=0, v0=col)
+                assert abs(ev[i, c] - e1[0]) < 1e-10 * abs(e1[0]), (i, c, ev[i, c], e1[0])
+                assert np.max(np.abs(al[i, c, :10] - a1[:10])) < 1e-10
+
+
 def test_binding_refuses_mismatched_tensors(X):
     """Sizes and dtypes are checked against the block before any launch: a
     tensor from a larger sector or an FP32 y for an FP64 x raises ValueError."""

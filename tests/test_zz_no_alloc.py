@@ -72,3 +72,34 @@ def test_noalloc_refuses_more_blocks_than_its_array_holds(X):
     assert e.value.code == X.XDG_EINVAL
     X.xdg_apply_batched_noalloc([h.handle] * 3, [x] * 3, [y] * 3)   # within the limit
     torch.cuda.synchronize()
+
+
+def test_noalloc_replays_from_a_captured_graph(X):
+    """Allocating nothing, the call can be captured into a graph: every replay
+    (with other work and a clobbered output in between) gives the eager y."""
+    ms = [W.chain_model(16, l=l) for l in (0, 5, 11)]
+    bs, hs, xs = blocks(X, ms, 2, torch.complex64, 7)
+    handles = [h.handle for h in hs]
+    ys = [torch.empty_like(x) for x in xs]
+    X.xdg_apply_batched_noalloc(handles, xs, ys)      # eager (takes the array's address)
+    torch.cuda.synchronize()
+    ref = [y.clone() for y in ys]
+    s = torch.cuda.Stream()
+    s.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(s):
+        X.xdg_apply_batched_noalloc(handles, xs, ys, stream=s)
+    torch.cuda.current_stream().wait_stream(s)
+    torch.cuda.synchronize()
+    graph = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(graph):
+        X.xdg_apply_batched_noalloc(handles, xs, ys, stream=torch.cuda.current_stream())
+    for rep in range(4):
+        for y in ys:
+            y.fill_(float("nan"))
+        z = torch.randn(1 << 16, device="cuda").sum()      # other eager work
+        torch.cuda.synchronize()
+        graph.replay()
+        torch.cuda.synchronize()
+        for i, (y, r) in enumerate(zip(ys, ref)):
+            assert torch.equal(y, r), (rep, i)
+        del z
