@@ -346,7 +346,8 @@ int ham_count_nnz(xdg_ham_s *h, int64_t *nnz) {
 }
 
 int batch_plan_host(int n, xdg_ham_s *const *hams, const void *const *xs, void *const *ys,
-                    int64_t nvec, int dtype, BatchMeta *P, SectorDesc *descs, uint32_t *prefix) {
+                    int64_t nvec, int dtype, BatchMeta *P, SectorDesc *descs, uint32_t *prefix,
+                    uint32_t tile_rows) {
     if (n < 1) {
         set_error("batched apply needs at least one block");
         return XDG_EINVAL;
@@ -377,7 +378,9 @@ int batch_plan_host(int n, xdg_ham_s *const *hams, const void *const *xs, void *
     P->tsingle = P->single && !P->acc64;
     P->cplx = any_cplx;
     P->cols = (dtype_complex(dtype) && !any_cplx) ? 2 * nvec : nvec;
-    P->tile_rows = 4 * APPLY_BLOCK;
+    // rows per work item: a multiple of the workgroup (default four rows per lane)
+    P->tile_rows = tile_rows ? (tile_rows + APPLY_BLOCK - 1) / APPLY_BLOCK * APPLY_BLOCK
+                             : 4 * APPLY_BLOCK;
     size_t lds_full = 0, lds_part = 0;
     uint64_t acc = 0;
     for (int i = 0; i < n; ++i) {
@@ -405,14 +408,15 @@ int batch_plan_host(int n, xdg_ham_s *const *hams, const void *const *xs, void *
 }
 
 int batch_prepare(int n, xdg_ham_s *const *hams, const void *const *xs, void *const *ys,
-                  int64_t nvec, int dtype, BatchPlan *P) {
+                  int64_t nvec, int dtype, BatchPlan *P, uint32_t tile_rows) {
     if (n < 1) {
         set_error("batched apply needs at least one block");
         return XDG_EINVAL;
     }
     std::vector<SectorDesc> descs(n);
     std::vector<uint32_t> prefix(n + 1, 0);
-    XDG_RETURN_IF(batch_plan_host(n, hams, xs, ys, nvec, dtype, P, descs.data(), prefix.data()));
+    XDG_RETURN_IF(batch_plan_host(n, hams, xs, ys, nvec, dtype, P, descs.data(), prefix.data(),
+                                  tile_rows));
     XDG_RETURN_IF(P->descs.upload(descs.data(), sizeof(SectorDesc) * n));
     XDG_RETURN_IF(P->prefix.upload(prefix.data(), sizeof(uint32_t) * (n + 1)));
     XDG_RETURN_IF(P->queue.alloc(sizeof(uint32_t)));

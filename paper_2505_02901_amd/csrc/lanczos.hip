@@ -16,6 +16,8 @@
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
+#include <map>
+#include <mutex>
 #include <vector>
 
 #include "xdg_internal.hpp"
@@ -1022,58 +1024,84 @@ int lanczos_batched(int n, xdg_ham_s *const *hams, const void *const *v0s, int64
     }
     auto vecp = [&](int i, int slot) -> char * { return S[i].buf.as<char>() + S[i].slot * slot; };
     // phase p: v = slot p, vprev = slot (p+2)%3 (none at j = 0), next = slot (p+1)%3, w = slot 3
-    BatchPlan plans[3];
     std::vector<xdg_ham_s *> hv(hams, hams + n);
-    for (int p = 0; p < 3; ++p) {
+    auto prepare = [&](int p, BatchPlan *P, uint32_t tile) -> int {
         std::vector<const void *> xs(n);
         std::vector<void *> ys(n);
         for (int i = 0; i < n; ++i) {
             xs[i] = vecp(i, p);
             ys[i] = vecp(i, 3);
         }
-        XDG_RETURN_IF(batch_prepare(n, hv.data(), xs.data(), ys.data(), nvec, dtype, &plans[p]));
-    }
-    // choose the persistent grid once per set of blocks (outside capture):
-    // a few sizes, timed; remembered for later calls on the same blocks
-    static std::map<std::vector<const void *>, int> grid_cache;
-    static std::mutex grid_mu;   // held while the grid is looked up or tuned
-    std::unique_lock<std::mutex> grid_lock(grid_mu);
+        return batch_prepare(n, hv.data(), xs.data(), ys.data(), nvec, dtype, P, tile);
+    };
+    // launch shape of the batched apply, chosen once per set of blocks
+    // (outside capture) and remembered: the persistent grid (1, 2 or 4
+    // workgroups per compute unit), then the rows per work item (1k - 16k),
+    // then the vectors per pass (8, 4, 2); XDG_TUNE_LOG=1 prints the timings
+    struct Shape {
+        int grid;
+        uint32_t tile;
+        int nv;
+    };
+    static std::map<std::vector<const void *>, Shape> shape_cache;
+    static std::mutex shape_mu;   // held while the shape is looked up or tuned
     std::vector<const void *> gkey;
     for (int i = 0; i < n; ++i) {
         gkey.push_back(hams[i]);
         gkey.push_back(reinterpret_cast<const void *>((uintptr_t)hams[i]->serial));
     }
     gkey.push_back(reinterpret_cast<const void *>((intptr_t)(nvec * 8 + dtype)));
-    int best_grid = apply_grid_for(2);
-    auto cached = grid_cache.find(gkey);
-    if (cached != grid_cache.end()) {
-        best_grid = cached->second;
-    } else {
-        hipEvent_t e0, e1;
-        XDG_TRY_HIP(hipEventCreate(&e0));
-        XDG_TRY_HIP(hipEventCreate(&e1));
-        float best = 1e30f;
-        for (int mult : {1, 2, 4}) {
-            const int g = apply_grid_for(mult);
-            XDG_RETURN_IF(batch_launch(plans[0], g, 8, st));
-            XDG_TRY_HIP(hipEventRecord(e0, st));
-            XDG_RETURN_IF(batch_launch(plans[0], g, 8, st));
-            XDG_TRY_HIP(hipEventRecord(e1, st));
-            XDG_TRY_HIP(hipEventSynchronize(e1));
-            float ms = 0;
-            XDG_TRY_HIP(hipEventElapsedTime(&ms, e0, e1));
-            if (ms < best) {
-                best = ms;
-                best_grid = g;
-            }
+    Shape best_shape{apply_grid_for(2), 4 * 1024, 8};
+    {
+        std::unique_lock<std::mutex> shape_lock(shape_mu);
+        auto cached = shape_cache.find(gkey);
+        if (cached != shape_cache.end()) {
+            best_shape = cached->second;
+        } else {
+            hipEvent_t e0, e1;
+            XDG_TRY_HIP(hipEventCreate(&e0));
+            XDG_TRY_HIP(hipEventCreate(&e1));
+            const char *log = getenv("XDG_TUNE_LOG");
+            float best = 1e30f;
+            auto time_shape = [&](const Shape &sh) -> int {
+                BatchPlan P;
+                XDG_RETURN_IF(prepare(0, &P, sh.tile));
+                XDG_RETURN_IF(batch_launch(P, sh.grid, sh.nv, st));
+                XDG_TRY_HIP(hipEventRecord(e0, st));
+                XDG_RETURN_IF(batch_launch(P, sh.grid, sh.nv, st));
+                XDG_TRY_HIP(hipEventRecord(e1, st));
+                XDG_TRY_HIP(hipEventSynchronize(e1));
+                float ms = 0;
+                XDG_TRY_HIP(hipEventElapsedTime(&ms, e0, e1));
+                if (log && atoi(log) > 0)
+                    fprintf(stderr, "[xdg tune] batched %d blocks nvec %lld: grid %d tile %u "
+                            "nv %d: %.3f ms\n", n, (long long)nvec, sh.grid, sh.tile, sh.nv, ms);
+                if (ms < best) {
+                    best = ms;
+                    best_shape = sh;
+                }
+                return XDG_OK;
+            };
+            int rc = XDG_OK;
+            for (int mult : {1, 2, 4})
+                if (rc == XDG_OK) rc = time_shape({apply_grid_for(mult), 4 * 1024, 8});
+            const Shape g = best_shape;
+            for (uint32_t tile : {1024u, 2048u, 8192u, 16384u})
+                if (rc == XDG_OK) rc = time_shape({g.grid, tile, g.nv});
+            const Shape t = best_shape;
+            for (int nv : {4, 2})
+                if (rc == XDG_OK && nv < cols) rc = time_shape({t.grid, t.tile, nv});
+            (void)hipEventDestroy(e0);
+            (void)hipEventDestroy(e1);
+            XDG_RETURN_IF(rc);
+            shape_cache[gkey] = best_shape;
         }
-        (void)hipEventDestroy(e0);
-        (void)hipEventDestroy(e1);
-        grid_cache[gkey] = best_grid;
     }
-    grid_lock.unlock();
+    BatchPlan plans[3];
+    for (int p = 0; p < 3; ++p) XDG_RETURN_IF(prepare(p, &plans[p], best_shape.tile));
+    const int best_grid = best_shape.grid;
     auto enqueue_step = [&](int p, bool first) -> int {
-        XDG_RETURN_IF(batch_launch(plans[p], best_grid, 8, st));
+        XDG_RETURN_IF(batch_launch(plans[p], best_grid, best_shape.nv, st));
         for (int i = 0; i < n; ++i) {
             Sec &s = S[i];
             char *v = vecp(i, p), *w = vecp(i, 3);

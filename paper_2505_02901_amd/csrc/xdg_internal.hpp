@@ -248,9 +248,10 @@ struct SectorDesc;
 // Host planning of a batch: fills M, and (when not null) descs[n] and
 // prefix[n + 1] in host memory.  Allocates nothing.
 int batch_plan_host(int n, xdg_ham_s *const *hams, const void *const *xs, void *const *ys,
-                    int64_t nvec, int dtype, BatchMeta *M, SectorDesc *descs, uint32_t *prefix);
+                    int64_t nvec, int dtype, BatchMeta *M, SectorDesc *descs, uint32_t *prefix,
+                    uint32_t tile_rows = 0);
 int batch_prepare(int n, xdg_ham_s *const *hams, const void *const *xs, void *const *ys,
-                  int64_t nvec, int dtype, BatchPlan *P);
+                  int64_t nvec, int dtype, BatchPlan *P, uint32_t tile_rows = 0);
 int batch_launch(const BatchPlan &P, int grid, int nv_cap, hipStream_t st);
 // The launch itself on device descriptors, tile prefix and queue counter.
 int batch_launch_raw(const BatchMeta &M, const SectorDesc *d_descs, const uint32_t *d_prefix,
