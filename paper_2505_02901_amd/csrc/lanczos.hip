@@ -202,12 +202,15 @@ __global__ void k_set_scalars(int *jdev, double *prev_beta, int nv) {
 // Reorthogonalisation of one vector against the stored Krylov vectors V_i,
 // i < k (classical Gram-Schmidt: the coefficients c_i = <V_i, w> first, then
 // w -= sum_i c_i V_i; complex when C = 2, conj(V_i) in the product).  Both
-// kernels stream row tiles: each thread owns RU 16-byte chunks of a tile
+// kernels stream row tiles: each thread owns ru 16-byte chunks of a tile
 // (L = 16 / sizeof(T) scalars each, consecutive threads on consecutive
-// chunks), so a block covers RB * RU * L scalars and a column is read with
-// RU independent 16-byte loads per thread; G columns are in flight at once.
+// chunks), so a block covers RB * ru * L scalars and a column is read with
+// ru independent 16-byte loads per thread; RG columns are in flight at once.
 // Sums are FP64 in a fixed order (bitwise reproducible).
-constexpr int RU = 4;   // 16-byte chunks per thread and column
+// 16-byte chunks per thread and column: eight scalars per thread for both
+// types (FP32 with four chunks held too many registers for enough waves)
+template <class T>
+constexpr int ru() { return sizeof(T) == 4 ? 2 : 4; }
 constexpr int RG = 4;   // columns per step
 
 template <class T> struct Chunk16;
@@ -219,7 +222,7 @@ template <> struct Chunk16<double> {
 };
 
 template <class T>
-constexpr int tile_scalars() { return RB * RU * (16 / (int)sizeof(T)); }
+constexpr int tile_scalars() { return RB * ru<T>() * (16 / (int)sizeof(T)); }
 
 // scalars [q, q + L) of column `col` (zero beyond n): one 16-byte load when
 // the chunk is whole, scalar loads at the ragged end
@@ -247,7 +250,7 @@ __device__ __forceinline__ double wave_sum(double v) {
 template <class T, int C>
 __global__ __launch_bounds__(RB) void k_reorth_dots(const T *V, uint64_t ld, int k, const T *w,
                                                     uint64_t nsc, double *partials) {
-    constexpr int L = 16 / (int)sizeof(T), S = RU * L;
+    constexpr int RU = ru<T>(), L = 16 / (int)sizeof(T), S = RU * L;
     __shared__ double sh[RB / 64][RG * C];
     const int nb = gridDim.x, t = threadIdx.x, wave = t >> 6, lane = t & 63;
     const uint64_t tile0 = (uint64_t)blockIdx.x * tile_scalars<T>();
@@ -318,7 +321,7 @@ __global__ __launch_bounds__(RB) void k_reorth_finalize(const double *partials, 
 template <class T, int C>
 __global__ __launch_bounds__(RB) void k_reorth_sub(const T *V, uint64_t ld, int k,
                                                    const double *coef, T *w, uint64_t nsc) {
-    constexpr int L = 16 / (int)sizeof(T), S = RU * L;
+    constexpr int RU = ru<T>(), L = 16 / (int)sizeof(T), S = RU * L;
     const int t = threadIdx.x;
     const uint64_t tile0 = (uint64_t)blockIdx.x * tile_scalars<T>();
     double acc[S];
