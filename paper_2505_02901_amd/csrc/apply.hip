@@ -5,6 +5,7 @@
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
+#include <map>
 #include <mutex>
 #include <vector>
 
@@ -152,6 +153,24 @@ int pick_nv(int64_t remaining, int cap) {
 
 }  // namespace
 
+// LDS bytes the apply kernel stages for this form, whether the sublattice
+// tables fit with them, and whether two workgroups fit one compute unit
+void apply_lds(const xdg_ham_s *h, int dtype, size_t *lds, int *stage_sub, int *occ_ok) {
+    const xdg_basis_s *b = h->basis;
+    const bool tsingle = dtype_single(dtype) && (b->plan.flags & XDG_FLAG_F32_ACCUMULATE);
+    const SectorDesc d = make_desc(h, tsingle, nullptr, nullptr);
+    size_t n = tsingle ? stage_bytes<float>(d, b->plan.kind, 1)
+                       : stage_bytes<double>(d, b->plan.kind, 1);
+    int st = 1;
+    if (n > lds_budget()) {
+        st = 0;
+        n = tsingle ? stage_bytes<float>(d, b->plan.kind, 0) : stage_bytes<double>(d, b->plan.kind, 0);
+    }
+    *lds = n;
+    *stage_sub = st;
+    *occ_ok = st ? occ_for(n) : 0;
+}
+
 int apply_launch(xdg_ham_s *h, const void *x, void *y, int64_t nvec, int dtype, hipStream_t st,
                  const LaunchCfg *cfg) {
     const xdg_basis_s *b = h->basis;
@@ -239,10 +258,15 @@ int apply_tuned(xdg_ham_s *h, const void *x, void *y, int64_t nvec, int dtype, h
         XDG_TRY_HIP(hipEventSynchronize(e1));
         XDG_TRY_HIP(hipEventElapsedTime(ms, e0, e1));
         *ms /= reps;
-        if (tune_log())
-            fprintf(stderr, "[xdg tune] dim %lld dtype %d nvec %lld: grid %d nv %d occ %d "
-                    "compact %d: %.3f ms\n", (long long)b->dim, dtype, (long long)nvec, c.grid,
-                    c.nv, c.occ, c.compact, *ms);
+        if (tune_log()) {
+            size_t lds = 0;
+            int stg = 0, occ_ok = 0;
+            apply_lds(h, dtype, &lds, &stg, &occ_ok);
+            fprintf(stderr, "[xdg tune] dim %lld dtype %d nvec %lld (LDS %zu B, tables staged %d, "
+                    "8-wave copy possible %d): grid %d nv %d occ %d compact %d: %.3f ms\n",
+                    (long long)b->dim, dtype, (long long)nvec, lds, stg, occ_ok, c.grid, c.nv,
+                    c.occ, c.compact, *ms);
+        }
         return XDG_OK;
     };
     std::vector<LaunchCfg> cands;
@@ -455,6 +479,86 @@ int batch_launch(const BatchPlan &P, int grid, int nv_cap, hipStream_t st) {
                             P.queue.as<uint32_t>(), grid, nv_cap, st);
 }
 
+// ------------------------------------------------- batched launch shape --
+// Chosen once per set of blocks (and nvec, dtype) and remembered: the
+// persistent grid (1, 2 or 4 workgroups per compute unit), then the rows per
+// work item (1k - 16k), then the vectors per pass (8, 4, 2).  XDG_TUNE_LOG=1
+// prints the timings.
+namespace {
+std::mutex g_shape_mu;
+std::map<std::vector<const void *>, BatchShape> g_shape_cache;
+
+std::vector<const void *> shape_key(int n, xdg_ham_s *const *hams, int64_t nvec, int dtype) {
+    std::vector<const void *> key;
+    for (int i = 0; i < n; ++i) {
+        key.push_back(hams[i]);
+        key.push_back(reinterpret_cast<const void *>((uintptr_t)hams[i]->serial));
+    }
+    key.push_back(reinterpret_cast<const void *>((intptr_t)(nvec * 8 + dtype)));
+    return key;
+}
+}  // namespace
+
+bool batch_shape_cached(int n, xdg_ham_s *const *hams, int64_t nvec, int dtype, BatchShape *out) {
+    std::lock_guard<std::mutex> lock(g_shape_mu);
+    auto it = g_shape_cache.find(shape_key(n, hams, nvec, dtype));
+    if (it == g_shape_cache.end()) return false;
+    *out = it->second;
+    return true;
+}
+
+int batch_shape_tuned(int n, xdg_ham_s *const *hams, const void *const *xs, void *const *ys,
+                      int64_t nvec, int dtype, hipStream_t st, BatchShape *out) {
+    const auto key = shape_key(n, hams, nvec, dtype);
+    std::lock_guard<std::mutex> lock(g_shape_mu);
+    auto it = g_shape_cache.find(key);
+    if (it != g_shape_cache.end()) {
+        *out = it->second;
+        return XDG_OK;
+    }
+    BatchShape best_shape{apply_grid_for(2), 4 * 1024, 8};
+    hipEvent_t e0, e1;
+    XDG_TRY_HIP(hipEventCreate(&e0));
+    XDG_TRY_HIP(hipEventCreate(&e1));
+    float best = 1e30f;
+    int64_t cols = 1;
+    auto time_shape = [&](const BatchShape &sh) -> int {
+        BatchPlan P;
+        XDG_RETURN_IF(batch_prepare(n, hams, xs, ys, nvec, dtype, &P, sh.tile));
+        cols = P.cols;
+        XDG_RETURN_IF(batch_launch(P, sh.grid, sh.nv, st));
+        XDG_TRY_HIP(hipEventRecord(e0, st));
+        XDG_RETURN_IF(batch_launch(P, sh.grid, sh.nv, st));
+        XDG_TRY_HIP(hipEventRecord(e1, st));
+        XDG_TRY_HIP(hipEventSynchronize(e1));
+        float ms = 0;
+        XDG_TRY_HIP(hipEventElapsedTime(&ms, e0, e1));
+        if (tune_log())
+            fprintf(stderr, "[xdg tune] batched %d blocks nvec %lld: grid %d tile %u nv %d: "
+                    "%.3f ms\n", n, (long long)nvec, sh.grid, sh.tile, sh.nv, ms);
+        if (ms < best) {
+            best = ms;
+            best_shape = sh;
+        }
+        return XDG_OK;
+    };
+    int rc = XDG_OK;
+    for (int mult : {1, 2, 4})
+        if (rc == XDG_OK) rc = time_shape({apply_grid_for(mult), 4 * 1024, 8});
+    const BatchShape g = best_shape;
+    for (uint32_t tile : {1024u, 2048u, 8192u, 16384u})
+        if (rc == XDG_OK) rc = time_shape({g.grid, tile, g.nv});
+    const BatchShape t = best_shape;
+    for (int nv : {4, 2})
+        if (rc == XDG_OK && nv < cols) rc = time_shape({t.grid, t.tile, nv});
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    XDG_RETURN_IF(rc);
+    g_shape_cache[key] = best_shape;
+    *out = best_shape;
+    return XDG_OK;
+}
+
 // ------------------------------------------------- allocation-free batch --
 // One file-scope device array per GPU holds everything the batched launch
 // needs beyond the caller's vectors: the queue counter, the tile prefix and
@@ -528,8 +632,11 @@ int apply_batched_noalloc(int n, xdg_ham_s *const *hams, const void *const *xs,
         }
     thread_local SectorDesc descs[NOALLOC_MAX_SECTORS];
     thread_local uint32_t prefix[NOALLOC_MAX_SECTORS + 1];
+    BatchShape sh;     // a shape tuned earlier for these blocks, else the default
+    const bool tuned = batch_shape_cached(n, hams, nvec, dtype, &sh);
     BatchMeta M;
-    XDG_RETURN_IF(batch_plan_host(n, hams, xs, ys, nvec, dtype, &M, descs, prefix));
+    XDG_RETURN_IF(batch_plan_host(n, hams, xs, ys, nvec, dtype, &M, descs, prefix,
+                                  tuned ? sh.tile : 0));
     unsigned char *base = nullptr;
     XDG_RETURN_IF(scratch_address(&base));
     for (int first = 0; first < n; first += FILL_PER_LAUNCH) {
@@ -545,7 +652,8 @@ int apply_batched_noalloc(int n, xdg_ham_s *const *hams, const void *const *xs,
     }
     return batch_launch_raw(M, reinterpret_cast<const SectorDesc *>(base + NOALLOC_DESC_OFF),
                             reinterpret_cast<const uint32_t *>(base + NOALLOC_PREFIX_OFF),
-                            reinterpret_cast<uint32_t *>(base), 0, 8, st);
+                            reinterpret_cast<uint32_t *>(base), tuned ? sh.grid : 0,
+                            tuned ? sh.nv : 8, st);
 }
 
 int apply_batched_launch(int n, xdg_ham_s *const *hams, const void *const *xs, void *const *ys,
@@ -574,17 +682,20 @@ int apply_batched_launch(int n, xdg_ham_s *const *hams, const void *const *xs, v
     }
     k.nvec = nvec;
     k.dtype = dtype;
+    BatchShape sh;
+    XDG_RETURN_IF(batch_shape_tuned(n, hams, xs, ys, nvec, dtype, st, &sh));
+    k.p.push_back(reinterpret_cast<const void *>((uintptr_t)sh.tile));
     BatchPlan *P = nullptr;
     for (auto &e : cache)
         if (e.first == k) P = e.second.get();
     if (!P) {
         auto up = std::make_unique<BatchPlan>();
-        XDG_RETURN_IF(batch_prepare(n, hams, xs, ys, nvec, dtype, up.get()));
+        XDG_RETURN_IF(batch_prepare(n, hams, xs, ys, nvec, dtype, up.get(), sh.tile));
         if (cache.size() >= 8) cache.erase(cache.begin());
         cache.emplace_back(k, std::move(up));
         P = cache.back().second.get();
     }
-    return batch_launch(*P, grid, 8, st);
+    return batch_launch(*P, grid > 0 ? grid : sh.grid, sh.nv, st);
 }
 
 }  // namespace xdg

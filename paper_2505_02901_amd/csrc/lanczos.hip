@@ -1037,68 +1037,17 @@ int lanczos_batched(int n, xdg_ham_s *const *hams, const void *const *v0s, int64
         }
         return batch_prepare(n, hv.data(), xs.data(), ys.data(), nvec, dtype, P, tile);
     };
-    // launch shape of the batched apply, chosen once per set of blocks
-    // (outside capture) and remembered: the persistent grid (1, 2 or 4
-    // workgroups per compute unit), then the rows per work item (1k - 16k),
-    // then the vectors per pass (8, 4, 2); XDG_TUNE_LOG=1 prints the timings
-    struct Shape {
-        int grid;
-        uint32_t tile;
-        int nv;
-    };
-    static std::map<std::vector<const void *>, Shape> shape_cache;
-    static std::mutex shape_mu;   // held while the shape is looked up or tuned
-    std::vector<const void *> gkey;
-    for (int i = 0; i < n; ++i) {
-        gkey.push_back(hams[i]);
-        gkey.push_back(reinterpret_cast<const void *>((uintptr_t)hams[i]->serial));
-    }
-    gkey.push_back(reinterpret_cast<const void *>((intptr_t)(nvec * 8 + dtype)));
-    Shape best_shape{apply_grid_for(2), 4 * 1024, 8};
+    // launch shape of the batched apply (tuned once per set of blocks)
+    BatchShape best_shape;
     {
-        std::unique_lock<std::mutex> shape_lock(shape_mu);
-        auto cached = shape_cache.find(gkey);
-        if (cached != shape_cache.end()) {
-            best_shape = cached->second;
-        } else {
-            hipEvent_t e0, e1;
-            XDG_TRY_HIP(hipEventCreate(&e0));
-            XDG_TRY_HIP(hipEventCreate(&e1));
-            const char *log = getenv("XDG_TUNE_LOG");
-            float best = 1e30f;
-            auto time_shape = [&](const Shape &sh) -> int {
-                BatchPlan P;
-                XDG_RETURN_IF(prepare(0, &P, sh.tile));
-                XDG_RETURN_IF(batch_launch(P, sh.grid, sh.nv, st));
-                XDG_TRY_HIP(hipEventRecord(e0, st));
-                XDG_RETURN_IF(batch_launch(P, sh.grid, sh.nv, st));
-                XDG_TRY_HIP(hipEventRecord(e1, st));
-                XDG_TRY_HIP(hipEventSynchronize(e1));
-                float ms = 0;
-                XDG_TRY_HIP(hipEventElapsedTime(&ms, e0, e1));
-                if (log && atoi(log) > 0)
-                    fprintf(stderr, "[xdg tune] batched %d blocks nvec %lld: grid %d tile %u "
-                            "nv %d: %.3f ms\n", n, (long long)nvec, sh.grid, sh.tile, sh.nv, ms);
-                if (ms < best) {
-                    best = ms;
-                    best_shape = sh;
-                }
-                return XDG_OK;
-            };
-            int rc = XDG_OK;
-            for (int mult : {1, 2, 4})
-                if (rc == XDG_OK) rc = time_shape({apply_grid_for(mult), 4 * 1024, 8});
-            const Shape g = best_shape;
-            for (uint32_t tile : {1024u, 2048u, 8192u, 16384u})
-                if (rc == XDG_OK) rc = time_shape({g.grid, tile, g.nv});
-            const Shape t = best_shape;
-            for (int nv : {4, 2})
-                if (rc == XDG_OK && nv < cols) rc = time_shape({t.grid, t.tile, nv});
-            (void)hipEventDestroy(e0);
-            (void)hipEventDestroy(e1);
-            XDG_RETURN_IF(rc);
-            shape_cache[gkey] = best_shape;
+        std::vector<const void *> xs(n);
+        std::vector<void *> ys(n);
+        for (int i = 0; i < n; ++i) {
+            xs[i] = vecp(i, 0);
+            ys[i] = vecp(i, 3);
         }
+        XDG_RETURN_IF(batch_shape_tuned(n, hv.data(), xs.data(), ys.data(), nvec, dtype, st,
+                                        &best_shape));
     }
     BatchPlan plans[3];
     for (int p = 0; p < 3; ++p) XDG_RETURN_IF(prepare(p, &plans[p], best_shape.tile));

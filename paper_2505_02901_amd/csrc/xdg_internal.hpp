@@ -258,6 +258,19 @@ int batch_launch_raw(const BatchMeta &M, const SectorDesc *d_descs, const uint32
                      uint32_t *d_queue, int grid, int nv_cap, hipStream_t st);
 int apply_batched_noalloc(int n, xdg_ham_s *const *hams, const void *const *xs,
                           void *const *ys, int64_t nvec, int dtype, hipStream_t st);
+// Launch shape of a batched apply: persistent grid, rows per work item,
+// vectors per pass.
+struct BatchShape {
+    int grid = 0;
+    uint32_t tile = 4096;
+    int nv = 8;
+};
+// The shape for this set of blocks (nvec, dtype): tuned on the first call by
+// timing launches on xs -> ys (which it overwrites) and cached; locked.
+int batch_shape_tuned(int n, xdg_ham_s *const *hams, const void *const *xs, void *const *ys,
+                      int64_t nvec, int dtype, hipStream_t st, BatchShape *out);
+// The cached shape, if any (no tuning, no allocation); false otherwise.
+bool batch_shape_cached(int n, xdg_ham_s *const *hams, int64_t nvec, int dtype, BatchShape *out);
 int lanczos_single(xdg_ham_s *h, const void *v0, int k, double tol, int max_iter, uint64_t seed,
                    int prec, double *evals, int *n_iter, double *alpha, double *beta,
                    hipStream_t st, double *t_total, double *t_apply);
