@@ -229,7 +229,10 @@ typedef struct xdg_launch_cfg {
                           two workgroups' LDS tables fit a compute unit); 0: 4 waves; -1: auto */
     int compact;       /* sublattice / table searches: 1 = wave-compacted term loop (terms of
                           64 rows packed into full passes), 0 or -1 = row loop */
-    int reserved[4];   /* must be zero */
+    int sub_form;      /* sublattice coding: 0 = automatic (the packed form wherever it
+                          applies: four blocks of at most 10 sites, tables in LDS), 2 = the
+                          block-by-block form (comparisons); both give bitwise the same y */
+    int reserved[3];   /* must be zero */
 } xdg_launch_cfg;
 
 /* xdg_apply in a given launch shape (tuning and tests: every shape computes

@@ -3,8 +3,10 @@
 //
 // Pull form: one lane owns one output row r (a basis state).  For every bond
 // with unequal spins it forms t = r with both spins exchanged, finds the
-// representative s of t, the first group element u with u.t = s and the
-// number of such elements (= |Stab(s)|), looks up the index of s, and adds
+// representative s of t, a group element u with u.t = s (the first one the
+// search meets: when s is in the block, chi is 1 on Stab(s), so every such u
+// has the same chi(u)) and the number of such elements (= |Stab(s)|), looks
+// up the index of s, and adds
 //      (Jxy/2) chi(u) sqrt(|Stab s| / |Stab r|) x[idx(s)]
 // to the row, after the diagonal Sum_b Jz_b (+-1/4) x[r].  The row is
 // written once: no atomics, bitwise reproducible for any launch shape.
@@ -70,6 +72,7 @@ struct SectorDesc {
     const uint16_t *tperm;
     int n_s, m, pb, n_perm;
     uint32_t n_cand;
+    int subf;                    // sublattice tables in the packed form (staged kernels)
     const void *bonds;           // BondD / BondF [n_bonds]
     const void *chi;             // double2 / float2 [n_sym]
     const void *sqrtt;           // T [2 (n_sym + 1)]: sqrt(c), then 1/sqrt(c)
@@ -118,6 +121,8 @@ __host__ __device__ inline size_t stage_bytes(const SectorDesc &d, int kind, int
         n += a16(rank_table_bytes(d));
         if (kind == K_AFF) n += a16(sizeof(AffineElem) * d.n_sym) + a16(4 * (size_t)d.n_sites);
         if (kind == K_SUB && stage_sub) n += sub_table_bytes(d);
+        // packed form: alignment of the permutation tables, per-bond flip masks
+        if (kind == K_SUB && stage_sub && d.subf) n += 128 + a16(8 * (size_t)d.n_bonds);
     }
     return n;
 }
@@ -132,6 +137,9 @@ struct Staged {
     const int16_t *ring_gidx;
     const void *rtab;
     SubCtx sub;
+    bool subf;             // packed sublattice search (sub.sp holds the packed entries)
+    uint32_t amask;        // ~(4E - 1)
+    const uint2 *bmask;    // [n_bonds] packed-word bits flipped by the bond
 };
 
 template <class E>
@@ -152,6 +160,7 @@ __device__ inline void stage(const SectorDesc &d, unsigned char *smem, Staged<T>
     size_t off = 0;
     S.bonds = stage_copy(smem, off, reinterpret_cast<const B *>(d.bonds), d.n_bonds);
     S.sub = SubCtx{d.mintop, d.cand_off, d.cand_list, d.sp, d.tperm, d.n_s, d.m, d.pb};
+    S.subf = false;
     if constexpr (KIND != K_U1) {
         S.chi = stage_copy(smem, off, reinterpret_cast<const T2 *>(d.chi), d.n_sym);
         const T *ls = stage_copy(smem, off, reinterpret_cast<const T *>(d.sqrtt), 2 * (d.n_sym + 1));
@@ -170,11 +179,42 @@ __device__ inline void stage(const SectorDesc &d, unsigned char *smem, Staged<T>
         if constexpr (KIND == K_SUB) {
             if constexpr (STAGE) {
                 const size_t NV = (size_t)d.n_s << d.m;
+                const size_t ntp = (size_t)d.n_perm * 2 * ((size_t)1 << d.pb);
                 S.sub.mintop = stage_copy(smem, off, d.mintop, NV);
                 S.sub.cand_off = stage_copy(smem, off, d.cand_off, NV + 1);
                 S.sub.cand_list = stage_copy(smem, off, d.cand_list, d.n_cand);
-                S.sub.sp = stage_copy(smem, off, d.sp, (size_t)d.n_sym * d.n_s);
-                S.sub.tperm = stage_copy(smem, off, d.tperm, (size_t)d.n_perm * 2 * ((size_t)1 << d.pb));
+                if (d.subf) {
+                    // permutation tables at a 128-byte aligned LDS address,
+                    // then the packed (element, block) entries pointing there
+                    const uint32_t base =
+                        (uint32_t)(uintptr_t)(__attribute__((address_space(3))) unsigned char *)smem;
+                    off += (128u - ((base + (uint32_t)off) & 127u)) & 127u;
+                    const uint32_t tpa = base + (uint32_t)off;
+                    S.sub.tperm = stage_copy(smem, off, d.tperm, ntp);
+                    const size_t nsp = (size_t)d.n_sym * d.n_s;
+                    uint32_t *sq = reinterpret_cast<uint32_t *>(smem + off);
+                    off = a16(off + 4 * nsp);
+                    for (size_t e = threadIdx.x; e < nsp; e += blockDim.x) {
+                        const uint32_t w = d.sp[e];
+                        sq[e] = (tpa + 2u * (w >> 8)) | (7u * ((w & 0xFFu) / (uint32_t)d.m));
+                    }
+                    S.sub.sp = sq;
+                    uint2 *bm = reinterpret_cast<uint2 *>(smem + off);
+                    off = a16(off + 8 * (size_t)d.n_bonds);
+                    const B *gb = reinterpret_cast<const B *>(d.bonds);
+                    for (int b = threadIdx.x; b < d.n_bonds; b += blockDim.x) {
+                        uint32_t lo = 0, hi = 0;
+                        sub_pack_site((int)gb[b].i, d.m, d.pb, lo, hi);
+                        sub_pack_site((int)gb[b].j, d.m, d.pb, lo, hi);
+                        bm[b] = make_uint2(lo, hi);
+                    }
+                    S.bmask = bm;
+                    S.amask = ~((4u << d.pb) - 1u);
+                    S.subf = true;
+                } else {
+                    S.sub.sp = stage_copy(smem, off, d.sp, (size_t)d.n_sym * d.n_s);
+                    S.sub.tperm = stage_copy(smem, off, d.tperm, ntp);
+                }
             }
         }
     }
@@ -185,10 +225,13 @@ template <class W> struct IndexT { using type = int64_t; };
 template <> struct IndexT<uint32_t> { using type = int32_t; };
 
 // Locate the representative of t and its index; returns -1 when the orbit
-// is not in the block.  On success writes u and |Stab(s)|.
-template <class W, int KIND, class T>
+// is not in the block.  On success writes u and |Stab(s)|.  PK: lo2 and hi2
+// are t's packed words for the packed sublattice search (else computed here
+// when that search is on).
+template <class W, int KIND, class T, bool PK = false>
 __device__ __forceinline__ typename IndexT<W>::type locate(const SectorDesc &d, const Staged<T> &S,
-                                                           W t, int &u, int &cnt) {
+                                                           W t, int &u, int &cnt,
+                                                           uint32_t lo2 = 0, uint32_t hi2 = 0) {
     using I = typename IndexT<W>::type;
     if constexpr (KIND == K_U1) {
         const uint64_t lo = (uint64_t)t & ((1ull << d.nlo) - 1);
@@ -205,7 +248,10 @@ __device__ __forceinline__ typename IndexT<W>::type locate(const SectorDesc &d, 
             else
                 aff_search<W>(S.aff, d.n_sym, d.n_sites, t, rep, u, cnt);
         } else if constexpr (KIND == K_SUB) {
-            if (d.n_s == 4)
+            if (S.subf) {
+                if constexpr (!PK) sub_pack<W>(t, d.m, d.pb, lo2, hi2);
+                sub_search_packed<W>(S.sub, S.amask, t, lo2, hi2, rep, u, cnt);
+            } else if (d.n_s == 4)
                 sub_search<W, 4>(S.sub, t, rep, u, cnt);
             else
                 sub_search<W, 0>(S.sub, t, rep, u, cnt);
@@ -213,16 +259,18 @@ __device__ __forceinline__ typename IndexT<W>::type locate(const SectorDesc &d, 
             tab_search<W>(d.bytetab, d.n_bchunks, d.n_sym, t, rep, u, cnt);
         }
         if (d.rwords) {
-            const uint64_t r = colex_rank<W>(S.rtab, d.rl, rep);
             if constexpr (sizeof(W) == 4) {
+                const uint64_t r = colex_rank<W>(S.rtab, d.rl, rep);
                 return rank_find32(d.rwords, (uint32_t)d.n_rwords, (uint32_t)r);
             } else {
                 // 4-byte entries: every basis state's rank is below 2^32 - 1
-                if (d.rl.e32)
-                    return r >= 0xFFFFFFFFull
-                               ? -1
-                               : rank_find_r32(d.rwords, (uint32_t)d.n_rwords, (uint32_t)r);
-                return rank_find(d.rwords, d.n_rwords, r);
+                if (d.rl.e32) {
+                    const uint32_t r =
+                        colex_rank_sat<W>(static_cast<const uint32_t *>(S.rtab), d.rl, rep);
+                    return r == 0xFFFFFFFFu ? -1
+                                            : rank_find_r32(d.rwords, (uint32_t)d.n_rwords, r);
+                }
+                return rank_find(d.rwords, d.n_rwords, colex_rank<W>(S.rtab, d.rl, rep));
             }
         }
         return (I)hash_find<W>(d.hash, d.n_lines, (W)d.empty, rep);
@@ -249,10 +297,14 @@ __device__ __forceinline__ void process_row(const SectorDesc &d, const Staged<A>
     for (int v = 0; v < NV * C; ++v) acc[v] = 0;
     A rn = A(1);
     if constexpr (KIND != K_U1) rn = S.rsq[gld(d.stab + row)];
-    auto term = [&](const B &bd) {
+    // packed sublattice words of the row; a term's words differ by its bond's mask
+    uint32_t plo = 0, phi = 0;
+    if constexpr (KIND == K_SUB)
+        if (S.subf) sub_pack<W>(s, d.m, d.pb, plo, phi);
+    auto term = [&](const B &bd, uint2 bm) {
         const W t = s ^ ((W(1) << bd.i) | (W(1) << bd.j));
         int u, cnt;
-        const auto idx = locate<W, KIND, A>(d, S, t, u, cnt);
+        const auto idx = locate<W, KIND, A, true>(d, S, t, u, cnt, plo ^ bm.x, phi ^ bm.y);
         if (idx < 0) return;
         A ar = bd.h, ai = 0;
         if constexpr (KIND != K_U1) {
@@ -300,7 +352,7 @@ __device__ __forceinline__ void process_row(const SectorDesc &d, const Staged<A>
                 act &= act - 1;
                 const B bd = S.bonds[b];
                 junq += bd.jz;
-                term(bd);
+                term(bd, make_uint2(0u, 0u));
             }
         }
     } else {
@@ -311,7 +363,10 @@ __device__ __forceinline__ void process_row(const SectorDesc &d, const Staged<A>
             const B bd = S.bonds[b];
             if (((s >> bd.i) & 1) == ((s >> bd.j) & 1)) continue;
             junq += bd.jz;
-            term(bd);
+            uint2 bm = make_uint2(0u, 0u);
+            if constexpr (KIND == K_SUB)
+                if (S.subf) bm = S.bmask[b];
+            term(bd, bm);
         }
     }
     const size_t base = ((size_t)row * nvec + v0) * C;

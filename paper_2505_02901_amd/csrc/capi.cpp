@@ -349,9 +349,9 @@ int xdg_apply_with_config(xdg_ham h, const void *x, void *y, int64_t nvec, int d
         bool res_ok = true;
         for (int r : cfg->reserved) res_ok &= r == 0;
         if (cfg->grid < 0 || !nv_ok || cfg->occ < -1 || cfg->occ > 1 || cfg->compact < -1 ||
-            cfg->compact > 1 || !res_ok) {
-            set_error("launch shape out of range (grid %d, nv %d, occ %d, compact %d)", cfg->grid,
-                      cfg->nv, cfg->occ, cfg->compact);
+            cfg->compact > 1 || (cfg->sub_form != 0 && cfg->sub_form != 2) || !res_ok) {
+            set_error("launch shape out of range (grid %d, nv %d, occ %d, compact %d, sub_form %d)",
+                      cfg->grid, cfg->nv, cfg->occ, cfg->compact, cfg->sub_form);
             return XDG_EINVAL;
         }
         LaunchCfg c;
@@ -360,6 +360,7 @@ int xdg_apply_with_config(xdg_ham h, const void *x, void *y, int64_t nvec, int d
         c.nv = cfg->nv > 0 ? cfg->nv : 8;
         c.occ = cfg->occ;
         c.compact = cfg->compact;
+        c.sub_form = cfg->sub_form;
         return apply_launch(h, x, y, nvec, dtype, (hipStream_t)stream, &c);
     });
 }

@@ -145,6 +145,31 @@ __host__ __device__ __forceinline__ uint64_t colex_rank(const void *T, const Ran
     }
 }
 
+// The colex rank of a wide state from 4-byte entries (layout with e32),
+// summed with unsigned saturation: a rank of 2^32 - 1 or more (never the
+// rank of a basis state) reads as 0xFFFFFFFF, every smaller rank exactly.
+// Chunks inside the low 32 bits come from that word with 32-bit shifts.
+template <class W>
+__host__ __device__ __forceinline__ uint32_t colex_rank_sat(const uint32_t *T32,
+                                                            const RankLayout &L, W s) {
+    const int cb = L.cb, nc = L.nc;
+    const int nlo = nc < 32 / cb ? nc : 32 / cb;
+    const uint32_t lo = (uint32_t)s, mask = (1u << cb) - 1u;
+    uint32_t below = 0, r = 0;
+    int k = 0;
+    for (; k < nlo; ++k) {
+        const uint32_t v = (lo >> (k * cb)) & mask;
+        r = __builtin_elementwise_add_sat(r, T32[(((uint32_t)L.rbase[k] + below) << cb) | v]);
+        below += (uint32_t)__builtin_popcount(v);
+    }
+    for (; k < nc; ++k) {
+        const uint32_t v = (uint32_t)((uint64_t)s >> (k * cb)) & mask;
+        r = __builtin_elementwise_add_sat(r, T32[(((uint32_t)L.rbase[k] + below) << cb) | v]);
+        below += (uint32_t)__builtin_popcount(v);
+    }
+    return r;
+}
+
 // Position of the state of colex rank r, or -1: words[r / 32] holds the
 // number of basis states of smaller rank (valid in words holding a state)
 // and one bit per rank.
@@ -492,7 +517,6 @@ __device__ __forceinline__ void sub_search(const SubCtx &C, W t, W &best, int &u
                 cnt = 1;
             } else if (img == best) {
                 ++cnt;
-                u = g < u ? g : u;
             }
         }
     }
@@ -534,6 +558,105 @@ __device__ __forceinline__ bool sub_is_rep(const SubCtx &C, W s, const double2 *
         }
     }
     return true;
+}
+
+// ------------------------------------- sublattice coding, packed form --
+// For four blocks of m <= 10 bits whose half-chunk tables (E = 2^pb entries,
+// 3 <= pb <= 5) sit in LDS at a 4E-aligned address.  A state enters as two
+// words of 7-bit fields: field k of lo2 is 2 (chunk_k mod E) and field k of
+// hi2 is 2 (E + chunk_k / E), the byte offsets of block k's two half-table
+// entries within one permutation's 4E bytes of tables.  Each (element,
+// block) entry w holds the LDS address of the permutation's tables (a
+// multiple of 4E) or'ed with 7 times the source block, so one bit-field
+// extract of the packed word at w's low five bits and one and-or with w give
+// a table address.  Every candidate's top block is the minimal top, so the
+// three lower image blocks (at most 30 bits) decide as one 32-bit word, and
+// the lists of all blocks reaching the minimal top run as one loop.
+typedef __attribute__((address_space(3))) const uint16_t lds_u16;
+
+__host__ __device__ constexpr bool sub_packed_ok(int n_s, int m, int pb) {
+    return n_s == 4 && m <= 10 && pb >= 3 && pb <= 5 && m - pb <= pb;
+}
+
+// the packed words of state t
+template <class W>
+__device__ __forceinline__ void sub_pack(W t, int m, int pb, uint32_t &lo2, uint32_t &hi2) {
+    const uint32_t E = 1u << pb, vmask = (1u << m) - 1;
+    lo2 = 0;
+    hi2 = 0;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        const uint32_t c = chunk_of<W>(t, k, m, vmask);
+        lo2 |= ((c & (E - 1)) << 1) << (7 * k);
+        hi2 |= ((E + (c >> pb)) << 1) << (7 * k);
+    }
+}
+
+// the bits of the packed words that change when site i flips
+__device__ __forceinline__ void sub_pack_site(int i, int m, int pb, uint32_t &lo2, uint32_t &hi2) {
+    const int q = i / m, p = i - q * m;
+    if (p < pb)
+        lo2 |= 1u << (7 * q + 1 + p);
+    else
+        hi2 |= 1u << (7 * q + 1 + p - pb);
+}
+
+// C.sp holds the packed (element, block) entries; amask = ~(4E - 1).
+template <class W>
+__device__ __forceinline__ void sub_search_packed(const SubCtx &C, uint32_t amask, W t,
+                                                  uint32_t lo2, uint32_t hi2, W &best, int &u,
+                                                  int &cnt) {
+    const int m = C.m;
+    const uint32_t V = 1u << m, vmask = V - 1;
+    uint32_t e[4], mv[4];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        e[k] = k * V + chunk_of<W>(t, k, m, vmask);
+        mv[k] = C.mintop[e[k]];
+    }
+    const uint32_t mt = min(min(mv[0], mv[1]), min(mv[2], mv[3]));
+    typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
+    uint32_t bl = 0xFFFFFFFFu, bu = 0x7fffffffu, bc = 0;
+    auto candidate = [&](uint32_t g) {
+        const u32x4 w = *reinterpret_cast<const u32x4 *>(C.sp + 4 * g);
+        uint32_t v[3];
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+            // the fields are below 4E: bitop3 table 0xE4 takes wa's bits
+            // under amask and the field's below it
+            const uint32_t wa = w[a];
+            const uint32_t la =
+                __builtin_amdgcn_bitop3_b32(wa, __builtin_amdgcn_ubfe(lo2, wa, 7), amask, 0xE4);
+            const uint32_t ha =
+                __builtin_amdgcn_bitop3_b32(wa, __builtin_amdgcn_ubfe(hi2, wa, 7), amask, 0xE4);
+            // the two halves set disjoint bits: an add keeps the sum in 32 bits
+            v[a] = (uint32_t)*(lds_u16 *)la + (uint32_t)*(lds_u16 *)ha;
+        }
+        const uint32_t img = (((v[2] << m) | v[1]) << m) | v[0];
+        const bool lt = img < bl, eq = img == bl;
+        bu = lt ? g : bu;
+        bc = lt ? 1u : bc + (eq ? 1u : 0u);
+        bl = lt ? img : bl;
+    };
+    // the list of the lowest block reaching mt (most terms have one such
+    // block): one paired read of its offsets, then one loop
+    const bool h0 = mv[0] == mt, h1 = mv[1] == mt, h2 = mv[2] == mt;
+    const uint32_t ef = h0 ? e[0] : h1 ? e[1] : h2 ? e[2] : e[3];
+    const uint32_t q0 = C.cand_off[ef], n = C.cand_off[ef + 1] - q0;
+    const uint16_t *cl = C.cand_list + q0;
+    for (uint32_t i = 0; i < n; ++i) candidate(cl[i]);
+    // the lists of further blocks reaching mt
+    const int kf = h0 ? 0 : h1 ? 1 : h2 ? 2 : 3;
+#pragma unroll
+    for (int k = 1; k < 4; ++k) {
+        if (k > kf && mv[k] == mt) {
+            const uint32_t r1 = C.cand_off[e[k] + 1];
+            for (uint32_t q = C.cand_off[e[k]]; q < r1; ++q) candidate(C.cand_list[q]);
+        }
+    }
+    best = ((W)mt << (3 * m)) | (W)bl;
+    u = (int)bu;
+    cnt = (int)bc;
 }
 
 // ---------------------------------------------------- search: byte tables --

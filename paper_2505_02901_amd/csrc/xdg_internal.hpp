@@ -190,6 +190,7 @@ struct LaunchCfg {
     int nv = 1;            // vectors per pass (<= nvec)
     int occ = -1;          // 64-VGPR copy at 8 waves per SIMD: 1 / 0 / -1 = when the LDS allows
     int compact = -1;      // table searches: 1 = wave-compacted term loop, 0 / -1 = row loop
+    int sub_form = 0;      // sublattice coding: 0 = packed form where it applies, 2 = block form
 };
 }  // namespace xdg
 

@@ -35,7 +35,7 @@ class XdgError(RuntimeError):
 
 class LaunchCfg(C.Structure):
     _fields_ = [("grid", C.c_int), ("nv", C.c_int), ("occ", C.c_int), ("compact", C.c_int),
-                ("reserved", C.c_int * 4)]
+                ("sub_form", C.c_int), ("reserved", C.c_int * 3)]
 
 
 class BasisOpts(C.Structure):
@@ -369,14 +369,15 @@ def xdg_apply(h, x, y, nvec: Optional[int] = None, dtype: Optional[int] = None, 
 
 
 def xdg_apply_with_config(h, x, y, grid: int = 0, nv: int = 0, occ: int = -1, compact: int = -1,
-                          nvec: Optional[int] = None, dtype: Optional[int] = None, stream=None):
+                          nvec: Optional[int] = None, dtype: Optional[int] = None, stream=None,
+                          sub_form: int = 0):
     """xdg_apply in an explicit launch shape (every shape gives the same y)."""
     if nvec is None:
         nvec = 1 if x.dim() == 1 else int(x.shape[1])
     if dtype is None:
         dtype = _dtype_code(x)
     _check_apply_vectors(h, x, y, nvec, dtype)
-    cfg = LaunchCfg(grid, nv, occ, compact)
+    cfg = LaunchCfg(grid, nv, occ, compact, sub_form)
     _check(lib().xdg_apply_with_config(h, _ptr(x), _ptr(y), nvec, dtype, C.byref(cfg),
                                        _stream(stream)))
 

@@ -57,11 +57,16 @@ static int check_rank_layout(int N, int n_up, uint64_t max_rank, std::mt19937_64
         if (it == 0) s = low;
         if (it == 1) s = low << (N - n_up);
         const uint64_t want = colex_plain(s), got = colex_rank<W>(T, L, (W)s);
-        // saturating 4-byte entries: exact below 2^32 - 1, at least that above
+        // saturating 4-byte entries: exact below 2^32 - 1, at least that above;
+        // the 32-bit saturating sum: exact below, 0xFFFFFFFF above
         if (wide && L.e32 && want >= 0xFFFFFFFFull) {
             if (got < 0xFFFFFFFFull) ++bad;
         } else if (got != want) {
             ++bad;
+        }
+        if (wide && L.e32) {
+            const uint32_t sat = colex_rank_sat<W>(T32.data(), L, (W)s);
+            if (sat != (want >= 0xFFFFFFFFull ? 0xFFFFFFFFu : (uint32_t)want)) ++bad;
         }
     }
     return bad;

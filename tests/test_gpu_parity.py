@@ -347,13 +347,17 @@ SHAPE_CASES = [
     (W.torus_model((4, 2), (-2, 4), 1.0, 0.0, "A1", reflections=False, n_up=8),
      4),                                                               # forced byte tables
     (W.chain_model(24, l=5), 0),                                       # ring search
+    (W.torus_model((4, 2), (-2, 4), 1.0, 0.0, "A1", reflections=False, n_up=8),
+     0),                                                               # 4 blocks of 5 sites
+    (W.torus_model((6, 0), (0, 4), 1.0, 0.3, "B1", rotations=False, name="rect24b"), 0),
 ]
 
 
 @pytest.mark.parametrize("case", range(len(SHAPE_CASES)))
 def test_every_launch_shape_gives_the_same_y(X, case):
     """The autotuner's candidates (grid, vectors per pass, occupancy copy,
-    row or compacted term loop) compute bitwise the same y."""
+    row or compacted term loop) and both forms of the sublattice search
+    compute bitwise the same y."""
     m, search = SHAPE_CASES[case]
     b = X.Basis.from_model(m, search=search)
     H = X.Hamiltonian.from_model(b, m)
@@ -367,17 +371,21 @@ def test_every_launch_shape_gives_the_same_y(X, case):
             for nv in (1, 2, 8):
                 for occ in (-1, 0, 1):
                     for compact in (0, 1):
-                        y = torch.full_like(x, float("nan"))
-                        X.xdg_apply_with_config(H.handle, x, y, grid=grid, nv=nv, occ=occ,
-                                                compact=compact)
-                        torch.cuda.synchronize()
-                        assert torch.equal(y, ref), (m.name, dt, grid, nv, occ, compact)
+                        for form in (0, 2):
+                            y = torch.full_like(x, float("nan"))
+                            X.xdg_apply_with_config(H.handle, x, y, grid=grid, nv=nv, occ=occ,
+                                                    compact=compact, sub_form=form)
+                            torch.cuda.synchronize()
+                            assert torch.equal(y, ref), (m.name, dt, grid, nv, occ, compact,
+                                                         form)
         code = {torch.float64: X.XDG_F64, torch.float32: X.XDG_F32,
                 torch.complex128: X.XDG_C128, torch.complex64: X.XDG_C64}[dt]
         cfg = X.xdg_apply_tuned_config(H.handle, code, 2)
         assert cfg["nv"] in (1, 2, 4, 8) and cfg["grid"] >= 1
     with pytest.raises(X.XdgError):
         X.xdg_apply_with_config(H.handle, x, torch.empty_like(x), nv=3)
+    with pytest.raises(X.XdgError):
+        X.xdg_apply_with_config(H.handle, x, torch.empty_like(x), sub_form=1)
     with pytest.raises(X.XdgError):                  # not tuned for this (dtype, nvec)
         X.xdg_apply_tuned_config(H.handle, code, 7)
 
