@@ -97,7 +97,8 @@ SectorDesc make_desc(const xdg_ham_s *h, bool single, const void *x, void *y) {
     d.pb = b->plan.sub.pb;
     d.n_perm = b->plan.sub.n_perm;
     d.n_cand = (uint32_t)b->plan.sub.cand_list.size();
-    d.subf = b->plan.kind == K_SUB && sub_packed_ok(d.n_s, d.m, d.pb);
+    d.subf = b->plan.kind == K_SUB && sub_packed_ok(d.n_s, d.m, d.pb) && h->bonds_x.p;
+    d.bx = d.subf ? h->bonds_x.as<BondX>() : nullptr;
     d.bonds = single ? h->bonds_f.p : h->bonds_d.p;
     d.chi = single ? b->chi_f.p : b->chi_d.p;
     d.sqrtt = single ? b->sqrt_f.p : b->sqrt_d.p;
@@ -189,7 +190,10 @@ int apply_launch(xdg_ham_s *h, const void *x, void *y, int64_t nvec, int dtype, 
     const unsigned grid = (unsigned)std::max<int64_t>(1, std::min<int64_t>(need, gmax));
     ApplyArgs A{};
     A.one = make_desc(h, f.tsingle, x, y);
-    if (c.sub_form == 2) A.one.subf = 0;
+    if (c.sub_form == 2) {
+        A.one.subf = 0;
+        A.one.bx = nullptr;
+    }
     A.nvec = f.cols;
     size_t lds = f.tsingle ? stage_bytes<float>(A.one, b->plan.kind, 1)
                            : stage_bytes<double>(A.one, b->plan.kind, 1);

@@ -73,6 +73,7 @@ struct SectorDesc {
     int n_s, m, pb, n_perm;
     uint32_t n_cand;
     int subf;                    // sublattice tables in the packed form (staged kernels)
+    const BondX *bx;             // per-bond data of the packed form [n_bonds]
     const void *bonds;           // BondD / BondF [n_bonds]
     const void *chi;             // double2 / float2 [n_sym]
     const void *sqrtt;           // T [2 (n_sym + 1)]: sqrt(c), then 1/sqrt(c)
@@ -121,8 +122,8 @@ __host__ __device__ inline size_t stage_bytes(const SectorDesc &d, int kind, int
         n += a16(rank_table_bytes(d));
         if (kind == K_AFF) n += a16(sizeof(AffineElem) * d.n_sym) + a16(4 * (size_t)d.n_sites);
         if (kind == K_SUB && stage_sub) n += sub_table_bytes(d);
-        // packed form: alignment of the permutation tables, per-bond flip masks
-        if (kind == K_SUB && stage_sub && d.subf) n += 128 + a16(8 * (size_t)d.n_bonds);
+        // packed form: alignment of the permutation tables
+        if (kind == K_SUB && stage_sub && d.subf) n += 128;
     }
     return n;
 }
@@ -139,7 +140,6 @@ struct Staged {
     SubCtx sub;
     bool subf;             // packed sublattice search (sub.sp holds the packed entries)
     uint32_t amask;        // ~(4E - 1)
-    const uint2 *bmask;    // [n_bonds] packed-word bits flipped by the bond
 };
 
 template <class E>
@@ -199,16 +199,6 @@ __device__ inline void stage(const SectorDesc &d, unsigned char *smem, Staged<T>
                         sq[e] = (tpa + 2u * (w >> 8)) | (7u * ((w & 0xFFu) / (uint32_t)d.m));
                     }
                     S.sub.sp = sq;
-                    uint2 *bm = reinterpret_cast<uint2 *>(smem + off);
-                    off = a16(off + 8 * (size_t)d.n_bonds);
-                    const B *gb = reinterpret_cast<const B *>(d.bonds);
-                    for (int b = threadIdx.x; b < d.n_bonds; b += blockDim.x) {
-                        uint32_t lo = 0, hi = 0;
-                        sub_pack_site((int)gb[b].i, d.m, d.pb, lo, hi);
-                        sub_pack_site((int)gb[b].j, d.m, d.pb, lo, hi);
-                        bm[b] = make_uint2(lo, hi);
-                    }
-                    S.bmask = bm;
                     S.amask = ~((4u << d.pb) - 1u);
                     S.subf = true;
                 } else {
@@ -225,13 +215,13 @@ template <class W> struct IndexT { using type = int64_t; };
 template <> struct IndexT<uint32_t> { using type = int32_t; };
 
 // Locate the representative of t and its index; returns -1 when the orbit
-// is not in the block.  On success writes u and |Stab(s)|.  PK: lo2 and hi2
-// are t's packed words for the packed sublattice search (else computed here
-// when that search is on).
-template <class W, int KIND, class T, bool PK = false>
+// is not in the block.  On success writes u and |Stab(s)|.  key: t's key for
+// the packed sublattice search (computed here from t when null and that
+// search is on).
+template <class W, int KIND, class T>
 __device__ __forceinline__ typename IndexT<W>::type locate(const SectorDesc &d, const Staged<T> &S,
                                                            W t, int &u, int &cnt,
-                                                           uint32_t lo2 = 0, uint32_t hi2 = 0) {
+                                                           const SubKey *key = nullptr) {
     using I = typename IndexT<W>::type;
     if constexpr (KIND == K_U1) {
         const uint64_t lo = (uint64_t)t & ((1ull << d.nlo) - 1);
@@ -249,8 +239,10 @@ __device__ __forceinline__ typename IndexT<W>::type locate(const SectorDesc &d, 
                 aff_search<W>(S.aff, d.n_sym, d.n_sites, t, rep, u, cnt);
         } else if constexpr (KIND == K_SUB) {
             if (S.subf) {
-                if constexpr (!PK) sub_pack<W>(t, d.m, d.pb, lo2, hi2);
-                sub_search_packed<W>(S.sub, S.amask, t, lo2, hi2, rep, u, cnt);
+                if (key)
+                    sub_search_packed<W>(S.sub, S.amask, *key, rep, u, cnt);
+                else
+                    sub_search_packed<W>(S.sub, S.amask, sub_key<W>(t, d.m, d.pb), rep, u, cnt);
             } else if (d.n_s == 4)
                 sub_search<W, 4>(S.sub, t, rep, u, cnt);
             else
@@ -297,14 +289,10 @@ __device__ __forceinline__ void process_row(const SectorDesc &d, const Staged<A>
     for (int v = 0; v < NV * C; ++v) acc[v] = 0;
     A rn = A(1);
     if constexpr (KIND != K_U1) rn = S.rsq[gld(d.stab + row)];
-    // packed sublattice words of the row; a term's words differ by its bond's mask
-    uint32_t plo = 0, phi = 0;
-    if constexpr (KIND == K_SUB)
-        if (S.subf) sub_pack<W>(s, d.m, d.pb, plo, phi);
-    auto term = [&](const B &bd, uint2 bm) {
-        const W t = s ^ ((W(1) << bd.i) | (W(1) << bd.j));
+    // key: the packed sublattice search's key of the term's state, if given
+    auto term = [&](const B &bd, W t, const SubKey *key) {
         int u, cnt;
-        const auto idx = locate<W, KIND, A, true>(d, S, t, u, cnt, plo ^ bm.x, phi ^ bm.y);
+        const auto idx = locate<W, KIND, A>(d, S, t, u, cnt, key);
         if (idx < 0) return;
         A ar = bd.h, ai = 0;
         if constexpr (KIND != K_U1) {
@@ -352,21 +340,38 @@ __device__ __forceinline__ void process_row(const SectorDesc &d, const Staged<A>
                 act &= act - 1;
                 const B bd = S.bonds[b];
                 junq += bd.jz;
-                term(bd, make_uint2(0u, 0u));
+                term(bd, s ^ ((W(1) << bd.i) | (W(1) << bd.j)), nullptr);
             }
         }
     } else {
         // Table searches: all lanes take the same bond at the same time, so
         // that neighbouring rows walk similar table entries and look up
         // neighbouring index words.
-        for (int b = 0; b < nb; ++b) {
-            const B bd = S.bonds[b];
-            if (((s >> bd.i) & 1) == ((s >> bd.j) & 1)) continue;
-            junq += bd.jz;
-            uint2 bm = make_uint2(0u, 0u);
-            if constexpr (KIND == K_SUB)
-                if (S.subf) bm = S.bmask[b];
-            term(bd, bm);
+        bool done = false;
+        if constexpr (KIND == K_SUB) {
+            if (S.subf && d.bx) {
+                // packed form: the bond comes with scalar loads, the term's key
+                // is the row's key with the bond's bits flipped
+                const SubKey kr = sub_key<W>(s, d.m, d.pb);
+                for (int b = 0; b < nb; ++b) {
+                    const BondX x = sld(d.bx + b);
+                    const B bd = sld(reinterpret_cast<const B *>(d.bonds) + b);
+                    const W fl = (W)x.flip, sf = s & fl;
+                    if (sf == 0 || sf == fl) continue;
+                    junq += bd.jz;
+                    const SubKey kt = sub_key_flip(kr, x);
+                    term(bd, s ^ fl, &kt);
+                }
+                done = true;
+            }
+        }
+        if (!done) {
+            for (int b = 0; b < nb; ++b) {
+                const B bd = S.bonds[b];
+                if (((s >> bd.i) & 1) == ((s >> bd.j) & 1)) continue;
+                junq += bd.jz;
+                term(bd, s ^ ((W(1) << bd.i) | (W(1) << bd.j)), nullptr);
+            }
         }
     }
     const size_t base = ((size_t)row * nvec + v0) * C;

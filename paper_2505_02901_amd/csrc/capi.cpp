@@ -266,6 +266,16 @@ int xdg_create_hamiltonian(xdg_basis b, int n_bonds, const int32_t *sites, const
         }
         int rc = h->bonds_d.upload(bd.data(), sizeof(BondD) * std::max(n_bonds, 1));
         if (rc == XDG_OK) rc = h->bonds_f.upload(bf.data(), sizeof(BondF) * std::max(n_bonds, 1));
+        const auto &sp = b->plan.sub;
+        if (rc == XDG_OK && b->plan.kind == XDG_SEARCH_SUBLATTICE &&
+            sub_packed_ok(sp.n_s, sp.m, sp.pb)) {
+            std::vector<BondX> bx(std::max(n_bonds, 1), BondX{});
+            for (int e = 0; e < n_bonds; ++e) {
+                bondx_site((int)bd[e].i, sp.m, sp.pb, bx[e]);
+                bondx_site((int)bd[e].j, sp.m, sp.pb, bx[e]);
+            }
+            rc = h->bonds_x.upload(bx.data(), sizeof(BondX) * bx.size());
+        }
         if (rc != XDG_OK) {
             basis_release(h->basis);
             delete h;

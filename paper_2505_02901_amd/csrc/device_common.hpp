@@ -34,6 +34,26 @@ template <class T>
 __device__ __forceinline__ void gst(T *p, T v) {
     *(__attribute__((address_space(1))) T *)p = v;
 }
+// Loads of read-only data at a wave-uniform address (the caller's promise):
+// the address is taken from the first active lane and read through the
+// constant address space, so the load is a scalar one into scalar registers.
+// Read dword by dword (a class type's copy constructor would take a generic
+// reference); the dwords merge into one wide scalar load.
+template <class T>
+__device__ __forceinline__ T sld(const T *p) {
+    static_assert(sizeof(T) % 4 == 0, "whole dwords");
+    const uint64_t a = (uint64_t)p;
+    const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)a);
+    const uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)(a >> 32));
+    const __attribute__((address_space(4))) uint32_t *q =
+        (const __attribute__((address_space(4))) uint32_t *)(((uint64_t)hi << 32) | lo);
+    struct Words {
+        uint32_t w[sizeof(T) / 4];
+    } v;
+#pragma unroll
+    for (int i = 0; i < (int)(sizeof(T) / 4); ++i) v.w[i] = q[i];
+    return __builtin_bit_cast(T, v);
+}
 
 // ------------------------------------------------------------ bit helpers --
 // Rotations of the low N bits of t by 0 <= a < N sites.  FULL: N is the
@@ -570,50 +590,52 @@ __device__ __forceinline__ bool sub_is_rep(const SubCtx &C, W s, const double2 *
 // multiple of 4E) or'ed with 7 times the source block, so one bit-field
 // extract of the packed word at w's low five bits and one and-or with w give
 // a table address.  Every candidate's top block is the minimal top, so the
-// three lower image blocks (at most 30 bits) decide as one 32-bit word, and
-// the lists of all blocks reaching the minimal top run as one loop.
+// three lower image blocks (at most 30 bits) decide as one 32-bit word.
 typedef __attribute__((address_space(3))) const uint16_t lds_u16;
 
-__host__ __device__ constexpr bool sub_packed_ok(int n_s, int m, int pb) {
-    return n_s == 4 && m <= 10 && pb >= 3 && pb <= 5 && m - pb <= pb;
-}
+// A state's key for the packed search: its four block-table indices
+// e_k = k 2^m + chunk_k and its two packed words.
+struct SubKey {
+    uint32_t e[4];
+    uint32_t lo2, hi2;
+};
 
-// the packed words of state t
 template <class W>
-__device__ __forceinline__ void sub_pack(W t, int m, int pb, uint32_t &lo2, uint32_t &hi2) {
-    const uint32_t E = 1u << pb, vmask = (1u << m) - 1;
-    lo2 = 0;
-    hi2 = 0;
+__device__ __forceinline__ SubKey sub_key(W t, int m, int pb) {
+    const uint32_t E = 1u << pb, V = 1u << m, vmask = V - 1;
+    SubKey K;
+    K.lo2 = 0;
+    K.hi2 = 0;
 #pragma unroll
     for (int k = 0; k < 4; ++k) {
         const uint32_t c = chunk_of<W>(t, k, m, vmask);
-        lo2 |= ((c & (E - 1)) << 1) << (7 * k);
-        hi2 |= ((E + (c >> pb)) << 1) << (7 * k);
+        K.e[k] = k * V + c;
+        K.lo2 |= ((c & (E - 1)) << 1) << (7 * k);
+        K.hi2 |= ((E + (c >> pb)) << 1) << (7 * k);
     }
+    return K;
 }
 
-// the bits of the packed words that change when site i flips
-__device__ __forceinline__ void sub_pack_site(int i, int m, int pb, uint32_t &lo2, uint32_t &hi2) {
-    const int q = i / m, p = i - q * m;
-    if (p < pb)
-        lo2 |= 1u << (7 * q + 1 + p);
-    else
-        hi2 |= 1u << (7 * q + 1 + p - pb);
+// the key of a state with two sites exchanged (x: that bond's bits)
+__device__ __forceinline__ SubKey sub_key_flip(const SubKey &K, const BondX &x) {
+    SubKey T;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) T.e[k] = K.e[k] ^ x.ek[k];
+    T.lo2 = K.lo2 ^ x.plo;
+    T.hi2 = K.hi2 ^ x.phi;
+    return T;
 }
 
 // C.sp holds the packed (element, block) entries; amask = ~(4E - 1).
 template <class W>
-__device__ __forceinline__ void sub_search_packed(const SubCtx &C, uint32_t amask, W t,
-                                                  uint32_t lo2, uint32_t hi2, W &best, int &u,
-                                                  int &cnt) {
+__device__ __forceinline__ void sub_search_packed(const SubCtx &C, uint32_t amask,
+                                                  const SubKey &K, W &best, int &u, int &cnt) {
     const int m = C.m;
-    const uint32_t V = 1u << m, vmask = V - 1;
-    uint32_t e[4], mv[4];
+    const uint32_t *e = K.e;
+    const uint32_t lo2 = K.lo2, hi2 = K.hi2;
+    uint32_t mv[4];
 #pragma unroll
-    for (int k = 0; k < 4; ++k) {
-        e[k] = k * V + chunk_of<W>(t, k, m, vmask);
-        mv[k] = C.mintop[e[k]];
-    }
+    for (int k = 0; k < 4; ++k) mv[k] = C.mintop[e[k]];
     const uint32_t mt = min(min(mv[0], mv[1]), min(mv[2], mv[3]));
     typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
     uint32_t bl = 0xFFFFFFFFu, bu = 0x7fffffffu, bc = 0;

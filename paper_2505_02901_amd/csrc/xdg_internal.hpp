@@ -202,6 +202,7 @@ struct xdg_ham_s {
     std::vector<double> jz, jxy;
     xdg::DevBuf bonds_d;        // BondD [n_bonds]
     xdg::DevBuf bonds_f;        // BondF [n_bonds]
+    xdg::DevBuf bonds_x;        // BondX [n_bonds] (packed sublattice search only)
     int64_t nnz = -1;
     std::mutex tune_mu;         // guards `tuned` (and the tuning runs that fill it)
     std::map<xdg::TuneKey, xdg::LaunchCfg> tuned;
@@ -217,6 +218,31 @@ struct BondF {
     uint32_t i, j;
     float jz, h;
 };
+
+// The packed form of the sublattice search applies to four blocks of at most
+// 10 sites whose half-chunk tables have 2^pb entries, 3 <= pb <= 5.
+__host__ __device__ constexpr bool sub_packed_ok(int n_s, int m, int pb) {
+    return n_s == 4 && m <= 10 && pb >= 3 && pb <= 5 && m - pb <= pb;
+}
+
+// Per-bond data of the packed sublattice search, in device bond order, read
+// with scalar loads: the two sites as a mask, and the bits that exchanging
+// them flips in a state's packed words and in its four block-table indices.
+struct BondX {
+    uint64_t flip;
+    uint32_t plo, phi;
+    uint32_t ek[4];
+};
+// site i's share of those bits (block q = i / m, position p = i mod m)
+inline void bondx_site(int i, int m, int pb, BondX &x) {
+    const int q = i / m, p = i - q * m;
+    x.flip |= 1ull << i;
+    x.ek[q] |= 1u << p;
+    if (p < pb)
+        x.plo |= 1u << (7 * q + 1 + p);
+    else
+        x.phi |= 1u << (7 * q + 1 + p - pb);
+}
 
 int basis_build_device(xdg_basis_s *b);                 // enumerate + index
 int basis_lookup(xdg_basis_s *b, const uint64_t *d_states, int64_t n, int64_t *d_idx,
