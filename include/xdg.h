@@ -344,6 +344,39 @@ int xdg_ftlm_thermo(int n_rec, int m, const double *alpha, const double *beta,
                     const double *weight, int n_temp, const double *temps, double *energy,
                     double *heat, double *log_z);
 
+/* Microcanonical thermal pure quantum states (the thermodynamics examples of
+ * Sec. 4.6; the construction of Sugiura and Shimizu 2012): from a unit start
+ * vector |0> (v0 normalised by the call, or the seeded Gaussian vector of
+ * xdg_random_vector kind 1 when v0 is NULL) the sequence
+ *   |k+1> = (l - H/N)|k> / || (l - H/N)|k> ||,   N = number of sites,
+ * one H x per step, recording for k = 0 .. n_steps - 1
+ *   u[k] = <k|H|k> / N,   u2[k] = <k|H^2|k> / N^2   (FP64 products).
+ * l must be at least the largest eigenvalue of H/N on the block for the
+ * sequence to run from high to low energy.
+ *   v0: device [dim] of the block's dtype for prec, or NULL; prec:
+ *   XDG_PREC_F64 or XDG_PREC_F32VEC; u, u2: host double[n_steps].
+ * Synchronises `stream` once, at the end. */
+int xdg_tpq_micro(xdg_ham h, const void *v0, uint64_t seed, int prec, double l, int n_steps,
+                  double *u, double *u2, void *stream);
+
+/* Canonical TPQ thermodynamics from n_rec microcanonical sequences of
+ * n_steps (Sec. 4.6; Sugiura and Shimizu 2013): with h = H/N, the moments
+ * M_n = <0|(l - h)^n|0> for n <= 2 n_steps follow from u and u2
+ * (q_0 = 1, q_{k+1} = q_k (l^2 - 2 l u_k + u2_k), M_{2k} = q_k,
+ * M_{2k+1} = q_k (l - u_k)); with x = N / T and S_j = sum_n M_{n+j} x^n / n!,
+ * summed over the sequences with their weights,
+ *   ln Z = ln sum_r weight[r] S_0 - x l,   <H> = N (l - S_1 / S_0),
+ *   heat = x^2 (S_2 / S_0 - (S_1 / S_0)^2)   (= (<H^2> - <H>^2) / T^2).
+ * weight[r] = block dimension / number of sequences in that block.  NaN at a
+ * temperature where a truncated series has not converged (last kept term
+ * not below 1e-12 of its sum): more steps are needed there.
+ * XDG_EINVAL if l < u[k] anywhere, a weight or temperature is not > 0.
+ *   u, u2: host double[n_rec][n_steps]; temps: host double[n_temp];
+ *   energy, heat, log_z: host double[n_temp].  Host only. */
+int xdg_tpq_thermo(int n_rec, int n_steps, const double *u, const double *u2, double l,
+                   int n_sites, const double *weight, int n_temp, const double *temps,
+                   double *energy, double *heat, double *log_z);
+
 /* y = O x for the one-site diagonal operator O = sum_j c_j S^z_j taking a
  * vector of block `in` to block `out` (an operator at momentum q from the
  * symmetrisation of Sec. 3.13, e.g. c_j = e^{i q j} / sqrt(N); dynamical

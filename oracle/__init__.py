@@ -382,3 +382,84 @@ def dense_sz_spectrum(m_u1, coef) -> Tuple[float, np.ndarray, np.ndarray]:
     phi = o * U[:, 0]
     w = np.abs(U.conj().T @ phi) ** 2
     return float(E[0]), E - E[0], w
+
+
+# ---------------------------------------------------------------------------
+# Thermal pure quantum states (thermodynamics examples, Sec. 4.6)
+# ---------------------------------------------------------------------------
+
+def tpq_micro(m, basis_list: np.ndarray, x0: np.ndarray, l: float, n_steps: int):
+    """Microcanonical TPQ sequence (Sugiura and Shimizu 2012) from the unit
+    vector x0 / |x0|: |k+1> = (l - H/N)|k>, normalised; returns
+    u[k] = <k|H|k> / N and u2[k] = <k|H^2|k> / N^2 for k < n_steps, with the
+    oracle's H x in FP64."""
+    N = m.n_sites
+    v = np.asarray(x0, dtype=np.complex128).ravel()
+    v = v / np.linalg.norm(v)
+    u = np.zeros(n_steps)
+    u2 = np.zeros(n_steps)
+    for k in range(n_steps):
+        w = apply(m, basis_list, v)
+        u[k] = np.vdot(v, w).real / N
+        u2[k] = np.vdot(w, w).real / N ** 2
+        v = l * v - w / N
+        v = v / np.linalg.norm(v)
+    return u, u2
+
+
+def tpq_canonical(u, u2, l: float, n_sites: int, weight, temps):
+    """Canonical TPQ thermodynamics (Sugiura and Shimizu 2013) from
+    microcanonical sequences u, u2 [n_rec][K]: the canonical state
+    exp(-H / 2T)|psi> = exp(-x l / 2) sum_n (x / 2)^n / n! (l - h)^n |psi>,
+    h = H/N, x = N/T, so every expectation value in it is a series in the
+    moments M_n = <psi|(l - h)^n|psi>.  Those come from the sequence:
+    |k> is (l - h)^k |psi> over its norm sqrt(q_k), hence
+    M_{2k} = q_k, M_{2k+1} = q_k <k|(l - h)|k>, q_{k+1} = q_k <k|(l - h)^2|k>.
+    Returns (energy, heat, log_z) per temperature; NaN where the last kept
+    term of a series is not below 1e-12 of its sum.  Plain loops in log
+    space (math.lgamma), one sequence at a time."""
+    import math
+    U = np.atleast_2d(np.asarray(u, np.float64))
+    U2 = np.atleast_2d(np.asarray(u2, np.float64))
+    R, K = U.shape
+    wts = np.broadcast_to(np.asarray(weight, np.float64), (R,))
+    logM = []
+    for r in range(R):
+        lm = [-math.inf] * (2 * K + 1)
+        lq = 0.0
+        for k in range(K):
+            lm[2 * k] = lq
+            a = l - U[r, k]
+            lm[2 * k + 1] = lq + math.log(a) if a > 0 else -math.inf
+            q = l * l - 2 * l * U[r, k] + U2[r, k]
+            if q <= 0:
+                break
+            lq += math.log(q)
+            if k == K - 1:
+                lm[2 * K] = lq
+        logM.append(lm)
+    N = n_sites
+    energy, heat, log_z = [], [], []
+    for T in np.asarray(temps, np.float64):
+        x = N / T
+        logS, ok = [], True
+        for j in range(3):
+            terms, lasts = [], []
+            for r in range(R):
+                for n in range(2 * K - j + 1):
+                    t = math.log(wts[r]) + logM[r][n + j] + n * math.log(x) - math.lgamma(n + 1)
+                    terms.append(t)
+                    if n == 2 * K - j:
+                        lasts.append(t)
+            top = max(terms)
+            s = sum(math.exp(t - top) for t in terms)
+            last = sum(math.exp(t - top) for t in lasts)
+            if last > 1e-12 * s:
+                ok = False
+            logS.append(top + math.log(s))
+        a1 = math.exp(logS[1] - logS[0])
+        a2 = math.exp(logS[2] - logS[0])
+        energy.append(N * (l - a1) if ok else math.nan)
+        heat.append(x * x * (a2 - a1 * a1) if ok else math.nan)
+        log_z.append(logS[0] - x * l if ok else math.nan)
+    return np.array(energy), np.array(heat), np.array(log_z)

@@ -476,6 +476,26 @@ int xdg_ftlm_thermo(int n_rec, int m, const double *alpha, const double *beta,
     });
 }
 
+int xdg_tpq_micro(xdg_ham h, const void *v0, uint64_t seed, int prec, double l, int n_steps,
+                  double *u, double *u2, void *stream) {
+    return guarded([&]() -> int {
+        if (!h) {
+            set_error("null hamiltonian");
+            return XDG_EINVAL;
+        }
+        return tpq_micro(h, v0, seed, prec, l, n_steps, u, u2, (hipStream_t)stream);
+    });
+}
+
+int xdg_tpq_thermo(int n_rec, int n_steps, const double *u, const double *u2, double l,
+                   int n_sites, const double *weight, int n_temp, const double *temps,
+                   double *energy, double *heat, double *log_z) {
+    return guarded([&]() -> int {
+        return tpq_thermo(n_rec, n_steps, u, u2, l, n_sites, weight, n_temp, temps, energy, heat,
+                          log_z);
+    });
+}
+
 int xdg_apply_sz_transfer(xdg_basis in, xdg_basis out, const double *coef, const void *x,
                           void *y, int dtype, void *stream) {
     return guarded([&]() -> int {

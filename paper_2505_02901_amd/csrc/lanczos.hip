@@ -1155,6 +1155,82 @@ int lanczos_batched(int n, xdg_ham_s *const *hams, const void *const *v0s, int64
     return rc;
 }
 
+// Microcanonical TPQ sequence (Sec. 4.6, after Sugiura and Shimizu 2012):
+// |k+1> = (l - H/N)|k> / norm from a unit start vector; per step one H x,
+// the FP64 products <k|H|k> and <H k|H k> into device histories, then the
+// next vector H|k> - l N |k> (the sign drops out of every expectation value)
+// normalised in place.  The histories reach the host once, at the end.
+int tpq_micro(xdg_ham_s *h, const void *v0, uint64_t seed, int prec, double l, int n_steps,
+              double *u, double *u2, hipStream_t st) {
+    const xdg_basis_s *b = h->basis;
+    if (n_steps < 1 || !u || !u2 || !std::isfinite(l)) {
+        set_error("tpq: need n_steps >= 1, output arrays and a finite l");
+        return XDG_EINVAL;
+    }
+    if (prec != XDG_PREC_F64 && prec != XDG_PREC_F32VEC) {
+        set_error("tpq: precision form %d (XDG_PREC_F64 or XDG_PREC_F32VEC)", prec);
+        return XDG_EINVAL;
+    }
+    const int64_t D = b->dim;
+    if (D < 1) {
+        set_error("tpq on an empty block");
+        return XDG_EINVAL;
+    }
+    const bool single = prec == XDG_PREC_F32VEC;
+    const int C = b->is_complex ? 2 : 1;
+    const int dtype = C == 2 ? (single ? XDG_C64 : XDG_C128) : (single ? XDG_F32 : XDG_F64);
+    const size_t esz = (single ? 4 : 8) * C;
+    const uint64_t nsc = (uint64_t)D * C;
+    const size_t vbytes = (size_t)D * esz;
+    const size_t vstride = (vbytes + 255) & ~(size_t)255;
+    const double N = (double)b->n_sites;
+
+    DevBuf vbuf, scal, parts;
+    XDG_RETURN_IF(vbuf.alloc(2 * vstride));
+    // scalars: <v,Hv>, <Hv,Hv>, norm, l N, unused, histories [2][n_steps], jdev
+    XDG_RETURN_IF(scal.alloc(sizeof(double) * (5 + 2 * (size_t)n_steps) + 16));
+    double *s_vw = scal.as<double>(), *s_ww = s_vw + 1, *s_nrm = s_vw + 2, *s_ln = s_vw + 3;
+    double *s_dummy = s_vw + 4, *h_vw = s_vw + 5, *h_ww = h_vw + n_steps;
+    int *jdev = reinterpret_cast<int *>(h_ww + n_steps);
+    VecOps ops{single, C, C, nsc, vec_grid(nsc), nullptr, st};
+    XDG_RETURN_IF(parts.alloc(sizeof(double) * (size_t)ops.grid * MAXC));
+    ops.partials = parts.as<double>();
+    char *v = vbuf.as<char>(), *w = v + vstride;
+    if (v0)
+        XDG_TRY_HIP(hipMemcpyAsync(v, v0, vbytes, hipMemcpyDeviceToDevice, st));
+    else
+        XDG_RETURN_IF(random_fill((int64_t)nsc, seed, 1, single, v, st));
+    const double ln = l * N;
+    XDG_TRY_HIP(hipMemcpyAsync(s_ln, &ln, sizeof(double), hipMemcpyHostToDevice, st));
+    hipLaunchKernelGGL(k_set_scalars, dim3(1), dim3(64), 0, st, jdev, s_dummy, 1);
+    XDG_TRY_HIP(hipGetLastError());
+    XDG_RETURN_IF(ops.dot(v, v));
+    XDG_RETURN_IF(ops.finalize(1, s_nrm, nullptr, jdev));
+    XDG_RETURN_IF(ops.scale(v, v, s_nrm));
+    for (int k = 0; k < n_steps; ++k) {
+        XDG_RETURN_IF(apply_tuned(h, v, w, 1, dtype, st));
+        XDG_RETURN_IF(ops.dot(v, w));
+        XDG_RETURN_IF(ops.finalize(0, s_vw, h_vw, jdev));
+        XDG_RETURN_IF(ops.dot(w, w));
+        XDG_RETURN_IF(ops.finalize(0, s_ww, h_ww, jdev));
+        if (k + 1 < n_steps) {
+            XDG_RETURN_IF(ops.update(w, v, nullptr, s_ln, nullptr));   // w = H v - l N v
+            XDG_RETURN_IF(ops.finalize(1, s_nrm, nullptr, jdev));
+            XDG_RETURN_IF(ops.scale(w, v, s_nrm));
+        }
+        hipLaunchKernelGGL(k_step_end, dim3(1), dim3(64), 0, st, jdev, s_dummy, s_dummy, 1);
+        XDG_TRY_HIP(hipGetLastError());
+    }
+    std::vector<double> hv(n_steps), hw(n_steps);
+    XDG_RETURN_IF(copy_d2h(hv.data(), h_vw, sizeof(double) * n_steps, st));
+    XDG_RETURN_IF(copy_d2h(hw.data(), h_ww, sizeof(double) * n_steps, st));
+    for (int k = 0; k < n_steps; ++k) {
+        u[k] = hv[k] / N;
+        u2[k] = hw[k] / (N * N);
+    }
+    return XDG_OK;
+}
+
 int last_timing(double *total, double *apply) {
     if (total) *total = g_t_total;
     if (apply) *apply = g_t_apply;

@@ -62,6 +62,91 @@ int ftlm_thermo(int n_rec, int m, const double *alpha, const double *beta, const
     return XDG_OK;
 }
 
+// Canonical TPQ thermodynamics from microcanonical sequences (Sec. 4.6,
+// after Sugiura and Shimizu 2013).  With h = H/N and |phi_k> = (l - h)^k |psi>
+// for a unit |psi>, the moments M_n = <psi|(l - h)^n|psi> follow from the
+// normalised sequence |k> = |phi_k> / sqrt(q_k):
+//   q_0 = 1,  q_{k+1} = q_k <k|(l - h)^2|k> = q_k (l^2 - 2 l u_k + u2_k),
+//   M_{2k} = q_k,  M_{2k+1} = q_k (l - u_k).
+// The canonical state e^{-beta H / 2}|psi> = e^{-x l / 2} e^{x (l - h) / 2}|psi>,
+// x = N beta, then has
+//   <(l - h)^j> = S_j / S_0,  S_j = sum_n M_{n+j} x^n / n!,
+//   <psi| e^{-beta H} |psi> = e^{-x l} S_0,
+// with every sum over the moments that K steps give (n + j <= 2K).  The
+// ensemble sums numerators and denominators over the sequences with their
+// weights; the sums run in log space.  A series whose last kept term is not
+// below 1e-12 of its sum is not converged at that temperature: NaN there.
+int tpq_thermo(int n_rec, int n_steps, const double *u, const double *u2, double l, int n_sites,
+               const double *weight, int n_temp, const double *temps, double *energy,
+               double *heat, double *log_z) {
+    if (n_rec < 1 || n_steps < 1 || !u || !u2 || !weight || n_sites < 1 || !std::isfinite(l) ||
+        n_temp < 0 || (n_temp > 0 && (!temps || !energy || !heat || !log_z))) {
+        set_error("tpq: bad arguments");
+        return XDG_EINVAL;
+    }
+    for (int t = 0; t < n_temp; ++t)
+        if (!(temps[t] > 0.0)) {
+            set_error("tpq: temperature %d is %g (must be > 0)", t, temps[t]);
+            return XDG_EINVAL;
+        }
+    const int K = n_steps;
+    // log moments per sequence; -inf for a zero moment (the sequence ended
+    // in an eigenvector of h with eigenvalue l: every later moment is zero)
+    std::vector<std::vector<double>> lm(n_rec, std::vector<double>(2 * (size_t)K + 1, -INFINITY));
+    for (int r = 0; r < n_rec; ++r) {
+        const double *ur = u + (size_t)r * K, *u2r = u2 + (size_t)r * K;
+        if (!(weight[r] > 0.0)) {
+            set_error("tpq: weight %d is %g (must be > 0)", r, weight[r]);
+            return XDG_EINVAL;
+        }
+        double lq = 0.0;   // log q_k
+        for (int k = 0; k < K; ++k) {
+            const double a = l - ur[k];
+            if (a < 0.0) {
+                set_error("tpq: l = %g is below <k|H/N|k> = %g (sequence %d, step %d)", l, ur[k],
+                          r, k);
+                return XDG_EINVAL;
+            }
+            lm[r][2 * k] = lq;
+            lm[r][2 * k + 1] = a > 0.0 ? lq + std::log(a) : -INFINITY;
+            const double q = l * l - 2.0 * l * ur[k] + u2r[k];
+            if (!(q > 0.0)) break;
+            lq += std::log(q);
+            if (k + 1 == K) lm[r][2 * K] = lq;
+        }
+    }
+    const double N = (double)n_sites;
+    for (int t = 0; t < n_temp; ++t) {
+        const double x = N / temps[t], lx = std::log(x);
+        // log of sum_r w_r S_j^(r), j = 0, 1, 2, and the convergence test
+        double ls[3];
+        bool ok = true;
+        for (int j = 0; j < 3; ++j) {
+            const int nmax = 2 * K - j;
+            double mx = -INFINITY;
+            for (int r = 0; r < n_rec; ++r)
+                for (int n = 0; n <= nmax; ++n)
+                    mx = std::max(mx, std::log(weight[r]) + lm[r][n + j] + n * lx -
+                                          std::lgamma(n + 1.0));
+            double s = 0.0, last = 0.0;
+            for (int r = 0; r < n_rec; ++r)
+                for (int n = 0; n <= nmax; ++n) {
+                    const double e = std::exp(std::log(weight[r]) + lm[r][n + j] + n * lx -
+                                              std::lgamma(n + 1.0) - mx);
+                    s += e;
+                    if (n == nmax) last += e;
+                }
+            ls[j] = mx + std::log(s);
+            if (last > 1e-12 * s) ok = false;
+        }
+        const double a1 = std::exp(ls[1] - ls[0]), a2 = std::exp(ls[2] - ls[0]);
+        energy[t] = ok ? N * (l - a1) : NAN;
+        heat[t] = ok ? x * x * (a2 - a1 * a1) : NAN;
+        log_z[t] = ok ? ls[0] - x * l : NAN;
+    }
+    return XDG_OK;
+}
+
 // Spectral function from a Lanczos recurrence started at phi (continued
 // fraction of the resolvent; the dynamical examples of Sec. 4.4):
 //   G(z) = |phi|^2 / (z - a_0 - b_0^2 / (z - a_1 - b_1^2 / (...))),

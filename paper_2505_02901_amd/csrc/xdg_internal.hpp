@@ -304,6 +304,11 @@ int lanczos_single(xdg_ham_s *h, const void *v0, int k, double tol, int max_iter
 int lanczos_batched(int n, xdg_ham_s *const *hams, const void *const *v0s, int64_t nvec,
                     int n_iter, uint64_t seed, int prec, double *evals, double *alpha,
                     double *beta, hipStream_t st, double *t_total, double *t_apply);
+int tpq_micro(xdg_ham_s *h, const void *v0, uint64_t seed, int prec, double l, int n_steps,
+              double *u, double *u2, hipStream_t st);
+int tpq_thermo(int n_rec, int n_steps, const double *u, const double *u2, double l, int n_sites,
+               const double *weight, int n_temp, const double *temps, double *energy,
+               double *heat, double *log_z);
 void tridiag_eigenvalues(int m, const double *alpha, const double *beta, std::vector<double> &out);
 void tridiag_spectral_weights(int m, const double *alpha, const double *beta,
                               std::vector<double> &evals, std::vector<double> &weights);

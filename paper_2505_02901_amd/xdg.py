@@ -92,6 +92,8 @@ def lib():
             "xdg_lanczos_eigvec": (I, [P, P, U64, I, I, P, P, I, P, P, P]),
             "xdg_expect_szsz": (I, [P, P, I, I, P, P, P]),
             "xdg_ftlm_thermo": (I, [I, I, P, P, P, I, P, P, P, P]),
+            "xdg_tpq_micro": (I, [P, P, U64, I, D, I, P, P, P]),
+            "xdg_tpq_thermo": (I, [I, I, P, P, D, I, P, I, P, P, P, P]),
             "xdg_apply_sz_transfer": (I, [P, P, P, P, P, I, P]),
             "xdg_spectral_cf": (I, [I, P, P, D, D, I, P, D, P]),
         }
@@ -115,7 +117,8 @@ def exported_names():
             "xdg_apply_tuned_config",
             "xdg_random_state", "xdg_lanczos_eigval", "xdg_lanczos_eigval_batched",
             "xdg_last_lanczos_timing", "xdg_lanczos_eigvec", "xdg_expect_szsz",
-            "xdg_ftlm_thermo", "xdg_apply_sz_transfer", "xdg_spectral_cf"]
+            "xdg_ftlm_thermo", "xdg_tpq_micro", "xdg_tpq_thermo", "xdg_apply_sz_transfer",
+            "xdg_spectral_cf"]
 
 
 def _check(rc: int, allow=(XDG_OK,)):
@@ -524,6 +527,41 @@ def xdg_ftlm_thermo(alpha, beta, weight, temps):
     return e, c, z
 
 
+def xdg_tpq_micro(h, l: float, n_steps: int, seed: int = 0, prec: int = XDG_PREC_F64, v0=None,
+                  stream=None):
+    """(u, u2) of the microcanonical TPQ sequence |k+1> ~ (l - H/N)|k>:
+    u[k] = <k|H|k>/N, u2[k] = <k|H^2|k>/N^2."""
+    if _is_tensor(v0):
+        dim, cplx = xdg_ham_dim(h)
+        _check_vec("v0", v0, dim, 1, _prec_dtype(prec, cplx))
+    u = np.zeros(n_steps, np.float64)
+    u2 = np.zeros(n_steps, np.float64)
+    _check(lib().xdg_tpq_micro(h, _ptr(v0), seed, prec, l, n_steps,
+                               u.ctypes.data_as(C.c_void_p), u2.ctypes.data_as(C.c_void_p),
+                               _stream(stream)))
+    return u, u2
+
+
+def xdg_tpq_thermo(u, u2, l: float, n_sites: int, weight, temps):
+    """(energy, heat, log_z) per temperature from microcanonical TPQ
+    sequences u, u2 [n_rec, n_steps] with weights [n_rec] (canonical TPQ)."""
+    uu = np.ascontiguousarray(u, dtype=np.float64)
+    K = uu.shape[-1]
+    uu = uu.reshape(-1, K)
+    vv = np.ascontiguousarray(u2, dtype=np.float64).reshape(-1, K)
+    if vv.shape != uu.shape:
+        raise ValueError("u and u2 must have the same shape")
+    w = np.ascontiguousarray(np.broadcast_to(np.asarray(weight, np.float64), (uu.shape[0],)))
+    T = np.ascontiguousarray(temps, dtype=np.float64)
+    e, c, z = (np.zeros(len(T)) for _ in range(3))
+    _check(lib().xdg_tpq_thermo(uu.shape[0], K, uu.ctypes.data_as(C.c_void_p),
+                                vv.ctypes.data_as(C.c_void_p), l, n_sites,
+                                w.ctypes.data_as(C.c_void_p), len(T),
+                                T.ctypes.data_as(C.c_void_p), e.ctypes.data_as(C.c_void_p),
+                                c.ctypes.data_as(C.c_void_p), z.ctypes.data_as(C.c_void_p)))
+    return e, c, z
+
+
 def xdg_apply_sz_transfer(b_in, b_out, coef, x, y, dtype: Optional[int] = None, stream=None):
     """y = (sum_j coef_j S^z_j) x from block b_in to block b_out."""
     c = np.asarray(coef, dtype=np.complex128)
@@ -630,6 +668,9 @@ class Hamiltonian:
 
     def lanczos(self, **kw):
         return xdg_lanczos_eigval(self.handle, **kw)
+
+    def tpq(self, l: float, n_steps: int, **kw):
+        return xdg_tpq_micro(self.handle, l, n_steps, **kw)
 
     def eig0(self, tol: float = 1e-12, max_iter: int = 300, seed: int = 0,
              prec: int = XDG_PREC_F64, v0=None, stream=None):

@@ -673,6 +673,50 @@ def test_ftlm_batched_matches_oracle_quadrature(X):
     assert abs(nodes.min() - bethe_energy(N, N // 2)) < 1e-8
 
 
+@pytest.mark.parametrize("mi", [0, 1])
+def test_tpq_micro_matches_oracle(X, mi):
+    """Microcanonical TPQ sequence on the GPU (one H x per step, FP64
+    products) against the oracle's recursion from the same start vector:
+    u and u2 to 1e-10 with FP64 vectors and 2e-5 with FP32 vectors; the
+    canonical energy and heat of that one vector from the GPU sequence against
+    <psi|e^{-H/T} H^k|psi> from the eigendecomposition of the oracle's block;
+    a seeded run without a start vector cools from the middle of the band."""
+    m = [W.chain_model(16, l=0), W.chain_model(14, l=3)][mi]
+    b = X.Basis.from_model(m)
+    H = X.Hamiltonian.from_model(b, m)
+    basis = oracle_basis(m)
+    D, N = len(basis), m.n_sites
+    x0 = W.random_vector(11, D, complex_=m.is_complex)
+    l, K = 1.0, 50
+    uo, u2o = oracle.tpq_micro(m, basis, x0, l, K)
+    forms = ((X.XDG_PREC_F64, torch.complex128 if m.is_complex else torch.float64, 1e-10),
+             (X.XDG_PREC_F32VEC, torch.complex64 if m.is_complex else torch.float32, 2e-5))
+    for prec, dt, tol in forms:
+        v0 = torch.from_numpy(x0).to("cuda", dt)
+        u, u2 = X.xdg_tpq_micro(H.handle, l, K, prec=prec, v0=v0)
+        assert np.max(np.abs(u - uo)) <= tol * np.max(np.abs(uo)), (prec, u[:3], uo[:3])
+        assert np.max(np.abs(u2 - u2o)) <= tol * np.max(np.abs(u2o)), prec
+        if prec == X.XDG_PREC_F64:
+            E, U = np.linalg.eigh(oracle.apply(m, basis, np.eye(D, dtype=np.complex128)))
+            c2 = np.abs(U.conj().T @ (x0 / np.linalg.norm(x0))) ** 2
+            T = np.array([1.0, 2.0, 5.0])
+            e, c, lz = X.xdg_tpq_thermo(u, u2, l, N, D, T)
+            for t, T_ in enumerate(T):
+                f = c2 * np.exp(-(E - E.min()) / T_)
+                z = f.sum()
+                ee = f @ E / z
+                cc = (f @ E ** 2 / z - ee ** 2) / T_ ** 2
+                assert abs(e[t] - ee) <= 1e-8 * max(1.0, abs(ee)), (T_, e[t], ee)
+                assert abs(c[t] - cc) <= 1e-7 * max(1.0, abs(cc)), (T_, c[t], cc)
+    u, u2 = H.tpq(l, 30, seed=4, prec=X.XDG_PREC_F32VEC)
+    assert abs(u[0]) < 0.1 and u[-1] < u[0] and np.all(u2 >= u ** 2 - 1e-6)
+    with pytest.raises(X.XdgError):
+        X.xdg_tpq_micro(H.handle, l, 0)
+    with pytest.raises(X.XdgError):
+        X.xdg_tpq_micro(H.handle, l, 5, prec=X.XDG_PREC_F64_REORTH)
+
+
+
 @pytest.mark.parametrize("lq", [3, 6])
 def test_dynamical_structure_factor_matches_dense(X, lq):
     """S^zz(q, omega) of the N = 12 ring: ground state of the k = 0 block (two

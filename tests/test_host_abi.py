@@ -174,6 +174,39 @@ def test_ftlm_quadrature_against_eigh(X):
         X.xdg_ftlm_thermo(al, be, w, [0.0])
 
 
+def test_tpq_thermo_matches_oracle_series(X):
+    """Host-side canonical TPQ sums (C++) against the oracle's series (plain
+    Python loops) on the same microcanonical sequences: TPQ sequences of the
+    oracle from three start vectors, an unconverged low temperature (NaN on
+    both sides) and the argument checks."""
+    import oracle
+    m = W.chain_model(12, l=0)
+    b = oracle.basis(m)
+    D, N = len(b), m.n_sites
+    l = 1.0
+    us, u2s = [], []
+    for seed in (1, 2, 3):
+        u, u2 = oracle.tpq_micro(m, b, W.random_vector(seed, D), l, 60)
+        us.append(u)
+        u2s.append(u2)
+    us, u2s = np.array(us), np.array(u2s)
+    w = np.array([D / 3.0] * 3)
+    T = np.array([0.02, 0.3, 0.6, 1.0, 2.5, 50.0])
+    e, c, lz = X.xdg_tpq_thermo(us, u2s, l, N, w, T)
+    eo, co, lo = oracle.tpq_canonical(us, u2s, l, N, w, T)
+    assert np.array_equal(np.isnan(e), np.isnan(eo)) and np.isnan(e[0])
+    ok = ~np.isnan(eo)
+    assert np.allclose(e[ok], eo[ok], rtol=1e-12, atol=1e-12)
+    assert np.allclose(c[ok], co[ok], rtol=1e-10, atol=1e-12)
+    assert np.allclose(lz[ok], lo[ok], rtol=1e-12, atol=1e-12)
+    with pytest.raises(X.XdgError):                     # l below <k|h|k>
+        X.xdg_tpq_thermo(us, u2s, float(us.min()) - 0.1, N, w, T)
+    with pytest.raises(X.XdgError):
+        X.xdg_tpq_thermo(us, u2s, l, N, w, [0.0])
+    with pytest.raises(X.XdgError):
+        X.xdg_tpq_thermo(us, u2s, l, N, [0.0, 1.0, 1.0], [1.0])
+
+
 def test_ftlm_exact_at_full_krylov_dimension(X):
     """With as many (reorthogonalised) Lanczos steps as the block dimension
     the quadrature is exact: the library's thermodynamics from the oracle's

@@ -631,3 +631,99 @@ def test_rep_many_and_sampled_states(oracle_lib):
         got = oracle_lib.sample_basis_states(m, min(50, len(b)), 7)
         assert len(got) == min(50, len(b)) and np.all(np.diff(got.astype(np.int64)) > 0)
         assert all(oracle_lib.index(b, int(s)) >= 0 for s in got)
+
+
+# ---------------------------------------------------- thermal pure states --
+# The TPQ recursion and the canonical series of the oracle against the
+# eigendecomposition of the block (LAPACK): the spectral forms follow from
+# |k> ~ (l - h)^k |psi> with h = H/N written in the eigenbasis.
+
+def _spectrum(oracle, m):
+    b = oracle.basis(m)
+    E, U = np.linalg.eigh(oracle_dense(oracle, m, b))
+    return b, E, U
+
+
+def _tpq_spectral(E, c2, l, N, K):
+    """u_k, u2_k from the weights |c_n|^2 (l - e_n)^(2k) (e_n = E_n / N), in
+    log space."""
+    e = E / N
+    u, u2 = np.zeros(K), np.zeros(K)
+    keep = c2 > 0
+    lw0 = np.log(c2[keep])
+    le = np.log(l - e[keep])
+    for k in range(K):
+        lw = lw0 + 2 * k * le
+        p = np.exp(lw - lw.max())
+        p /= p.sum()
+        u[k] = p @ e[keep]
+        u2[k] = p @ e[keep] ** 2
+    return u, u2
+
+
+def _canonical_exact(E, c2, T):
+    """<psi|e^{-H/T} A|psi> forms for one vector: (energy, heat, ln sum)."""
+    lw = np.log(c2[c2 > 0]) - E[c2 > 0] / T
+    p = np.exp(lw - lw.max())
+    s = p.sum()
+    e1 = p @ E[c2 > 0] / s
+    e2 = p @ E[c2 > 0] ** 2 / s
+    return e1, (e2 - e1 * e1) / T ** 2, lw.max() + np.log(s)
+
+
+@pytest.mark.parametrize("mi", [0, 1])
+def test_tpq_micro_matches_spectral_form(oracle_lib, mi):
+    m = [W.chain_model(12, l=0), W.chain_model(12, l=5)][mi]
+    b, E, U = _spectrum(oracle_lib, m)
+    x0 = W.random_vector(3, len(b), complex_=m.is_complex)
+    c2 = np.abs(U.conj().T @ (x0 / np.linalg.norm(x0))) ** 2
+    l = E.max() / m.n_sites + 0.25
+    u, u2 = oracle_lib.tpq_micro(m, b, x0, l, 40)
+    uw, u2w = _tpq_spectral(E, c2, l, m.n_sites, 40)
+    assert np.allclose(u, uw, rtol=1e-10, atol=1e-12)
+    assert np.allclose(u2, u2w, rtol=1e-10, atol=1e-12)
+    assert u[-1] < u[0]                     # the sequence cools
+
+
+def test_tpq_canonical_single_vector_is_exact(oracle_lib):
+    m = W.chain_model(12, l=0)
+    b, E, U = _spectrum(oracle_lib, m)
+    D, N = len(b), m.n_sites
+    x0 = W.random_vector(5, D)
+    c2 = np.abs(U.T @ (x0 / np.linalg.norm(x0))) ** 2
+    l = E.max() / N + 0.25
+    u, u2 = _tpq_spectral(E, c2, l, N, 120)
+    T = np.array([0.4, 0.7, 1.0, 2.0, 10.0])
+    e, c, lz = oracle_lib.tpq_canonical(u, u2, l, N, D, T)
+    for t in range(len(T)):
+        ee, cc, ll = _canonical_exact(E, c2, T[t])
+        assert abs(e[t] - ee) <= 1e-9 * max(1.0, abs(ee))
+        assert abs(c[t] - cc) <= 1e-8 * max(1.0, abs(cc))
+        assert abs(lz[t] - (np.log(D) + ll)) <= 1e-9 * max(1.0, abs(ll))
+    # too few steps for a low temperature: not converged, NaN
+    e, c, lz = oracle_lib.tpq_canonical(u[:4], u2[:4], l, N, D, [0.05])
+    assert np.isnan(e[0]) and np.isnan(c[0]) and np.isnan(lz[0])
+
+
+def test_tpq_canonical_unit_vector_ensemble_is_the_trace(oracle_lib):
+    """All D basis vectors as start vectors, weight 1 each: Z = Tr e^{-H/T}
+    and the canonical energy and heat of the block, exactly."""
+    m = W.chain_model(10, l=0)
+    b, E, U = _spectrum(oracle_lib, m)
+    D, N = len(b), m.n_sites
+    l = E.max() / N + 0.25
+    us, u2s = [], []
+    for i in range(D):
+        u, u2 = _tpq_spectral(E, np.abs(U[i, :]) ** 2, l, N, 100)
+        us.append(u)
+        u2s.append(u2)
+    T = np.array([0.5, 1.0, 3.0])
+    e, c, lz = oracle_lib.tpq_canonical(np.array(us), np.array(u2s), l, N, 1.0, T)
+    for t in range(len(T)):
+        p = np.exp(-(E - E.min()) / T[t])
+        z = p.sum()
+        ee = p @ E / z
+        cc = (p @ E ** 2 / z - ee ** 2) / T[t] ** 2
+        assert abs(e[t] - ee) <= 1e-9 * max(1.0, abs(ee))
+        assert abs(c[t] - cc) <= 1e-8 * max(1.0, abs(cc))
+        assert abs(lz[t] - (np.log(z) - E.min() / T[t])) <= 1e-9 * max(1.0, abs(lz[t]))
