@@ -75,7 +75,7 @@ extern "C" {
 /* ---- Lanczos precision forms --------------------------------------------- */
 #define XDG_PREC_F64          0  /* FP64 (or complex FP64) vectors */
 #define XDG_PREC_F32VEC       1  /* FP32 (or complex FP32) vectors; FP64 dot products, norms, update, tridiagonal solve */
-#define XDG_PREC_F32VEC_REORTH 2 /* as F32VEC plus full reorthogonalisation (classical Gram-Schmidt twice, FP64 coefficients) */
+#define XDG_PREC_F32VEC_REORTH 2 /* as F32VEC plus full reorthogonalisation (classical Gram-Schmidt, FP64 coefficients, a second pass where the first removes more than half of the norm squared: Daniel, Gragg, Kaufman, Stewart 1976) */
 #define XDG_PREC_F64_REORTH   3  /* FP64 vectors plus full reorthogonalisation */
 
 typedef struct xdg_basis_s *xdg_basis;

@@ -246,10 +246,13 @@ __device__ __forceinline__ double wave_sum(double v) {
     return v;
 }
 
-// partials[(i C + c) nb + block] = the block's share of Re / Im <V_i, w>
+// partials[(i C + c) nb + block] = the block's share of Re / Im <V_i, w>.
+// skip (may be null): a device flag; when set the pass does nothing.
 template <class T, int C>
 __global__ __launch_bounds__(RB) void k_reorth_dots(const T *V, uint64_t ld, int k, const T *w,
-                                                    uint64_t nsc, double *partials) {
+                                                    uint64_t nsc, double *partials,
+                                                    const int *skip) {
+    if (skip && *skip) return;
     constexpr int RU = ru<T>(), L = 16 / (int)sizeof(T), S = RU * L;
     __shared__ double sh[RB / 64][RG * C];
     const int nb = gridDim.x, t = threadIdx.x, wave = t >> 6, lane = t & 63;
@@ -303,7 +306,8 @@ __global__ __launch_bounds__(RB) void k_reorth_dots(const T *V, uint64_t ld, int
 // per (i, c); coef[2 i + 1] = 0 for real vectors
 template <int C>
 __global__ __launch_bounds__(RB) void k_reorth_finalize(const double *partials, int n_blocks,
-                                                        double *coef) {
+                                                        double *coef, const int *skip) {
+    if (skip && *skip) return;
     __shared__ double sh[RB];
     const int e = blockIdx.x;   // i C + c
     double s = 0.0;
@@ -320,7 +324,9 @@ __global__ __launch_bounds__(RB) void k_reorth_finalize(const double *partials, 
 // w -= sum_i c_i V_i, accumulated in FP64 and rounded once on store
 template <class T, int C>
 __global__ __launch_bounds__(RB) void k_reorth_sub(const T *V, uint64_t ld, int k,
-                                                   const double *coef, T *w, uint64_t nsc) {
+                                                   const double *coef, T *w, uint64_t nsc,
+                                                   const int *skip) {
+    if (skip && *skip) return;
     constexpr int RU = ru<T>(), L = 16 / (int)sizeof(T), S = RU * L;
     const int t = threadIdx.x;
     const uint64_t tile0 = (uint64_t)blockIdx.x * tile_scalars<T>();
@@ -374,6 +380,14 @@ __global__ __launch_bounds__(RB) void k_reorth_sub(const T *V, uint64_t ld, int 
                 if (q + e < nsc) w[q + e] = (T)acc[u * L + e];
         }
     }
+}
+
+// Second Gram-Schmidt pass only where the first removed more than half of
+// |w|^2 (Daniel, Gragg, Kaufman and Stewart 1976, eta = 1/sqrt 2): skip = 1
+// when |w'|^2 >= |w|^2 / 2 (no cancellation, w' orthogonal to working
+// precision).
+__global__ void k_dgks(const double *n0, const double *n1, int *skip) {
+    if (threadIdx.x == 0) *skip = (*n1 >= 0.5 * *n0) ? 1 : 0;
 }
 
 int vec_grid(uint64_t n) {
@@ -618,12 +632,16 @@ int lanczos_single(xdg_ham_s *h, const void *v0, int k, double tol, int max_iter
     const int nstore = reorth ? max_iter + 1 : 3;
     XDG_RETURN_IF(bufs.alloc(vstride * nstore));
     XDG_RETURN_IF(wbuf.alloc(vbytes));
-    // scalars: cur_alpha, cur_beta, prev_beta, hist_alpha[max_iter], hist_beta[max_iter], jdev
-    XDG_RETURN_IF(scal.alloc(sizeof(double) * (3 + 2 * (size_t)max_iter + 2 * (size_t)(max_iter + 1)) + 16));
+    // scalars: cur_alpha, cur_beta, prev_beta, |w|^2 before and after a first
+    // reorthogonalisation pass, hist_alpha[max_iter], hist_beta[max_iter],
+    // coef[2 (max_iter + 1)], then jdev and the skip flag of the second pass
+    XDG_RETURN_IF(scal.alloc(sizeof(double) * (5 + 2 * (size_t)max_iter + 2 * (size_t)(max_iter + 1)) + 16));
     double *cur_alpha = scal.as<double>(), *cur_beta = cur_alpha + 1, *prev_beta = cur_alpha + 2;
-    double *hist_a = cur_alpha + 3, *hist_b = hist_a + max_iter;
+    double *nrm0 = cur_alpha + 3, *nrm1 = cur_alpha + 4;
+    double *hist_a = cur_alpha + 5, *hist_b = hist_a + max_iter;
     double *coef = hist_b + max_iter;
     int *jdev = reinterpret_cast<int *>(coef + 2 * (size_t)(max_iter + 1));
+    int *skip2 = jdev + 1;
     VecOps ops{single, C, C, nsc, vec_grid(nsc), nullptr, st};
     XDG_RETURN_IF(parts.alloc(sizeof(double) * (size_t)ops.grid * MAXC));
     ops.partials = parts.as<double>();
@@ -672,48 +690,58 @@ int lanczos_single(xdg_ham_s *h, const void *v0, int k, double tol, int max_iter
         XDG_RETURN_IF(ops.finalize(0, cur_alpha, hist_a, jdev));
         XDG_RETURN_IF(ops.update(w, v, vp, cur_alpha, prev_beta));
         if (reorth) {
+            // classical Gram-Schmidt against v_0 .. v_j, FP64 coefficients; the
+            // second pass runs only where the first removed more than half of |w|^2
             const int kk = j + 1;
-            for (int pass = 0; pass < 2; ++pass) {
-                double *rp = rparts.as<double>();
+            double *rp = rparts.as<double>();
+            auto pass = [&](const int *skip) -> int {
                 if (single) {
                     const float *Vf = (const float *)vec(0);
                     float *wf = (float *)w;
                     if (C == 1) {
                         hipLaunchKernelGGL((k_reorth_dots<float, 1>), dim3(rgrid), dim3(RB), 0, st,
-                                           Vf, ld, kk, wf, nsc, rp);
+                                           Vf, ld, kk, wf, nsc, rp, skip);
                         hipLaunchKernelGGL(k_reorth_finalize<1>, dim3(kk), dim3(RB), 0, st, rp,
-                                           rgrid, coef);
+                                           rgrid, coef, skip);
                         hipLaunchKernelGGL((k_reorth_sub<float, 1>), dim3(rgrid), dim3(RB), 0, st,
-                                           Vf, ld, kk, coef, wf, nsc);
+                                           Vf, ld, kk, coef, wf, nsc, skip);
                     } else {
                         hipLaunchKernelGGL((k_reorth_dots<float, 2>), dim3(rgrid), dim3(RB), 0, st,
-                                           Vf, ld, kk, wf, nsc, rp);
+                                           Vf, ld, kk, wf, nsc, rp, skip);
                         hipLaunchKernelGGL(k_reorth_finalize<2>, dim3(2 * kk), dim3(RB), 0, st,
-                                           rp, rgrid, coef);
+                                           rp, rgrid, coef, skip);
                         hipLaunchKernelGGL((k_reorth_sub<float, 2>), dim3(rgrid), dim3(RB), 0, st,
-                                           Vf, ld, kk, coef, wf, nsc);
+                                           Vf, ld, kk, coef, wf, nsc, skip);
                     }
                 } else {
                     const double *Vd = (const double *)vec(0);
                     double *wd = (double *)w;
                     if (C == 1) {
                         hipLaunchKernelGGL((k_reorth_dots<double, 1>), dim3(rgrid), dim3(RB), 0,
-                                           st, Vd, ld, kk, wd, nsc, rp);
+                                           st, Vd, ld, kk, wd, nsc, rp, skip);
                         hipLaunchKernelGGL(k_reorth_finalize<1>, dim3(kk), dim3(RB), 0, st, rp,
-                                           rgrid, coef);
+                                           rgrid, coef, skip);
                         hipLaunchKernelGGL((k_reorth_sub<double, 1>), dim3(rgrid), dim3(RB), 0,
-                                           st, Vd, ld, kk, coef, wd, nsc);
+                                           st, Vd, ld, kk, coef, wd, nsc, skip);
                     } else {
                         hipLaunchKernelGGL((k_reorth_dots<double, 2>), dim3(rgrid), dim3(RB), 0,
-                                           st, Vd, ld, kk, wd, nsc, rp);
+                                           st, Vd, ld, kk, wd, nsc, rp, skip);
                         hipLaunchKernelGGL(k_reorth_finalize<2>, dim3(2 * kk), dim3(RB), 0, st,
-                                           rp, rgrid, coef);
+                                           rp, rgrid, coef, skip);
                         hipLaunchKernelGGL((k_reorth_sub<double, 2>), dim3(rgrid), dim3(RB), 0,
-                                           st, Vd, ld, kk, coef, wd, nsc);
+                                           st, Vd, ld, kk, coef, wd, nsc, skip);
                     }
                 }
                 XDG_TRY_HIP(hipGetLastError());
-            }
+                return XDG_OK;
+            };
+            XDG_RETURN_IF(ops.finalize(0, nrm0, nullptr, jdev));   // |w|^2 from the update
+            XDG_RETURN_IF(pass(nullptr));
+            XDG_RETURN_IF(ops.dot(w, w));
+            XDG_RETURN_IF(ops.finalize(0, nrm1, nullptr, jdev));
+            hipLaunchKernelGGL(k_dgks, dim3(1), dim3(64), 0, st, nrm0, nrm1, skip2);
+            XDG_TRY_HIP(hipGetLastError());
+            XDG_RETURN_IF(pass(skip2));
             XDG_RETURN_IF(ops.dot(w, w));
         }
         XDG_RETURN_IF(ops.finalize(1, cur_beta, hist_b, jdev));
