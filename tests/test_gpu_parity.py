@@ -28,6 +28,15 @@ TOL64 = 1e-12
 TOL32 = 2e-6
 
 
+def c4_complex_model(n_up=None):
+    """20-site tilted torus, translations x C4 rotations, characters i^r:
+    four blocks of five sites (the packed sublattice search) with complex
+    characters."""
+    m = W.torus_model((4, 2), (-2, 4), 1.0, 0.0, None, n_up=n_up)
+    perm, labels = W.Torus((4, 2), (-2, 4)).symmetry_group(True, False)
+    return m.with_sector(perm, W.gamma_characters(labels, 1j, 1.0), "tilted20_C4_i")
+
+
 def sector_models():
     out = [W.chain_model(12), W.chain_model(20), W.chain_model(17, n_up=6)]   # U(1)
     out += [W.chain_model(12, l=l) for l in range(12)]                          # affine, real+complex
@@ -44,6 +53,7 @@ def sector_models():
             for n in (10, 7)]
     out += [W.torus_model((6, 0), (0, 4), 1.0, 0.3, "A1", rotations=False, name="rect24")]
     out += [W.torus_model((6, 0), (0, 4), 1.0, 0.3, "B1", rotations=False, name="rect24b")]
+    out += [c4_complex_model(n) for n in (10, 8)]
     # 64-bit state words: the benchmark lattices at low filling, long rings
     out += [W.torus_model((6, 0), (0, 6), 1.0, 0.5, ir, n_up=n, name="square36")
             for ir, n in (("A1", 3), ("A1", 5), ("B2", 5))]
@@ -350,6 +360,7 @@ SHAPE_CASES = [
     (W.torus_model((4, 2), (-2, 4), 1.0, 0.0, "A1", reflections=False, n_up=8),
      0),                                                               # 4 blocks of 5 sites
     (W.torus_model((6, 0), (0, 4), 1.0, 0.3, "B1", rotations=False, name="rect24b"), 0),
+    (c4_complex_model(9), 0),                                          # packed, complex chi
 ]
 
 
