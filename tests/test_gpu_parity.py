@@ -54,6 +54,9 @@ def sector_models():
     out += [W.torus_model((6, 0), (0, 4), 1.0, 0.3, "A1", rotations=False, name="rect24")]
     out += [W.torus_model((6, 0), (0, 4), 1.0, 0.3, "B1", rotations=False, name="rect24b")]
     out += [c4_complex_model(n) for n in (10, 8)]
+    # four blocks of eight sites (half tables of 16 entries)
+    out += [W.torus_model((8, 0), (0, 4), 1.0, 0.3, ir, rotations=False, n_up=n, name="rect32")
+            for ir, n in (("A1", 6), ("B2", 7))]
     # 64-bit state words: the benchmark lattices at low filling, long rings
     out += [W.torus_model((6, 0), (0, 6), 1.0, 0.5, ir, n_up=n, name="square36")
             for ir, n in (("A1", 3), ("A1", 5), ("B2", 5))]
@@ -361,6 +364,8 @@ SHAPE_CASES = [
      0),                                                               # 4 blocks of 5 sites
     (W.torus_model((6, 0), (0, 4), 1.0, 0.3, "B1", rotations=False, name="rect24b"), 0),
     (c4_complex_model(9), 0),                                          # packed, complex chi
+    (W.torus_model((8, 0), (0, 4), 1.0, 0.3, "B2", rotations=False, n_up=5, name="rect32"),
+     0),                                                               # packed, 8-site blocks
 ]
 
 
