@@ -332,7 +332,9 @@ class Ctx:
 def run_standard(c: Ctx, prec_fast, prec_ref, step_name, extra_ref=None):
     """Per-sector single-vector Lanczos runs of K iterations in two precision
     forms (K = the E0 iteration count by default, so the timed runs are the
-    energy runs); a third form (extra_ref) is run for its energy only."""
+    energy runs); a third form (extra_ref: FP64 with the same
+    reorthogonalisation as the fast form) is timed the same way and reported
+    beside them with its energy."""
     X, a = c.X, c.args
     res = {}
 
@@ -347,6 +349,10 @@ def run_standard(c: Ctx, prec_fast, prec_ref, step_name, extra_ref=None):
     log(f"timed {a.steps} steps (fast form): {el_fast:.3f}s")
     el_ref = c.timed(steps(prec_ref))
     log(f"timed {a.steps} steps (reference form): {el_ref:.3f}s")
+    el_x = None
+    if extra_ref is not None:
+        el_x = c.timed(steps(extra_ref))
+        log(f"timed {a.steps} steps (FP64 form with reorthogonalisation): {el_x:.3f}s")
     nnz_step = sum(c.nnzs)
 
     def e0(prec):
@@ -367,6 +373,9 @@ def run_standard(c: Ctx, prec_fast, prec_ref, step_name, extra_ref=None):
     }
     if extra_ref is not None:
         out["e0"]["reference_reorth"] = e0(extra_ref)
+        out["reference_reorth_form"] = {"value": nnz_step * a.steps / el_x, "unit": "nonzeros/s",
+                                        "ms_per_step": 1e3 * el_x / a.steps,
+                                        "lanczos_iters_per_s": len(c.hams) * a.steps / el_x}
     return out
 
 
@@ -582,6 +591,8 @@ def main():
                    "step": r["step"]},
         "lanczos_iters_per_s": r["lanczos_iters_per_s"],
         "reference_form": r["reference_form"],
+        **({"reference_reorth_form": r["reference_reorth_form"]}
+           if "reference_reorth_form" in r else {}),
         "e0": r["e0"],
         "basis_build_s": c.t_build,
         "roofline": roof,
