@@ -282,7 +282,9 @@ class Ctx:
     def apply_roofline(self, nvec=1, reps=20, batched=False):
         """Average duration of one launch of the dominant kernel (the apply of
         the first sector, or the batched apply over every sector), timed with
-        HIP events on the stream it is launched on, and its algorithmic bytes."""
+        HIP events on the stream it is launched on after three warm-up
+        launches (an event between consecutive launches also gives the median
+        launch), and its algorithmic bytes."""
         torch, X = self.torch, self.X
         vdt = torch.complex64 if self.cplx else torch.float32
         idx = range(len(self.hams)) if batched else [0]
@@ -298,16 +300,18 @@ class Ctx:
                 X.xdg_apply_batched([h.handle for h in hs], xs, ys, stream=st)
             else:
                 hs[0].apply(xs[0], ys[0], stream=st)
-        launch()
+        for _ in range(3):
+            launch()
         torch.cuda.synchronize()
         st = torch.cuda.current_stream()
-        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-        e0.record(st)
-        for _ in range(reps):
+        ev = [torch.cuda.Event(enable_timing=True) for _ in range(reps + 1)]
+        ev[0].record(st)
+        for r in range(reps):
             launch(st)
-        e1.record(st)
-        e1.synchronize()
-        sec = e0.elapsed_time(e1) * 1e-3 / reps
+            ev[r + 1].record(st)
+        ev[-1].synchronize()
+        sec = ev[0].elapsed_time(ev[-1]) * 1e-3 / reps
+        med_ms = sorted(ev[r].elapsed_time(ev[r + 1]) for r in range(reps))[reps // 2]
         del xs, ys
         vb = 8 if self.cplx else 4
         alg = 0
@@ -323,7 +327,8 @@ class Ctx:
                 else f"k_apply, sector {self.models[0].name}")
         roof.update({"kernel": f"{what} ({'complex ' if self.cplx else ''}FP32 vectors, "
                                f"{nvec} per sector)",
-                     "avg_launch_ms": sec * 1e3, "alg_bytes_per_launch": alg,
+                     "avg_launch_ms": sec * 1e3, "median_launch_ms": med_ms,
+                     "alg_bytes_per_launch": alg,
                      "nnz_per_launch": sum(self.nnzs[i] for i in idx) * nvec,
                      "source_hash": khash})
         return roof
