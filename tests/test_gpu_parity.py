@@ -333,6 +333,9 @@ def test_empty_and_degenerate_blocks(X):
     H = X.Hamiltonian.from_model(b, m)
     e = torch.empty(0, dtype=torch.complex128, device="cuda")
     H.apply(e, torch.empty(0, dtype=torch.complex128, device="cuda"))
+    # no thermal sequence on an empty block
+    with pytest.raises(X.XdgError):
+        H.tpq(1.0, 3)
 
 
 def test_apply_argument_errors(X):
