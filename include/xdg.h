@@ -359,6 +359,18 @@ int xdg_ftlm_thermo(int n_rec, int m, const double *alpha, const double *beta,
 int xdg_tpq_micro(xdg_ham h, const void *v0, uint64_t seed, int prec, double l, int n_steps,
                   double *u, double *u2, void *stream);
 
+/* xdg_tpq_micro for n blocks x nvec start vectors in lockstep: one batched
+ * H x per step over every block (the persistent launch of
+ * xdg_apply_batched), per-vector FP64 products, one captured step replayed
+ * n_steps times.  Start blocks v0s[i]: device [dim_i][nvec] (complex if any
+ * block is), normalised per vector by the call; v0s NULL: the seeded
+ * Gaussian block of seed + i for block i.  nvec in {1, 2, 4, 8}; prec
+ * XDG_PREC_F64 or XDG_PREC_F32VEC.  u, u2: host double[n][nvec][n_steps].
+ * Synchronises `stream` (or a stream of its own when NULL) at the end. */
+int xdg_tpq_micro_batched(int n, const xdg_ham *hams, const void *const *v0s, int64_t nvec,
+                          uint64_t seed, int prec, double l, int n_steps, double *u, double *u2,
+                          void *stream);
+
 /* Canonical TPQ thermodynamics from n_rec microcanonical sequences of
  * n_steps (Sec. 4.6; Sugiura and Shimizu 2013): with h = H/N, the moments
  * M_n = <0|(l - h)^n|0> for n <= 2 n_steps follow from u and u2

@@ -487,6 +487,19 @@ int xdg_tpq_micro(xdg_ham h, const void *v0, uint64_t seed, int prec, double l, 
     });
 }
 
+int xdg_tpq_micro_batched(int n, const xdg_ham *hams, const void *const *v0s, int64_t nvec,
+                          uint64_t seed, int prec, double l, int n_steps, double *u, double *u2,
+                          void *stream) {
+    return guarded([&]() -> int {
+        if (n < 1 || !hams) {
+            set_error("batched tpq: need n >= 1 Hamiltonians");
+            return XDG_EINVAL;
+        }
+        return tpq_micro_batched(n, hams, v0s, nvec, seed, prec, l, n_steps, u, u2,
+                                 (hipStream_t)stream);
+    });
+}
+
 int xdg_tpq_thermo(int n_rec, int n_steps, const double *u, const double *u2, double l,
                    int n_sites, const double *weight, int n_temp, const double *temps,
                    double *energy, double *heat, double *log_z) {

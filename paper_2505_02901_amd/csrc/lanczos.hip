@@ -1259,6 +1259,158 @@ int tpq_micro(xdg_ham_s *h, const void *v0, uint64_t seed, int prec, double l, i
     return XDG_OK;
 }
 
+// The same sequence for n blocks x nvec start vectors in lockstep: one
+// batched H x per step over every block (the persistent launch), per-column
+// FP64 products and updates; one captured step replayed n_steps times.
+int tpq_micro_batched(int n, xdg_ham_s *const *hams, const void *const *v0s, int64_t nvec,
+                      uint64_t seed, int prec, double l, int n_steps, double *u, double *u2,
+                      hipStream_t user_st) {
+    if (n < 1 || n_steps < 1 || !u || !u2 || !std::isfinite(l)) {
+        set_error("batched tpq: need n >= 1, n_steps >= 1, output arrays and a finite l");
+        return XDG_EINVAL;
+    }
+    if (nvec != 1 && nvec != 2 && nvec != 4 && nvec != 8) {
+        set_error("batched tpq: nvec must be 1, 2, 4 or 8");
+        return XDG_EINVAL;
+    }
+    if (prec != XDG_PREC_F64 && prec != XDG_PREC_F32VEC) {
+        set_error("batched tpq: precision form %d (XDG_PREC_F64 or XDG_PREC_F32VEC)", prec);
+        return XDG_EINVAL;
+    }
+    bool any_c = false;
+    for (int i = 0; i < n; ++i) {
+        if (!hams[i] || hams[i]->basis->dim < 1) {
+            set_error("batched tpq: block %d is null or empty", i);
+            return XDG_EINVAL;
+        }
+        any_c |= hams[i]->basis->is_complex;
+    }
+    const bool single = prec == XDG_PREC_F32VEC;
+    const int C = any_c ? 2 : 1;
+    const int dtype = any_c ? (single ? XDG_C64 : XDG_C128) : (single ? XDG_F32 : XDG_F64);
+    const size_t ssz = single ? 4 : 8;
+    const int cols = (int)nvec * C;
+
+    hipStream_t st = user_st;
+    hipStream_t own = nullptr;
+    if (!st) {
+        XDG_TRY_HIP(hipStreamCreateWithFlags(&own, hipStreamNonBlocking));
+        st = own;
+    }
+    struct OwnStream {
+        hipStream_t s;
+        ~OwnStream() {
+            if (s) (void)hipStreamDestroy(s);
+        }
+    } own_guard{own};
+    struct Sec {
+        DevBuf buf, parts, scal;
+        uint64_t nsc;
+        size_t slot;
+        VecOps ops;
+        double *ln, *nrm, *vw, *ww, *h_vw, *h_ww;
+    };
+    std::vector<Sec> S(n);
+    DevBuf jbuf;
+    XDG_RETURN_IF(jbuf.alloc(16));
+    int *jdev = jbuf.as<int>();
+    for (int i = 0; i < n; ++i) {
+        Sec &s = S[i];
+        const int64_t D = hams[i]->basis->dim;
+        s.nsc = (uint64_t)D * cols;
+        s.slot = (ssz * s.nsc + 255) & ~(size_t)255;
+        XDG_RETURN_IF(s.buf.alloc(s.slot * 2));   // v, w
+        s.ops = VecOps{single, cols, C, s.nsc, vec_grid(s.nsc), nullptr, st};
+        XDG_RETURN_IF(s.parts.alloc(sizeof(double) * (size_t)s.ops.grid * MAXC));
+        s.ops.partials = s.parts.as<double>();
+        // per vector: l N, norm, <v, Hv>, <Hv, Hv>; then the two histories
+        XDG_RETURN_IF(s.scal.alloc(sizeof(double) * (4 * (size_t)nvec + 2 * (size_t)n_steps * nvec)));
+        s.ln = s.scal.as<double>();
+        s.nrm = s.ln + nvec;
+        s.vw = s.nrm + nvec;
+        s.ww = s.vw + nvec;
+        s.h_vw = s.ww + nvec;
+        s.h_ww = s.h_vw + (size_t)n_steps * nvec;
+        const std::vector<double> lnv(nvec, l * (double)hams[i]->basis->n_sites);
+        XDG_TRY_HIP(hipMemcpyAsync(s.ln, lnv.data(), sizeof(double) * nvec, hipMemcpyHostToDevice,
+                                   st));
+        char *v = s.buf.as<char>();
+        if (v0s && v0s[i])
+            XDG_TRY_HIP(hipMemcpyAsync(v, v0s[i], ssz * s.nsc, hipMemcpyDeviceToDevice, st));
+        else
+            XDG_RETURN_IF(random_fill((int64_t)s.nsc, seed + (uint64_t)i, 1, single, v, st));
+        XDG_RETURN_IF(s.ops.dot(v, v));
+        XDG_RETURN_IF(s.ops.finalize(1, s.nrm, nullptr, jdev));
+        XDG_RETURN_IF(s.ops.scale(v, v, s.nrm));
+    }
+    hipLaunchKernelGGL(k_set_scalars, dim3(1), dim3(64), 0, st, jdev, S[0].nrm, 0);
+    XDG_TRY_HIP(hipGetLastError());
+    std::vector<xdg_ham_s *> hv(hams, hams + n);
+    std::vector<const void *> xs(n);
+    std::vector<void *> ys(n);
+    for (int i = 0; i < n; ++i) {
+        xs[i] = S[i].buf.as<char>();
+        ys[i] = S[i].buf.as<char>() + S[i].slot;
+    }
+    BatchShape shape;
+    XDG_RETURN_IF(batch_shape_tuned(n, hv.data(), xs.data(), ys.data(), nvec, dtype, st, &shape));
+    BatchPlan plan;
+    XDG_RETURN_IF(batch_prepare(n, hv.data(), xs.data(), ys.data(), nvec, dtype, &plan, shape.tile));
+    auto step = [&]() -> int {
+        XDG_RETURN_IF(batch_launch(plan, shape.grid, shape.nv, st));
+        for (int i = 0; i < n; ++i) {
+            Sec &s = S[i];
+            char *v = s.buf.as<char>(), *w = v + s.slot;
+            XDG_RETURN_IF(s.ops.dot(v, w));
+            XDG_RETURN_IF(s.ops.finalize(0, s.vw, s.h_vw, jdev));
+            XDG_RETURN_IF(s.ops.dot(w, w));
+            XDG_RETURN_IF(s.ops.finalize(0, s.ww, s.h_ww, jdev));
+            XDG_RETURN_IF(s.ops.update(w, v, nullptr, s.ln, nullptr));   // H v - l N v
+            XDG_RETURN_IF(s.ops.finalize(1, s.nrm, nullptr, jdev));
+            XDG_RETURN_IF(s.ops.scale(w, v, s.nrm));
+        }
+        hipLaunchKernelGGL(k_step_end, dim3(1), dim3(64), 0, st, jdev, S[0].nrm, S[0].nrm, 0);
+        XDG_TRY_HIP(hipGetLastError());
+        return XDG_OK;
+    };
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    int rc = XDG_OK;
+    XDG_TRY_HIP(hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal));
+    rc = step();
+    hipError_t e = hipStreamEndCapture(st, &graph);
+    if (rc == XDG_OK && e != hipSuccess) {
+        set_error("graph capture failed: %s", hipGetErrorString(e));
+        rc = XDG_EHIP;
+    }
+    if (rc == XDG_OK && hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0) != hipSuccess) {
+        set_error("graph instantiation failed");
+        rc = XDG_EHIP;
+    }
+    for (int k = 0; k < n_steps && rc == XDG_OK; ++k) {
+        if (hipGraphLaunch(exec, st) != hipSuccess) {
+            set_error("graph launch failed");
+            rc = XDG_EHIP;
+        }
+    }
+    if (exec) (void)hipGraphExecDestroy(exec);
+    if (graph) (void)hipGraphDestroy(graph);
+    if (rc == XDG_OK) {
+        std::vector<double> hv_((size_t)n_steps * nvec), hw_((size_t)n_steps * nvec);
+        for (int i = 0; i < n && rc == XDG_OK; ++i) {
+            rc = copy_d2h(hv_.data(), S[i].h_vw, sizeof(double) * hv_.size(), st);
+            if (rc == XDG_OK) rc = copy_d2h(hw_.data(), S[i].h_ww, sizeof(double) * hw_.size(), st);
+            const double N = (double)hams[i]->basis->n_sites;
+            for (int v = 0; v < nvec && rc == XDG_OK; ++v)
+                for (int k = 0; k < n_steps; ++k) {
+                    u[((size_t)i * nvec + v) * n_steps + k] = hv_[(size_t)k * nvec + v] / N;
+                    u2[((size_t)i * nvec + v) * n_steps + k] = hw_[(size_t)k * nvec + v] / (N * N);
+                }
+        }
+    }
+    return rc;
+}
+
 int last_timing(double *total, double *apply) {
     if (total) *total = g_t_total;
     if (apply) *apply = g_t_apply;

@@ -306,6 +306,9 @@ int lanczos_batched(int n, xdg_ham_s *const *hams, const void *const *v0s, int64
                     double *beta, hipStream_t st, double *t_total, double *t_apply);
 int tpq_micro(xdg_ham_s *h, const void *v0, uint64_t seed, int prec, double l, int n_steps,
               double *u, double *u2, hipStream_t st);
+int tpq_micro_batched(int n, xdg_ham_s *const *hams, const void *const *v0s, int64_t nvec,
+                      uint64_t seed, int prec, double l, int n_steps, double *u, double *u2,
+                      hipStream_t st);
 int tpq_thermo(int n_rec, int n_steps, const double *u, const double *u2, double l, int n_sites,
                const double *weight, int n_temp, const double *temps, double *energy,
                double *heat, double *log_z);

@@ -93,6 +93,7 @@ def lib():
             "xdg_expect_szsz": (I, [P, P, I, I, P, P, P]),
             "xdg_ftlm_thermo": (I, [I, I, P, P, P, I, P, P, P, P]),
             "xdg_tpq_micro": (I, [P, P, U64, I, D, I, P, P, P]),
+            "xdg_tpq_micro_batched": (I, [I, P, P, I64, U64, I, D, I, P, P, P]),
             "xdg_tpq_thermo": (I, [I, I, P, P, D, I, P, I, P, P, P, P]),
             "xdg_apply_sz_transfer": (I, [P, P, P, P, P, I, P]),
             "xdg_spectral_cf": (I, [I, P, P, D, D, I, P, D, P]),
@@ -117,7 +118,8 @@ def exported_names():
             "xdg_apply_tuned_config",
             "xdg_random_state", "xdg_lanczos_eigval", "xdg_lanczos_eigval_batched",
             "xdg_last_lanczos_timing", "xdg_lanczos_eigvec", "xdg_expect_szsz",
-            "xdg_ftlm_thermo", "xdg_tpq_micro", "xdg_tpq_thermo", "xdg_apply_sz_transfer",
+            "xdg_ftlm_thermo", "xdg_tpq_micro", "xdg_tpq_micro_batched", "xdg_tpq_thermo",
+            "xdg_apply_sz_transfer",
             "xdg_spectral_cf"]
 
 
@@ -540,6 +542,28 @@ def xdg_tpq_micro(h, l: float, n_steps: int, seed: int = 0, prec: int = XDG_PREC
                                u.ctypes.data_as(C.c_void_p), u2.ctypes.data_as(C.c_void_p),
                                _stream(stream)))
     return u, u2
+
+
+def xdg_tpq_micro_batched(hams: Sequence, l: float, n_steps: int, nvec: int, seed: int = 0,
+                          prec: int = XDG_PREC_F32VEC, v0s=None, stream=None):
+    """(u, u2) [n, nvec, n_steps] of TPQ sequences for every block and start
+    vector in lockstep (one batched H x per step)."""
+    n = len(hams)
+    if v0s is not None:
+        if len(v0s) != n:
+            raise ValueError("one start block per Hamiltonian")
+        info = [xdg_ham_dim(h) for h in hams]
+        dt = _prec_dtype(prec, any(c for _, c in info))
+        for i, (dim, _) in enumerate(info):
+            _check_vec(f"v0s[{i}]", v0s[i], dim, nvec, dt)
+    u = np.zeros(n * nvec * n_steps, np.float64)
+    u2 = np.zeros(n * nvec * n_steps, np.float64)
+    H = (C.c_void_p * n)(*[h.value if isinstance(h, C.c_void_p) else h for h in hams])
+    V = None if v0s is None else (C.c_void_p * n)(*[_ptr(v) for v in v0s])
+    _check(lib().xdg_tpq_micro_batched(n, H, V, nvec, seed, prec, l, n_steps,
+                                       u.ctypes.data_as(C.c_void_p),
+                                       u2.ctypes.data_as(C.c_void_p), _stream(stream)))
+    return u.reshape(n, nvec, n_steps), u2.reshape(n, nvec, n_steps)
 
 
 def xdg_tpq_thermo(u, u2, l: float, n_sites: int, weight, temps):

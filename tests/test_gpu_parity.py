@@ -735,6 +735,48 @@ def test_tpq_micro_matches_oracle(X, mi):
         X.xdg_tpq_micro(H.handle, l, 5, prec=X.XDG_PREC_F64_REORTH)
 
 
+def test_tpq_micro_batched_matches_single(X):
+    """Batched TPQ (four ring momenta, real and complex blocks, four start
+    vectors each, one batched H x per step) against the oracle's recursion
+    per start vector (1e-10 FP64 vectors, 2e-5 FP32) and against the
+    one-vector call from the same start vector (1e-12 FP64); a seeded run
+    cools every sequence from the middle of the band."""
+    ms = [W.chain_model(12, l=l) for l in (0, 3, 6, 5)]
+    bs = [X.Basis.from_model(m) for m in ms]
+    hs = [X.Hamiltonian.from_model(b, m) for b, m in zip(bs, ms)]
+    nv, l, K = 4, 1.0, 40
+    x0s = []
+    for i, (m, b) in enumerate(zip(ms, bs)):
+        x = W.random_vector(200 + i, b.dim, nv, complex_=m.is_complex)
+        x0s.append(x.astype(np.complex128))
+    forms = ((X.XDG_PREC_F64, torch.complex128, torch.float64, 1e-10),
+             (X.XDG_PREC_F32VEC, torch.complex64, torch.float32, 2e-5))
+    for prec, dt, rdt, tol in forms:
+        v0s = [torch.from_numpy(x).to("cuda", dt) for x in x0s]
+        u, u2 = X.xdg_tpq_micro_batched([h.handle for h in hs], l, K, nv, prec=prec, v0s=v0s)
+        assert u.shape == (len(ms), nv, K)
+        for i, m in enumerate(ms):
+            basis = oracle_basis(m)
+            for v in range(nv):
+                uo, u2o = oracle.tpq_micro(m, basis, x0s[i][:, v], l, K)
+                assert np.max(np.abs(u[i, v] - uo)) <= tol * np.max(np.abs(uo)), (prec, i, v)
+                assert np.max(np.abs(u2[i, v] - u2o)) <= tol * np.max(np.abs(u2o)), (prec, i, v)
+                if prec == X.XDG_PREC_F64:
+                    col = x0s[i][:, v] if m.is_complex else x0s[i][:, v].real
+                    v0 = torch.from_numpy(np.ascontiguousarray(col)).to(
+                        "cuda", dt if m.is_complex else rdt)
+                    us, u2s = X.xdg_tpq_micro(hs[i].handle, l, K, prec=prec, v0=v0)
+                    assert np.max(np.abs(u[i, v] - us)) <= 1e-12 * np.max(np.abs(us)), (i, v)
+                    assert np.max(np.abs(u2[i, v] - u2s)) <= 1e-12 * np.max(np.abs(u2s)), (i, v)
+    u, u2 = X.xdg_tpq_micro_batched([h.handle for h in hs], l, 30, 2, seed=8)
+    assert np.all(np.abs(u[:, :, 0]) < 0.15) and np.all(u[:, :, -1] < u[:, :, 0])
+    assert np.all(u2 >= u ** 2 - 1e-6)
+    with pytest.raises(X.XdgError):
+        X.xdg_tpq_micro_batched([h.handle for h in hs], l, 5, 3)
+    with pytest.raises(X.XdgError):
+        X.xdg_tpq_micro_batched([h.handle for h in hs], l, 0, 2)
+
+
 
 @pytest.mark.parametrize("lq", [3, 6])
 def test_dynamical_structure_factor_matches_dense(X, lq):
