@@ -232,7 +232,17 @@ typedef struct xdg_launch_cfg {
     int sub_form;      /* sublattice coding: 0 = automatic (the packed form wherever it
                           applies: four blocks of at most 10 sites, tables in LDS), 2 = the
                           block-by-block form (comparisons); both give bitwise the same y */
-    int reserved[3];   /* must be zero */
+    int xr;            /* sublattice coding with a rank index: 1 = the terms read x from a
+                          rank-addressed copy (slot = rank of the representative among the
+                          states whose top block is a minimal top; zeros where the
+                          representative is not a basis state), filled by a scatter before
+                          the launch: one random read per term instead of an index word and
+                          x.  The copy is device memory held by the Hamiltonian (slots x the
+                          row's bytes; XDG_ENOMEM when it does not fit), set up by a first call
+                          outside graph capture; calls on other streams wait for the last
+                          launch that read it.  0 = through the rank index.  Elsewhere
+                          ignored.  Both give the same y (up to the sign of zero sums) */
+    int reserved[2];   /* must be zero */
 } xdg_launch_cfg;
 
 /* xdg_apply in a given launch shape (tuning and tests: every shape computes

@@ -147,6 +147,88 @@ int form_of(const xdg_basis_s *b, int dtype, int64_t nvec, Form *f) {
     return XDG_OK;
 }
 
+// Rank-addressed x: row i of x goes to slot top_rank(reps[i]) of xr (spr
+// scalars per row); the other slots hold zeros.
+template <class W, class T>
+__global__ __launch_bounds__(256) void k_xr_scatter(const W *reps, int64_t dim, int spr,
+                                                   const T *x, T *xr, const void *rtab,
+                                                   RankLayout L, int B, const uint64_t *top,
+                                                   uint64_t slots) {
+    const int64_t stride = (int64_t)gridDim.x * 256;
+    for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < dim; i += stride) {
+        const uint64_t r = top_rank<W>(rtab, L, B, top, reps[i]);
+        if (r >= slots) continue;   // never for a basis state
+        for (int c = 0; c < spr; ++c) xr[r * spr + c] = x[i * spr + c];
+    }
+}
+
+__global__ __launch_bounds__(256) void k_zero32(uint32_t *p, uint64_t n) {
+    const uint64_t stride = (uint64_t)gridDim.x * 256;
+    for (uint64_t i = (uint64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += stride) p[i] = 0u;
+}
+
+// Fill the rank-addressed copy of x for this call (caller holds h->xr_mu):
+// wait for the last launch that read it, (re)allocate and zero it when the
+// layout changes (not under graph capture), then scatter x.
+int xr_prepare(xdg_ham_s *h, const void *x, const Form &f, hipStream_t st, bool *capturing) {
+    const xdg_basis_s *b = h->basis;
+    const int spr = (int)f.cols * (f.cplx_kernel ? 2 : 1);
+    const size_t tsz = f.single ? 4 : 8;
+    const size_t slot_bytes = (size_t)spr * tsz;
+    const size_t need = (size_t)b->xr_slots * slot_bytes;
+    hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+    XDG_TRY_HIP(hipStreamIsCapturing(st, &cs));
+    *capturing = cs != hipStreamCaptureStatusNone;
+    if (!h->xr_ev) XDG_TRY_HIP(hipEventCreateWithFlags(&h->xr_ev, hipEventDisableTiming));
+    if (!*capturing) XDG_TRY_HIP(hipStreamWaitEvent(st, h->xr_ev, 0));
+    const int gcap = device_cu_count() * 32;
+    if (h->xr_buf.bytes < need || h->xr_slot_bytes != slot_bytes) {
+        if (*capturing) {
+            set_error("the rank-addressed copy of x is set up by a first call outside graph capture");
+            return XDG_EINVAL;
+        }
+        if (h->xr_buf.bytes < need) {
+            h->xr_slot_bytes = 0;
+            h->xr_buf.release();   // waits for the device
+            XDG_RETURN_IF(h->xr_buf.alloc(need));
+        }
+        const uint64_t nw = need / 4;
+        const unsigned g = (unsigned)std::min<uint64_t>((nw + 255) / 256, (uint64_t)gcap);
+        hipLaunchKernelGGL(k_zero32, dim3(std::max(1u, g)), dim3(256), 0, st,
+                           h->xr_buf.as<uint32_t>(), nw);
+        XDG_TRY_HIP(hipGetLastError());
+        h->xr_slot_bytes = slot_bytes;
+    }
+    const unsigned g =
+        (unsigned)std::min<int64_t>((b->dim + 255) / 256, (int64_t)gcap);
+    const uint64_t *top = b->xr_top.as<uint64_t>();
+    if (b->wide) {
+        if (f.single)
+            hipLaunchKernelGGL((k_xr_scatter<uint64_t, float>), dim3(g), dim3(256), 0, st,
+                               b->reps.as<uint64_t>(), b->dim, spr, (const float *)x,
+                               h->xr_buf.as<float>(), b->rtab.p, b->rank, b->xr_bits, top,
+                               b->xr_slots);
+        else
+            hipLaunchKernelGGL((k_xr_scatter<uint64_t, double>), dim3(g), dim3(256), 0, st,
+                               b->reps.as<uint64_t>(), b->dim, spr, (const double *)x,
+                               h->xr_buf.as<double>(), b->rtab.p, b->rank, b->xr_bits, top,
+                               b->xr_slots);
+    } else {
+        if (f.single)
+            hipLaunchKernelGGL((k_xr_scatter<uint32_t, float>), dim3(g), dim3(256), 0, st,
+                               b->reps.as<uint32_t>(), b->dim, spr, (const float *)x,
+                               h->xr_buf.as<float>(), b->rtab.p, b->rank, b->xr_bits, top,
+                               b->xr_slots);
+        else
+            hipLaunchKernelGGL((k_xr_scatter<uint32_t, double>), dim3(g), dim3(256), 0, st,
+                               b->reps.as<uint32_t>(), b->dim, spr, (const double *)x,
+                               h->xr_buf.as<double>(), b->rtab.p, b->rank, b->xr_bits, top,
+                               b->xr_slots);
+    }
+    XDG_TRY_HIP(hipGetLastError());
+    return XDG_OK;
+}
+
 int pick_nv(int64_t remaining, int cap) {
     int nv = 8;
     while (nv > 1 && (nv > remaining || nv > cap)) nv >>= 1;
@@ -194,6 +276,30 @@ int apply_launch(xdg_ham_s *h, const void *x, void *y, int64_t nvec, int dtype, 
         A.one.subf = 0;
         A.one.bx = nullptr;
     }
+    // rank-addressed x: when its tables fit in LDS with the others
+    bool xr_on = c.xr && b->xr_slots && b->plan.kind == K_SUB, capturing = false;
+    if (xr_on) {
+        A.one.xr = b->xr_top.p;   // the copy is set below; non-null for the LDS size
+        A.one.xr_top = b->xr_top.as<uint64_t>();
+        A.one.xr_top32 = b->xr_top32.as<uint32_t>();
+        A.one.xr_slots = b->xr_slots;
+        A.one.xr_bits = b->xr_bits;
+        A.one.xr_rows = b->xr_rows;
+        const size_t lx = f.tsingle ? stage_bytes<float>(A.one, b->plan.kind, 1)
+                                    : stage_bytes<double>(A.one, b->plan.kind, 1);
+        if (lx > lds_budget()) {
+            xr_on = false;
+            A.one.xr = nullptr;
+            A.one.xr_top = nullptr;
+            A.one.xr_top32 = nullptr;
+        }
+    }
+    std::unique_lock<std::mutex> xr_lock;
+    if (xr_on) {
+        xr_lock = std::unique_lock<std::mutex>(h->xr_mu);
+        XDG_RETURN_IF(xr_prepare(h, x, f, st, &capturing));
+        A.one.xr = h->xr_buf.p;
+    }
     A.nvec = f.cols;
     size_t lds = f.tsingle ? stage_bytes<float>(A.one, b->plan.kind, 1)
                            : stage_bytes<double>(A.one, b->plan.kind, 1);
@@ -204,15 +310,20 @@ int apply_launch(xdg_ham_s *h, const void *x, void *y, int64_t nvec, int dtype, 
                         : stage_bytes<double>(A.one, b->plan.kind, 0);
     }
     A.occ = A.stage_sub ? (c.occ >= 0 ? (c.occ && occ_for(lds)) : occ_for(lds)) : 0;
-    A.compact = c.compact > 0 ? 1 : 0;
-    const int cap = c.nv > 0 ? c.nv : 8;
+    A.compact = c.compact > 0 && !xr_on ? 1 : 0;   // the compacted loop reads x itself
+    const int cap = std::min(c.nv > 0 ? c.nv : 8, xr_on ? 2 : 8);
     for (int64_t v0 = 0; v0 < f.cols;) {
         const int nv = pick_nv(f.cols - v0, cap);
         A.v0 = (int)v0;
-        XDG_RETURN_IF(launch_dispatch(b->plan.kind, b->wide, f.single, f.acc64, f.cplx_kernel, nv,
-                                      A, grid, block, lds, st));
+        if (xr_on)
+            XDG_RETURN_IF(launch_sub_xr(b->wide, f.single, f.acc64, f.cplx_kernel, nv, A, grid,
+                                        block, lds, st));
+        else
+            XDG_RETURN_IF(launch_dispatch(b->plan.kind, b->wide, f.single, f.acc64,
+                                          f.cplx_kernel, nv, A, grid, block, lds, st));
         v0 += nv;
     }
+    if (xr_on && !capturing) XDG_TRY_HIP(hipEventRecord(h->xr_ev, st));
     return XDG_OK;
 }
 
@@ -269,9 +380,9 @@ int apply_tuned(xdg_ham_s *h, const void *x, void *y, int64_t nvec, int dtype, h
             int stg = 0, occ_ok = 0;
             apply_lds(h, dtype, &lds, &stg, &occ_ok);
             fprintf(stderr, "[xdg tune] dim %lld dtype %d nvec %lld (LDS %zu B, tables staged %d, "
-                    "8-wave copy possible %d): grid %d nv %d occ %d compact %d: %.3f ms\n",
+                    "8-wave copy possible %d): grid %d nv %d occ %d compact %d xr %d: %.3f ms\n",
                     (long long)b->dim, dtype, (long long)nvec, lds, stg, occ_ok, c.grid, c.nv,
-                    c.occ, c.compact, *ms);
+                    c.occ, c.compact, c.xr, *ms);
         }
         return XDG_OK;
     };
@@ -306,9 +417,24 @@ int apply_tuned(xdg_ham_s *h, const void *x, void *y, int64_t nvec, int dtype, h
                 c.compact = cmp;
                 more.push_back(c);
             }
+        // sublattice coding: terms reading a rank-addressed copy of x
+        if (b->xr_slots && b->plan.kind == K_SUB)
+            for (int occ : {0, 1}) {
+                LaunchCfg c = bestc;
+                c.occ = occ;
+                c.compact = 0;
+                c.xr = 1;
+                more.push_back(c);
+            }
         for (const LaunchCfg &c : more) {
             float ms = 0;
-            if ((rc = time_cfg(c, &ms)) != XDG_OK) break;
+            if ((rc = time_cfg(c, &ms)) != XDG_OK) {
+                if (c.xr && rc == XDG_ENOMEM) {   // no room for the copy: not a candidate
+                    rc = XDG_OK;
+                    continue;
+                }
+                break;
+            }
             if (ms < best) {
                 best = ms;
                 bestc = c;
@@ -319,6 +445,13 @@ int apply_tuned(xdg_ham_s *h, const void *x, void *y, int64_t nvec, int dtype, h
     (void)hipEventDestroy(e1);
     XDG_RETURN_IF(rc);
     h->tuned[key] = bestc;
+    bool xr_used = false;
+    for (const auto &kv : h->tuned) xr_used |= kv.second.xr != 0;
+    if (!xr_used) {   // free the copy no tuned shape reads
+        std::lock_guard<std::mutex> g(h->xr_mu);
+        h->xr_slot_bytes = 0;
+        h->xr_buf.release();
+    }
     return apply_launch(h, x, y, nvec, dtype, st, &bestc);
 }
 

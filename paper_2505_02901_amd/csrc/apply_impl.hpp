@@ -79,6 +79,15 @@ struct SectorDesc {
     const void *sqrtt;           // T [2 (n_sym + 1)]: sqrt(c), then 1/sqrt(c)
     double jz_quarter;           // (1/4) sum_b Jz_b: the diagonal of the all-aligned state
     int ring_bonds;              // 1: n_bonds = n_sites and bond b joins sites b and b + 1 mod N
+    // rank-addressed x (sublattice coding): slot top_rank(s) of xr holds the
+    // row of representative s when s is a basis state, zeros otherwise, so a
+    // term reads x without the index lookup (null: through the rank index)
+    const void *xr;
+    const uint64_t *xr_top;      // [2^m] first rank of each top block, ~0 if none
+    const uint32_t *xr_top32;    // the same in 4 bytes (0xFFFFFFFF if none), when all fit; or null
+    uint64_t xr_slots;           // slots of xr (beyond the last one: not in the block)
+    int xr_bits;                 // sites below the top block
+    int xr_rows;                 // rows of the rank tables for the chunks below the top block
     const void *x;
     void *y;
 };
@@ -109,7 +118,15 @@ __host__ __device__ inline size_t sub_table_bytes(const SectorDesc &d) {
 }
 
 __host__ __device__ inline size_t rank_table_bytes(const SectorDesc &d) {
-    return d.rwords ? ((size_t)d.rl.rows << d.rl.cb) * (d.rl.e32 ? 4 : 8) : 0;
+    if (!d.rwords) return 0;
+    // the rank-addressed x reads only the rows of the chunks below the top block
+    const size_t rows = d.xr ? (size_t)d.xr_rows : (size_t)d.rl.rows;
+    return (rows << d.rl.cb) * (d.rl.e32 ? 4 : 8);
+}
+
+// bytes of the first-rank table of the rank-addressed x in LDS
+__host__ __device__ inline size_t xr_top_bytes(const SectorDesc &d) {
+    return ((size_t)1 << d.m) * (d.xr_top32 ? 4 : 8);
 }
 
 // LDS bytes needed to stage a sector's tables.
@@ -124,6 +141,7 @@ __host__ __device__ inline size_t stage_bytes(const SectorDesc &d, int kind, int
         if (kind == K_SUB && stage_sub) n += sub_table_bytes(d);
         // packed form: alignment of the permutation tables
         if (kind == K_SUB && stage_sub && d.subf) n += 128;
+        if (kind == K_SUB && stage_sub && d.xr) n += a16(xr_top_bytes(d));
     }
     return n;
 }
@@ -140,6 +158,8 @@ struct Staged {
     SubCtx sub;
     bool subf;             // packed sublattice search (sub.sp holds the packed entries)
     uint32_t amask;        // ~(4E - 1)
+    const uint64_t *xr_top;   // first rank of each top block (rank-addressed x)
+    const uint32_t *xr_top32; // the same in 4 bytes, or null
 };
 
 template <class E>
@@ -161,6 +181,8 @@ __device__ inline void stage(const SectorDesc &d, unsigned char *smem, Staged<T>
     S.bonds = stage_copy(smem, off, reinterpret_cast<const B *>(d.bonds), d.n_bonds);
     S.sub = SubCtx{d.mintop, d.cand_off, d.cand_list, d.sp, d.tperm, d.n_s, d.m, d.pb};
     S.subf = false;
+    S.xr_top = d.xr_top;
+    S.xr_top32 = d.xr_top32;
     if constexpr (KIND != K_U1) {
         S.chi = stage_copy(smem, off, reinterpret_cast<const T2 *>(d.chi), d.n_sym);
         const T *ls = stage_copy(smem, off, reinterpret_cast<const T *>(d.sqrtt), 2 * (d.n_sym + 1));
@@ -205,6 +227,12 @@ __device__ inline void stage(const SectorDesc &d, unsigned char *smem, Staged<T>
                     S.sub.sp = stage_copy(smem, off, d.sp, (size_t)d.n_sym * d.n_s);
                     S.sub.tperm = stage_copy(smem, off, d.tperm, ntp);
                 }
+                if (d.xr) {
+                    if (d.xr_top32)
+                        S.xr_top32 = stage_copy(smem, off, d.xr_top32, (size_t)1 << d.m);
+                    else
+                        S.xr_top = stage_copy(smem, off, d.xr_top, (size_t)1 << d.m);
+                }
             }
         }
     }
@@ -217,8 +245,9 @@ template <> struct IndexT<uint32_t> { using type = int32_t; };
 // Locate the representative of t and its index; returns -1 when the orbit
 // is not in the block.  On success writes u and |Stab(s)|.  key: t's key for
 // the packed sublattice search (computed here from t when null and that
-// search is on).
-template <class W, int KIND, class T>
+// search is on).  XR: the position is the slot in the rank-addressed x
+// (sublattice coding with d.xr set).
+template <class W, int KIND, class T, bool XR = false>
 __device__ __forceinline__ typename IndexT<W>::type locate(const SectorDesc &d, const Staged<T> &S,
                                                            W t, int &u, int &cnt,
                                                            const SubKey *key = nullptr) {
@@ -250,6 +279,13 @@ __device__ __forceinline__ typename IndexT<W>::type locate(const SectorDesc &d, 
         } else {
             tab_search<W>(d.bytetab, d.n_bchunks, d.n_sym, t, rep, u, cnt);
         }
+        if constexpr (KIND == K_SUB && XR) {
+            // the slot of rep in the rank-addressed x (zeros unless rep is a basis state)
+            const uint64_t r = S.xr_top32
+                                   ? top_rank32<W>(S.rtab, d.rl, d.xr_bits, S.xr_top32, rep)
+                                   : top_rank<W>(S.rtab, d.rl, d.xr_bits, S.xr_top, rep);
+            return r < d.xr_slots ? (I)r : (I)-1;
+        }
         if (d.rwords) {
             if constexpr (sizeof(W) == 4) {
                 const uint64_t r = colex_rank<W>(S.rtab, d.rl, rep);
@@ -271,7 +307,8 @@ __device__ __forceinline__ typename IndexT<W>::type locate(const SectorDesc &d, 
 
 // T: storage type of x and y; A: type of the amplitudes and of the per-row
 // accumulation (each output element is rounded to T once, at the store).
-template <class W, int KIND, class T, class A, bool CPLX, int NV>
+// XR: the terms read the rank-addressed x (sublattice coding, d.xr set).
+template <class W, int KIND, class T, class A, bool CPLX, int NV, bool XR = false>
 __device__ __forceinline__ void process_row(const SectorDesc &d, const Staged<A> &S, int64_t row,
                                             int64_t nvec, int v0) {
     using B = typename BondT<A>::type;
@@ -279,6 +316,8 @@ __device__ __forceinline__ void process_row(const SectorDesc &d, const Staged<A>
     const W s = gld(reinterpret_cast<const W *>(d.reps) + row);
     const T *X = reinterpret_cast<const T *>(d.x);
     T *Y = reinterpret_cast<T *>(d.y);
+    // the terms' x: rank-addressed (the same values at other places) or x itself
+    const T *XT = XR ? reinterpret_cast<const T *>(d.xr) : X;
     const int nb = d.n_bonds;
     // Diagonal: sum_b Jz_b (+1/4 if the spins of b are equal, -1/4 if not)
     // = (1/4) sum_b Jz_b - (1/2) sum over the unequal-spin bonds of Jz_b; the
@@ -292,7 +331,7 @@ __device__ __forceinline__ void process_row(const SectorDesc &d, const Staged<A>
     // key: the packed sublattice search's key of the term's state, if given
     auto term = [&](const B &bd, W t, const SubKey *key) {
         int u, cnt;
-        const auto idx = locate<W, KIND, A>(d, S, t, u, cnt, key);
+        const auto idx = locate<W, KIND, A, XR>(d, S, t, u, cnt, key);
         if (idx < 0) return;
         A ar = bd.h, ai = 0;
         if constexpr (KIND != K_U1) {
@@ -310,11 +349,11 @@ __device__ __forceinline__ void process_row(const SectorDesc &d, const Staged<A>
 #pragma unroll
         for (int v = 0; v < NV; ++v) {
             if constexpr (CPLX) {
-                const A xr = gld(X + xb + 2 * v), xi = gld(X + xb + 2 * v + 1);
+                const A xr = gld(XT + xb + 2 * v), xi = gld(XT + xb + 2 * v + 1);
                 acc[2 * v] = fmadd<A>(-ai, xi, fmadd<A>(ar, xr, acc[2 * v]));
                 acc[2 * v + 1] = fmadd<A>(ai, xr, fmadd<A>(ar, xi, acc[2 * v + 1]));
             } else {
-                acc[v] = fmadd<A>(ar, (A)gld(X + xb + v), acc[v]);
+                acc[v] = fmadd<A>(ar, (A)gld(XT + xb + v), acc[v]);
             }
         }
     };
@@ -551,8 +590,9 @@ __device__ __forceinline__ void process_window(const SectorDesc &d, const Staged
 
 // rows [r0, r1) of a sector.  CMP: windows of CMP_ROWS rows per wave (every
 // lane of a wave takes part in its permutes; `first` and `stride` count
-// lanes, so wave w of the launch starts at window w); otherwise a lane per row
-template <class W, int KIND, class T, class A, bool CPLX, int NV, bool CMP>
+// lanes, so wave w of the launch starts at window w); otherwise a lane per
+// row, reading the rank-addressed x when XR.
+template <class W, int KIND, class T, class A, bool CPLX, int NV, bool CMP, bool XR>
 __device__ __forceinline__ void process_range(const SectorDesc &d, const Staged<A> &S, int64_t r0,
                                               int64_t r1, int64_t first, int64_t stride,
                                               int64_t nvec, int v0) {
@@ -562,7 +602,7 @@ __device__ __forceinline__ void process_range(const SectorDesc &d, const Staged<
             process_window<W, KIND, T, A, CPLX, NV>(d, S, w0, r1, nvec, v0);
     } else {
         for (int64_t row = r0 + first; row < r1; row += stride)
-            process_row<W, KIND, T, A, CPLX, NV>(d, S, row, nvec, v0);
+            process_row<W, KIND, T, A, CPLX, NV, XR>(d, S, row, nvec, v0);
     }
 }
 
@@ -583,7 +623,7 @@ __device__ __forceinline__ uint32_t count_row(const SectorDesc &d, const Staged<
 }
 
 template <class W, int KIND, class T, class AC, bool CPLX, int NV, bool STAGE, bool OCC,
-          bool CMP>
+          bool CMP, bool XR>
 __global__ __launch_bounds__(APPLY_BLOCK, OCC ? OCC_WAVES : 1) void k_apply(ApplyArgs A) {
     extern __shared__ __align__(16) unsigned char smem[];
     __shared__ uint32_t s_tile;
@@ -594,7 +634,7 @@ __global__ __launch_bounds__(APPLY_BLOCK, OCC ? OCC_WAVES : 1) void k_apply(Appl
         stage<KIND, AC, STAGE>(d, smem, S);
         __syncthreads();
         const int64_t stride = (int64_t)gridDim.x * blockDim.x;
-        process_range<W, KIND, T, AC, CPLX, NV, CMP>(d, S, 0, d.dim,
+        process_range<W, KIND, T, AC, CPLX, NV, CMP, XR>(d, S, 0, d.dim,
                                                 (int64_t)blockIdx.x * blockDim.x + threadIdx.x,
                                                 stride, A.nvec, A.v0);
         return;
@@ -622,7 +662,7 @@ __global__ __launch_bounds__(APPLY_BLOCK, OCC ? OCC_WAVES : 1) void k_apply(Appl
         const int64_t r0 = (int64_t)(tile - A.tile_prefix[lo]) * A.tile_rows;
         int64_t r1 = r0 + A.tile_rows;
         r1 = r1 < d.dim ? r1 : d.dim;
-        process_range<W, KIND, T, AC, CPLX, NV, CMP>(d, S, r0, r1, threadIdx.x, blockDim.x,
+        process_range<W, KIND, T, AC, CPLX, NV, CMP, XR>(d, S, r0, r1, threadIdx.x, blockDim.x,
                                                      A.nvec, A.v0);
         __syncthreads();
     }
@@ -659,16 +699,23 @@ template <int KIND>
 int launch_count_kind(bool wide, const ApplyArgs &A, unsigned grid, unsigned block, size_t lds,
                       hipStream_t st);
 
-template <class W, int KIND, class T, class AC, bool CPLX, bool STAGE, bool OCC, bool CMP>
+// The sublattice kernels whose terms read the rank-addressed x (their own
+// translation unit).
+int launch_sub_xr(bool wide, bool single, bool acc64, bool cplx, int nv, const ApplyArgs &A,
+                  unsigned grid, unsigned block, size_t lds, hipStream_t st);
+
+// XR (the rank-addressed x): passes of at most two vectors.
+template <class W, int KIND, class T, class AC, bool CPLX, bool STAGE, bool OCC, bool CMP,
+          bool XR = false>
 void (*apply_kernel(int nv))(ApplyArgs) {
     switch (nv) {
-        case 1: return k_apply<W, KIND, T, AC, CPLX, 1, STAGE, OCC, CMP>;
-        case 2: return k_apply<W, KIND, T, AC, CPLX, 2, STAGE, OCC, CMP>;
+        case 1: return k_apply<W, KIND, T, AC, CPLX, 1, STAGE, OCC, CMP, XR>;
+        case 2: return k_apply<W, KIND, T, AC, CPLX, 2, STAGE, OCC, CMP, XR>;
     }
-    if constexpr (!CMP) {
+    if constexpr (!CMP && !XR) {
         switch (nv) {
-            case 4: return k_apply<W, KIND, T, AC, CPLX, 4, STAGE, OCC, false>;
-            case 8: return k_apply<W, KIND, T, AC, CPLX, 8, STAGE, OCC, false>;
+            case 4: return k_apply<W, KIND, T, AC, CPLX, 4, STAGE, OCC, false, false>;
+            case 8: return k_apply<W, KIND, T, AC, CPLX, 8, STAGE, OCC, false, false>;
         }
     }
     return nullptr;
@@ -686,7 +733,7 @@ void (*apply_kernel_loop(int nv, bool compact))(ApplyArgs) {
     return apply_kernel<W, KIND, T, AC, CPLX, STAGE, OCC, false>(nv);
 }
 
-template <class W, int KIND, class T, class AC, bool CPLX>
+template <class W, int KIND, class T, class AC, bool CPLX, bool XR>
 int launch_nv(int nv, const ApplyArgs &A, unsigned grid, unsigned block, size_t lds,
               hipStream_t st) {
     void (*f)(ApplyArgs) = nullptr;
@@ -695,13 +742,18 @@ int launch_nv(int nv, const ApplyArgs &A, unsigned grid, unsigned block, size_t 
     // scalars: with more it spills them (complex 8-vector passes: 200 bytes)
     const bool occ = A.occ && nv * (CPLX ? 2 : 1) <= 2;
     const bool cmp = A.compact != 0;
-    if (KIND != K_SUB || A.stage_sub)
+    if constexpr (XR) {   // row loop, tables in LDS
+        if (A.stage_sub)
+            f = occ ? apply_kernel<W, KIND, T, AC, CPLX, true, true, false, true>(nv)
+                    : apply_kernel<W, KIND, T, AC, CPLX, true, false, false, true>(nv);
+    } else if (KIND != K_SUB || A.stage_sub)
         f = occ ? apply_kernel_loop<W, KIND, T, AC, CPLX, true, true>(nv, cmp)
                 : apply_kernel_loop<W, KIND, T, AC, CPLX, true, false>(nv, cmp);
     else if constexpr (KIND == K_SUB)
         f = apply_kernel_loop<W, KIND, T, AC, CPLX, false, false>(nv, cmp);
     if (!f) {
-        set_error("vectors per pass %d not in {1, 2, 4, 8}", nv);
+        set_error("vectors per pass %d not in {1, 2, 4, 8} (at most 2 with the rank-addressed x, "
+                  "whose tables must be in LDS)", nv);
         return XDG_EINVAL;
     }
     if (lds > 65536)
@@ -712,15 +764,15 @@ int launch_nv(int nv, const ApplyArgs &A, unsigned grid, unsigned block, size_t 
     return XDG_OK;
 }
 
-template <class W, int KIND, bool CPLX>
+template <class W, int KIND, bool CPLX, bool XR>
 int launch_prec(bool single, bool acc64, int nv, const ApplyArgs &A, unsigned grid,
                 unsigned block, size_t lds, hipStream_t st) {
-    if (!single) return launch_nv<W, KIND, double, double, CPLX>(nv, A, grid, block, lds, st);
-    if (acc64) return launch_nv<W, KIND, float, double, CPLX>(nv, A, grid, block, lds, st);
-    return launch_nv<W, KIND, float, float, CPLX>(nv, A, grid, block, lds, st);
+    if (!single) return launch_nv<W, KIND, double, double, CPLX, XR>(nv, A, grid, block, lds, st);
+    if (acc64) return launch_nv<W, KIND, float, double, CPLX, XR>(nv, A, grid, block, lds, st);
+    return launch_nv<W, KIND, float, float, CPLX, XR>(nv, A, grid, block, lds, st);
 }
 
-template <int KIND>
+template <int KIND, bool XR = false>
 int launch_kind_impl(bool wide, bool single, bool acc64, bool cplx, int nv, const ApplyArgs &A,
                      unsigned grid, unsigned block, size_t lds, hipStream_t st) {
     if constexpr (KIND == K_U1) {
@@ -728,14 +780,14 @@ int launch_kind_impl(bool wide, bool single, bool acc64, bool cplx, int nv, cons
             set_error("complex kernel requested for a U(1) block");
             return XDG_EINVAL;
         }
-        return wide ? launch_prec<uint64_t, KIND, false>(single, acc64, nv, A, grid, block, lds, st)
-                    : launch_prec<uint32_t, KIND, false>(single, acc64, nv, A, grid, block, lds, st);
+        return wide ? launch_prec<uint64_t, KIND, false, XR>(single, acc64, nv, A, grid, block, lds, st)
+                    : launch_prec<uint32_t, KIND, false, XR>(single, acc64, nv, A, grid, block, lds, st);
     } else {
         if (wide)
-            return cplx ? launch_prec<uint64_t, KIND, true>(single, acc64, nv, A, grid, block, lds, st)
-                        : launch_prec<uint64_t, KIND, false>(single, acc64, nv, A, grid, block, lds, st);
-        return cplx ? launch_prec<uint32_t, KIND, true>(single, acc64, nv, A, grid, block, lds, st)
-                    : launch_prec<uint32_t, KIND, false>(single, acc64, nv, A, grid, block, lds, st);
+            return cplx ? launch_prec<uint64_t, KIND, true, XR>(single, acc64, nv, A, grid, block, lds, st)
+                        : launch_prec<uint64_t, KIND, false, XR>(single, acc64, nv, A, grid, block, lds, st);
+        return cplx ? launch_prec<uint32_t, KIND, true, XR>(single, acc64, nv, A, grid, block, lds, st)
+                    : launch_prec<uint32_t, KIND, false, XR>(single, acc64, nv, A, grid, block, lds, st);
     }
 }
 

@@ -642,6 +642,45 @@ uint64_t colex_rank_host(uint64_t s) {
     return r;
 }
 
+// First rank of every top block for rank-addressed vectors (top_rank): the
+// blocks that are the minimal top of their own content, ascending, each
+// followed by the colex ranks of the states of the remaining popcount on the
+// B sites below it.  Not set up when the blocks do not tile the sites or B
+// exceeds 31.  first, last: the block's smallest and largest basis states.
+template <class W>
+int build_xr(xdg_basis_s *b, const void *T, const RankLayout &L, W first, W last) {
+    const SublatticeTables &S = b->plan.sub;
+    const int n_s = S.n_s, m = S.m, B = (n_s - 1) * m;
+    if (n_s < 2 || n_s * m != b->n_sites || B < 1 || B > 31 || m > 16) return XDG_OK;
+    const uint32_t V = 1u << m;
+    std::vector<uint64_t> top(V, ~0ull);
+    uint64_t acc = 0;
+    for (uint32_t c = 0; c < V; ++c) {
+        if (S.mintop[(size_t)(n_s - 1) * V + c] != c) continue;
+        const int k = b->n_up - __builtin_popcount(c);
+        if (k < 0 || k > B) continue;
+        top[c] = acc;
+        acc += binomial(B, k);
+    }
+    const uint64_t r0 = top_rank<W>(T, L, B, top.data(), first);
+    const uint64_t r1 = top_rank<W>(T, L, B, top.data(), last);
+    if (r0 == ~0ull || r1 == ~0ull || r0 > r1 || r1 >= acc) {
+        set_error("internal: a representative lies outside the top-block rank space");
+        return XDG_EINVAL;
+    }
+    XDG_RETURN_IF(b->xr_top.upload(top.data(), sizeof(uint64_t) * V));
+    if (acc < 0xFFFFFFFFull) {   // 4-byte first ranks for the kernels' LDS
+        std::vector<uint32_t> t32(V);
+        for (uint32_t c = 0; c < V; ++c) t32[c] = top[c] == ~0ull ? 0xFFFFFFFFu : (uint32_t)top[c];
+        XDG_RETURN_IF(b->xr_top32.upload(t32.data(), sizeof(uint32_t) * V));
+    }
+    const int nlc = (B + L.cb - 1) / L.cb;
+    b->xr_rows = L.rbase[nlc - 1] + rank_hi(b->n_up, L.cb, nlc - 1) + 1;
+    b->xr_slots = r1 + 1;
+    b->xr_bits = B;
+    return XDG_OK;
+}
+
 // Rank index when it fits (see XDG_INDEX_RANK); returns XDG_OK with
 // b->n_rwords = 0 when the hash index should be used instead.
 template <class W>
@@ -683,6 +722,11 @@ int build_rank(xdg_basis_s *b) {
     XDG_TRY_HIP(hipDeviceSynchronize());
     b->n_rwords = n_words;
     b->rank = L;
+    if (b->plan.kind == K_SUB) {
+        W first = 0;
+        XDG_RETURN_IF(copy_d2h(&first, b->reps.as<W>(), sizeof(W), nullptr));
+        XDG_RETURN_IF(build_xr<W>(b, T, L, first, (W)last));
+    }
     return XDG_OK;
 }
 

@@ -359,9 +359,11 @@ int xdg_apply_with_config(xdg_ham h, const void *x, void *y, int64_t nvec, int d
         bool res_ok = true;
         for (int r : cfg->reserved) res_ok &= r == 0;
         if (cfg->grid < 0 || !nv_ok || cfg->occ < -1 || cfg->occ > 1 || cfg->compact < -1 ||
-            cfg->compact > 1 || (cfg->sub_form != 0 && cfg->sub_form != 2) || !res_ok) {
-            set_error("launch shape out of range (grid %d, nv %d, occ %d, compact %d, sub_form %d)",
-                      cfg->grid, cfg->nv, cfg->occ, cfg->compact, cfg->sub_form);
+            cfg->compact > 1 || (cfg->sub_form != 0 && cfg->sub_form != 2) || cfg->xr < 0 ||
+            cfg->xr > 1 || !res_ok) {
+            set_error("launch shape out of range (grid %d, nv %d, occ %d, compact %d, sub_form %d, "
+                      "xr %d)", cfg->grid, cfg->nv, cfg->occ, cfg->compact, cfg->sub_form,
+                      cfg->xr);
             return XDG_EINVAL;
         }
         LaunchCfg c;
@@ -371,6 +373,7 @@ int xdg_apply_with_config(xdg_ham h, const void *x, void *y, int64_t nvec, int d
         c.occ = cfg->occ;
         c.compact = cfg->compact;
         c.sub_form = cfg->sub_form;
+        c.xr = cfg->xr;
         return apply_launch(h, x, y, nvec, dtype, (hipStream_t)stream, &c);
     });
 }
@@ -388,6 +391,8 @@ int xdg_apply_tuned_config(xdg_ham h, int dtype, int64_t nvec, xdg_launch_cfg *o
         out->nv = c.nv;
         out->occ = c.occ;
         out->compact = c.compact;
+        out->sub_form = c.sub_form;
+        out->xr = c.xr;
         return XDG_OK;
     });
 }

@@ -165,6 +165,13 @@ struct xdg_basis_s {
     uint64_t n_rwords = 0;      // 0: the hash index is used
     xdg::DevBuf rtab;
     xdg::RankLayout rank{};     // layout of rtab (chunks, entry size, row bases)
+    // rank-addressed vectors (sublattice coding, see top_rank): first rank of
+    // each top block (u64 [2^m], ~0 for a block that is never a minimal top),
+    // the slots up to the last basis state and the sites below the top block
+    xdg::DevBuf xr_top, xr_top32;   // xr_top32: u32 copy when every first rank fits
+    uint64_t xr_slots = 0;      // 0: not available
+    int xr_bits = 0;
+    int xr_rows = 0;            // rank-table rows of the chunks below the top block
     int lin_nlo = 0, lin_nhi = 0;
     // sublattice tables on the device: t_pid = u32 [n_sym][n_s], the offset of
     // the block permutation's tables in t_tperm << 8 | first bit of the source block
@@ -191,6 +198,7 @@ struct LaunchCfg {
     int occ = -1;          // 64-VGPR copy at 8 waves per SIMD: 1 / 0 / -1 = when the LDS allows
     int compact = -1;      // table searches: 1 = wave-compacted term loop, 0 / -1 = row loop
     int sub_form = 0;      // sublattice coding: 0 = packed form where it applies, 2 = block form
+    int xr = 0;            // sublattice coding: 1 = terms read a rank-addressed copy of x
 };
 }  // namespace xdg
 
@@ -206,6 +214,16 @@ struct xdg_ham_s {
     int64_t nnz = -1;
     std::mutex tune_mu;         // guards `tuned` (and the tuning runs that fill it)
     std::map<xdg::TuneKey, xdg::LaunchCfg> tuned;
+    // the rank-addressed copy of x (LaunchCfg::xr): slot bytes of its current
+    // layout (slots outside the block hold zeros in it), and an event after
+    // the last launch that read it (calls on other streams wait for it)
+    std::mutex xr_mu;
+    xdg::DevBuf xr_buf;
+    size_t xr_slot_bytes = 0;
+    hipEvent_t xr_ev = nullptr;
+    ~xdg_ham_s() {
+        if (xr_ev) (void)hipEventDestroy(xr_ev);
+    }
 };
 
 namespace xdg {

@@ -35,7 +35,7 @@ class XdgError(RuntimeError):
 
 class LaunchCfg(C.Structure):
     _fields_ = [("grid", C.c_int), ("nv", C.c_int), ("occ", C.c_int), ("compact", C.c_int),
-                ("sub_form", C.c_int), ("reserved", C.c_int * 3)]
+                ("sub_form", C.c_int), ("xr", C.c_int), ("reserved", C.c_int * 2)]
 
 
 class BasisOpts(C.Structure):
@@ -375,14 +375,14 @@ def xdg_apply(h, x, y, nvec: Optional[int] = None, dtype: Optional[int] = None, 
 
 def xdg_apply_with_config(h, x, y, grid: int = 0, nv: int = 0, occ: int = -1, compact: int = -1,
                           nvec: Optional[int] = None, dtype: Optional[int] = None, stream=None,
-                          sub_form: int = 0):
+                          sub_form: int = 0, xr: int = 0):
     """xdg_apply in an explicit launch shape (every shape gives the same y)."""
     if nvec is None:
         nvec = 1 if x.dim() == 1 else int(x.shape[1])
     if dtype is None:
         dtype = _dtype_code(x)
     _check_apply_vectors(h, x, y, nvec, dtype)
-    cfg = LaunchCfg(grid, nv, occ, compact, sub_form)
+    cfg = LaunchCfg(grid, nv, occ, compact, sub_form, xr)
     _check(lib().xdg_apply_with_config(h, _ptr(x), _ptr(y), nvec, dtype, C.byref(cfg),
                                        _stream(stream)))
 
@@ -391,7 +391,8 @@ def xdg_apply_tuned_config(h, dtype: int, nvec: int = 1) -> dict:
     """The autotuner's launch shape for (dtype, nvec) on this Hamiltonian."""
     cfg = LaunchCfg()
     _check(lib().xdg_apply_tuned_config(h, dtype, nvec, C.byref(cfg)))
-    return {"grid": cfg.grid, "nv": cfg.nv, "occ": cfg.occ, "compact": cfg.compact}
+    return {"grid": cfg.grid, "nv": cfg.nv, "occ": cfg.occ, "compact": cfg.compact,
+            "sub_form": cfg.sub_form, "xr": cfg.xr}
 
 
 def xdg_apply_batched(hams: Sequence, xs: Sequence, ys: Sequence, nvec: Optional[int] = None,

@@ -292,6 +292,21 @@ def test_c3_fullsize(X):
     lhs, rhs = torch.dot(w, hx).item(), torch.dot(x, hw).item()
     assert abs(lhs - rhs) < 1e-10 * abs(lhs)
     del x, w, hx, hw
+    check_rank_addressed(X, b, H, 44)
+
+
+def check_rank_addressed(X, b, H, seed):
+    """x through the rank index and through the rank-addressed copy give
+    bitwise the same y (FP32 vectors, then FP64)."""
+    g = torch.Generator(device="cuda").manual_seed(seed)
+    for dt in (torch.float32, torch.float64):
+        x = torch.randn(b.dim, dtype=dt, device="cuda", generator=g)
+        y0, y1 = torch.empty_like(x), torch.full_like(x, float("nan"))
+        X.xdg_apply_with_config(H.handle, x, y0, grid=1024, occ=-1, xr=0)
+        X.xdg_apply_with_config(H.handle, x, y1, grid=1024, occ=-1, xr=1)
+        torch.cuda.synchronize()
+        assert torch.equal(y0, y1), dt
+        del x, y0, y1
 
 
 def test_c3_sampled_rows(X):
@@ -345,6 +360,7 @@ def test_c5_fullsize(X):
     check_membership(X, m, b, 51, n_members=600, n_random=600)
     check_columns(X, m, b, H, 52, 2, [(torch.float64, 1e-12)])
     check_hermitian(b, H, 53, fp32=False)
+    check_rank_addressed(X, b, H, 55)
 
 
 def test_c5_sampled_rows(X):

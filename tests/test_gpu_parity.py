@@ -375,8 +375,8 @@ SHAPE_CASES = [
 @pytest.mark.parametrize("case", range(len(SHAPE_CASES)))
 def test_every_launch_shape_gives_the_same_y(X, case):
     """The autotuner's candidates (grid, vectors per pass, occupancy copy,
-    row or compacted term loop) and both forms of the sublattice search
-    compute bitwise the same y."""
+    row or compacted term loop, x through the rank index or rank-addressed)
+    and both forms of the sublattice search compute bitwise the same y."""
     m, search = SHAPE_CASES[case]
     b = X.Basis.from_model(m, search=search)
     H = X.Hamiltonian.from_model(b, m)
@@ -391,12 +391,14 @@ def test_every_launch_shape_gives_the_same_y(X, case):
                 for occ in (-1, 0, 1):
                     for compact in (0, 1):
                         for form in (0, 2):
-                            y = torch.full_like(x, float("nan"))
-                            X.xdg_apply_with_config(H.handle, x, y, grid=grid, nv=nv, occ=occ,
-                                                    compact=compact, sub_form=form)
-                            torch.cuda.synchronize()
-                            assert torch.equal(y, ref), (m.name, dt, grid, nv, occ, compact,
-                                                         form)
+                            for xr in (0, 1):
+                                y = torch.full_like(x, float("nan"))
+                                X.xdg_apply_with_config(H.handle, x, y, grid=grid, nv=nv,
+                                                        occ=occ, compact=compact,
+                                                        sub_form=form, xr=xr)
+                                torch.cuda.synchronize()
+                                assert torch.equal(y, ref), (m.name, dt, grid, nv, occ,
+                                                             compact, form, xr)
         code = {torch.float64: X.XDG_F64, torch.float32: X.XDG_F32,
                 torch.complex128: X.XDG_C128, torch.complex64: X.XDG_C64}[dt]
         cfg = X.xdg_apply_tuned_config(H.handle, code, 2)
@@ -405,8 +407,57 @@ def test_every_launch_shape_gives_the_same_y(X, case):
         X.xdg_apply_with_config(H.handle, x, torch.empty_like(x), nv=3)
     with pytest.raises(X.XdgError):
         X.xdg_apply_with_config(H.handle, x, torch.empty_like(x), sub_form=1)
+    with pytest.raises(X.XdgError):
+        X.xdg_apply_with_config(H.handle, x, torch.empty_like(x), xr=2)
     with pytest.raises(X.XdgError):                  # not tuned for this (dtype, nvec)
         X.xdg_apply_tuned_config(H.handle, code, 7)
+
+
+XR_CASES = [0, 4, 5, 6, 7]   # the sublattice cases of SHAPE_CASES with four blocks
+
+
+@pytest.mark.parametrize("case", XR_CASES)
+def test_rank_addressed_x_layouts(X, case):
+    """The rank-addressed copy of x through changes of its layout on one
+    Hamiltonian (one vector, three vectors, FP64 / FP32, complex vectors on a
+    real block, back to one vector: each change re-zeroes the slots outside
+    the block) and calls alternating between two streams: every y equals the
+    one through the rank index, bitwise, against the oracle's H x in FP64."""
+    m, _ = SHAPE_CASES[case]
+    b = X.Basis.from_model(m)
+    H = X.Hamiltonian.from_model(b, m)
+    basis = oracle_basis(m)
+    cdt = (torch.complex128, torch.complex64)
+    forms = [(1, cdt[0] if b.is_complex else torch.float64),
+             (3, cdt[1] if b.is_complex else torch.float32),
+             (2, cdt[0]), (1, cdt[1] if b.is_complex else torch.float32),
+             (1, cdt[0] if b.is_complex else torch.float64)]
+    for i, (nv, dt) in enumerate(forms):
+        x0 = W.random_vector(300 + i, b.dim, nv, complex_=dt.is_complex)
+        x = torch.from_numpy(np.ascontiguousarray(x0)).to("cuda", dt)
+        ref, y = torch.empty_like(x), torch.full_like(x, float("nan"))
+        X.xdg_apply_with_config(H.handle, x, ref, xr=0)
+        X.xdg_apply_with_config(H.handle, x, y, xr=1)
+        torch.cuda.synchronize()
+        assert torch.equal(y, ref), (m.name, nv, dt)
+        if i == 0:
+            want = oracle.apply(m, basis, x0.astype(np.complex128))
+            got = y.cpu().numpy().astype(np.complex128)
+            assert np.max(np.abs(got - want)) <= 1e-12 * max(1.0, np.max(np.abs(want)))
+    s1, s2 = torch.cuda.Stream(), torch.cuda.Stream()
+    dt = cdt[1] if b.is_complex else torch.float32
+    xs = [torch.randn(b.dim, dtype=dt, device="cuda") for _ in range(4)]
+    ref = [torch.empty_like(x) for x in xs]
+    for x, r in zip(xs, ref):
+        X.xdg_apply_with_config(H.handle, x, r, xr=0)
+    torch.cuda.synchronize()
+    ys = [torch.full_like(x, float("nan")) for x in xs]
+    for k, (x, y) in enumerate(zip(xs, ys)):
+        st = s1 if k % 2 == 0 else s2
+        X.xdg_apply_with_config(H.handle, x, y, xr=1, stream=st.cuda_stream)
+    torch.cuda.synchronize()
+    for y, r in zip(ys, ref):
+        assert torch.equal(y, r)
 
 
 def test_failure_paths(X):
