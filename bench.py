@@ -99,7 +99,7 @@ def alg_bytes(dim: int, n_sites: int, n_up: int, n_bonds: int, vec: int, nvec: i
 APPLY_SOURCES = ["include/xdg.h"] + [
     "paper_2505_02901_amd/csrc/" + f for f in (
         "xdg_internal.hpp", "device_common.hpp", "apply_impl.hpp", "apply.hip",
-        "apply_u1.hip", "apply_aff.hip", "apply_sub.hip", "apply_tab.hip")]
+        "apply_u1.hip", "apply_aff.hip", "apply_sub.hip", "apply_sub_xr.hip", "apply_tab.hip")]
 
 
 def source_hash() -> str:
@@ -456,22 +456,43 @@ def counters_run(args):
                       "nnz": sum(h.nnz for h in hs), "nvec": nvec, "copy_bytes": a.numel() * 4}))
 
 
+def apply_dispatches(rows):
+    """Dispatch ids of the last apply launch in a counter CSV: the last
+    k_apply dispatch and, when the terms read the rank-addressed x, the
+    scatter that filled it just before (both are inside the timed launch)."""
+    apply_ids = sorted({int(r["Dispatch_Id"]) for r in rows if "k_apply" in r["Kernel_Name"]})
+    last = apply_ids[-1]
+    scat = [int(r["Dispatch_Id"]) for r in rows
+            if "k_xr_scatter" in r["Kernel_Name"] and int(r["Dispatch_Id"]) < last]
+    prev = max(apply_ids[:-1] + [-1]) if len(apply_ids) > 1 else -1
+    ids = {last}
+    if scat and max(scat) > prev:
+        ids.add(max(scat))
+    return ids
+
+
 def summarize_issue(args):
     """profiles/issue_<workload>.json from the CSV of the SQ_INSTS_* run (last
-    apply dispatch; counts summed over the chip)."""
+    apply launch: the apply dispatch and its scatter, if any; counts summed
+    over the chip)."""
     import csv
     import glob
     f = glob.glob(os.path.join(args.summarize_issue, "**", "*counter_collection.csv"),
                   recursive=True)[0]
     rows = list(csv.DictReader(open(f)))
-    last = [r["Dispatch_Id"] for r in rows if "k_apply" in r["Kernel_Name"]][-1]
-    vals, kname = {}, ""
+    ids = apply_dispatches(rows)
+    vals, kname, scatter = {}, "", {}
     for r in rows:
-        if r["Dispatch_Id"] == last:
+        if int(r["Dispatch_Id"]) in ids:
             vals[r["Counter_Name"]] = vals.get(r["Counter_Name"], 0.0) + float(r["Counter_Value"])
-            kname = r["Kernel_Name"]
+            if "k_apply" in r["Kernel_Name"]:
+                kname = r["Kernel_Name"]
+            else:
+                scatter[r["Counter_Name"]] = scatter.get(r["Counter_Name"], 0.0) + float(
+                    r["Counter_Value"])
     out = {"workload": args.workload, "kernel": kname, "source_hash": source_hash(),
-           "valu_wave_insts": vals["SQ_INSTS_VALU"], "counters": vals}
+           "valu_wave_insts": vals["SQ_INSTS_VALU"], "counters": vals,
+           "scatter_counters": scatter}
     p = os.path.join(ROOT, "profiles", f"issue_{args.workload}.json")
     with open(p, "w") as fh:
         json.dump(out, fh, indent=1)
@@ -488,19 +509,23 @@ def summarize_counters(args):
     def read(d, counter):
         f = glob.glob(os.path.join(d, "**", "*counter_collection.csv"), recursive=True)[0]
         rows = [r for r in csv.DictReader(open(f)) if r["Counter_Name"] == counter]
-        app = [r for r in rows if "k_apply" in r["Kernel_Name"]][-1]
+        ids = apply_dispatches(rows)
+        app = [r for r in rows if int(r["Dispatch_Id"]) in ids]
+        kname = [r["Kernel_Name"] for r in app if "k_apply" in r["Kernel_Name"]][0]
+        sc = sum(float(r["Counter_Value"]) for r in app if "k_apply" not in r["Kernel_Name"])
         cp = [r for r in rows if "copyBuffer" in r["Kernel_Name"] or "copy" in r["Kernel_Name"]]
         cp = max(cp, key=lambda r: float(r["Counter_Value"]))
-        return float(app["Counter_Value"]), float(cp["Counter_Value"]), app["Kernel_Name"]
+        return sum(float(r["Counter_Value"]) for r in app), float(cp["Counter_Value"]), kname, sc
 
-    fetch, fetch_cp, kname = read(args.summarize_counters[0], "FETCH_SIZE")
-    write, write_cp, _ = read(args.summarize_counters[1], "WRITE_SIZE")
+    fetch, fetch_cp, kname, fetch_sc = read(args.summarize_counters[0], "FETCH_SIZE")
+    write, write_cp, _, write_sc = read(args.summarize_counters[1], "WRITE_SIZE")
     copy_bytes = 256 << 22
     f_scale = copy_bytes / (fetch_cp * 1024.0)
     w_scale = copy_bytes / (write_cp * 1024.0)
     traffic = fetch * 1024.0 * f_scale + write * 1024.0 * w_scale
     out = {"workload": args.workload, "kernel": kname, "source_hash": source_hash(),
-           "fetch_kib": fetch, "write_kib": write, "copy_fetch_kib": fetch_cp,
+           "fetch_kib": fetch, "write_kib": write, "scatter_fetch_kib": fetch_sc,
+           "scatter_write_kib": write_sc, "copy_fetch_kib": fetch_cp,
            "copy_write_kib": write_cp, "fetch_scale": f_scale, "write_scale": w_scale,
            "traffic_bytes_per_launch": traffic}
     p = os.path.join(ROOT, "profiles", f"traffic_{args.workload}.json")
