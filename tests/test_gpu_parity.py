@@ -485,6 +485,29 @@ def test_failure_paths(X):
         X.xdg_set_device_memory_limit(-1)
 
 
+def test_rank_addressed_x_out_of_memory(X):
+    """The rank-addressed copy of x under a memory cap too small for it:
+    XDG_ENOMEM before any launch, then the same call works once the cap is
+    lifted, and y equals the form through the rank index."""
+    m, _ = SHAPE_CASES[0]
+    b = X.Basis.from_model(m)
+    H = X.Hamiltonian.from_model(b, m)
+    x = torch.randn(b.dim, 3, dtype=torch.float64, device="cuda")
+    ref, y = torch.empty_like(x), torch.full_like(x, float("nan"))
+    X.xdg_apply_with_config(H.handle, x, ref, xr=0)
+    used = X.xdg_set_device_memory_limit(0)
+    try:
+        X.xdg_set_device_memory_limit(used + 256)
+        with pytest.raises(X.XdgError) as e:
+            X.xdg_apply_with_config(H.handle, x, y, xr=1)
+        assert e.value.code == X.XDG_ENOMEM
+    finally:
+        X.xdg_set_device_memory_limit(0)
+    X.xdg_apply_with_config(H.handle, x, y, xr=1)
+    torch.cuda.synchronize()
+    assert torch.equal(y, ref)
+
+
 def test_batched_plans_follow_new_pointers(X):
     """Cached batched plans are keyed by the vectors: new tensors, then the
     first ones again, all give the single-block results; batched Lanczos
