@@ -159,7 +159,8 @@ struct Staged {
     bool subf;             // packed sublattice search (sub.sp holds the packed entries)
     uint32_t amask;        // ~(4E - 1)
     const uint64_t *xr_top;   // first rank of each top block (rank-addressed x)
-    const uint32_t *xr_top32; // the same in 4 bytes, or null
+    const uint32_t *xr_top32; // the same in 4 bytes (xr_w32) at the same place
+    bool xr_w32;
 };
 
 template <class E>
@@ -183,6 +184,7 @@ __device__ inline void stage(const SectorDesc &d, unsigned char *smem, Staged<T>
     S.subf = false;
     S.xr_top = d.xr_top;
     S.xr_top32 = d.xr_top32;
+    S.xr_w32 = d.xr_top32 != nullptr;
     if constexpr (KIND != K_U1) {
         S.chi = stage_copy(smem, off, reinterpret_cast<const T2 *>(d.chi), d.n_sym);
         const T *ls = stage_copy(smem, off, reinterpret_cast<const T *>(d.sqrtt), 2 * (d.n_sym + 1));
@@ -227,12 +229,17 @@ __device__ inline void stage(const SectorDesc &d, unsigned char *smem, Staged<T>
                     S.sub.sp = stage_copy(smem, off, d.sp, (size_t)d.n_sym * d.n_s);
                     S.sub.tperm = stage_copy(smem, off, d.tperm, ntp);
                 }
+                // the first-rank table at one LDS address whatever its entry
+                // size (both pointers always address LDS here: LDS reads)
+                unsigned char *tp = smem + off;
                 if (d.xr) {
                     if (d.xr_top32)
-                        S.xr_top32 = stage_copy(smem, off, d.xr_top32, (size_t)1 << d.m);
+                        stage_copy(smem, off, d.xr_top32, (size_t)1 << d.m);
                     else
-                        S.xr_top = stage_copy(smem, off, d.xr_top, (size_t)1 << d.m);
+                        stage_copy(smem, off, d.xr_top, (size_t)1 << d.m);
                 }
+                S.xr_top32 = reinterpret_cast<const uint32_t *>(tp);
+                S.xr_top = reinterpret_cast<const uint64_t *>(tp);
             }
         }
     }
@@ -281,7 +288,7 @@ __device__ __forceinline__ typename IndexT<W>::type locate(const SectorDesc &d, 
         }
         if constexpr (KIND == K_SUB && XR) {
             // the slot of rep in the rank-addressed x (zeros unless rep is a basis state)
-            const uint64_t r = S.xr_top32
+            const uint64_t r = S.xr_w32
                                    ? top_rank32<W>(S.rtab, d.rl, d.xr_bits, S.xr_top32, rep)
                                    : top_rank<W>(S.rtab, d.rl, d.xr_bits, S.xr_top, rep);
             return r < d.xr_slots ? (I)r : (I)-1;
@@ -308,7 +315,11 @@ __device__ __forceinline__ typename IndexT<W>::type locate(const SectorDesc &d, 
 // T: storage type of x and y; A: type of the amplitudes and of the per-row
 // accumulation (each output element is rounded to T once, at the store).
 // XR: the terms read the rank-addressed x (sublattice coding, d.xr set).
-template <class W, int KIND, class T, class A, bool CPLX, int NV, bool XR = false>
+// PIPE: each term's gather is added at the next term of the row (or after
+// its last bond), so that its latency overlaps the next search; the same
+// fused multiply-adds in the same order.
+template <class W, int KIND, class T, class A, bool CPLX, int NV, bool XR = false,
+          bool PIPE = false>
 __device__ __forceinline__ void process_row(const SectorDesc &d, const Staged<A> &S, int64_t row,
                                             int64_t nvec, int v0) {
     using B = typename BondT<A>::type;
@@ -328,10 +339,51 @@ __device__ __forceinline__ void process_row(const SectorDesc &d, const Staged<A>
     for (int v = 0; v < NV * C; ++v) acc[v] = 0;
     A rn = A(1);
     if constexpr (KIND != K_U1) rn = S.rsq[gld(d.stab + row)];
+    // explicit fused multiply-adds: a complex kernel on a block with real
+    // characters (ai = 0) rounds exactly like the real kernel
+    auto add = [&](A ar, A ai, const T *xv) {
+#pragma unroll
+        for (int v = 0; v < NV; ++v) {
+            if constexpr (CPLX) {
+                const A xr = xv[2 * v], xi = xv[2 * v + 1];
+                acc[2 * v] = fmadd<A>(-ai, xi, fmadd<A>(ar, xr, acc[2 * v]));
+                acc[2 * v + 1] = fmadd<A>(ai, xr, fmadd<A>(ar, xi, acc[2 * v + 1]));
+            } else {
+                acc[v] = fmadd<A>(ar, (A)xv[v], acc[v]);
+            }
+        }
+    };
+    bool p_ok = false;   // PIPE: the pending term
+    A p_ar = 0, p_ai = 0;
+    T p_x[NV * C];
+#pragma unroll
+    for (int v = 0; v < NV * C; ++v) p_x[v] = T(0);
     // key: the packed sublattice search's key of the term's state, if given
     auto term = [&](const B &bd, W t, const SubKey *key) {
         int u, cnt;
         const auto idx = locate<W, KIND, A, XR>(d, S, t, u, cnt, key);
+        if constexpr (PIPE) {
+            // the gather is issued for every term (row 0 when the orbit is
+            // not in the block: a valid address, never added)
+            const bool ok = idx >= 0;
+            A ar = 0, ai = 0;
+            if (ok) {
+                const A f = bd.h * S.sq[cnt];
+                const auto c = S.chi[u];
+                ar = f * c.x;
+                if constexpr (CPLX) ai = f * c.y;
+            }
+            // the previous gather (issued one search ago) is added first, so
+            // that the new one can land in the same registers
+            if (p_ok) add(p_ar, p_ai, p_x);
+            const size_t xb = ((size_t)(ok ? idx : 0) * nvec + v0) * C;
+#pragma unroll
+            for (int v = 0; v < NV * C; ++v) p_x[v] = gld(XT + xb + v);
+            p_ok = ok;
+            p_ar = ar;
+            p_ai = ai;
+            return;
+        }
         if (idx < 0) return;
         A ar = bd.h, ai = 0;
         if constexpr (KIND != K_U1) {
@@ -401,6 +453,10 @@ __device__ __forceinline__ void process_row(const SectorDesc &d, const Staged<A>
                     const SubKey kt = sub_key_flip(kr, x);
                     term(bd, s ^ fl, &kt);
                 }
+                if constexpr (PIPE) {
+                    if (p_ok) add(p_ar, p_ai, p_x);
+                    p_ok = false;
+                }
                 done = true;
             }
         }
@@ -410,6 +466,10 @@ __device__ __forceinline__ void process_row(const SectorDesc &d, const Staged<A>
                 if (((s >> bd.i) & 1) == ((s >> bd.j) & 1)) continue;
                 junq += bd.jz;
                 term(bd, s ^ ((W(1) << bd.i) | (W(1) << bd.j)), nullptr);
+            }
+            if constexpr (PIPE) {
+                if (p_ok) add(p_ar, p_ai, p_x);
+                p_ok = false;
             }
         }
     }
@@ -592,7 +652,7 @@ __device__ __forceinline__ void process_window(const SectorDesc &d, const Staged
 // lane of a wave takes part in its permutes; `first` and `stride` count
 // lanes, so wave w of the launch starts at window w); otherwise a lane per
 // row, reading the rank-addressed x when XR.
-template <class W, int KIND, class T, class A, bool CPLX, int NV, bool CMP, bool XR>
+template <class W, int KIND, class T, class A, bool CPLX, int NV, bool CMP, bool XR, bool PIPE>
 __device__ __forceinline__ void process_range(const SectorDesc &d, const Staged<A> &S, int64_t r0,
                                               int64_t r1, int64_t first, int64_t stride,
                                               int64_t nvec, int v0) {
@@ -602,7 +662,7 @@ __device__ __forceinline__ void process_range(const SectorDesc &d, const Staged<
             process_window<W, KIND, T, A, CPLX, NV>(d, S, w0, r1, nvec, v0);
     } else {
         for (int64_t row = r0 + first; row < r1; row += stride)
-            process_row<W, KIND, T, A, CPLX, NV, XR>(d, S, row, nvec, v0);
+            process_row<W, KIND, T, A, CPLX, NV, XR, PIPE>(d, S, row, nvec, v0);
     }
 }
 
@@ -625,6 +685,8 @@ __device__ __forceinline__ uint32_t count_row(const SectorDesc &d, const Staged<
 template <class W, int KIND, class T, class AC, bool CPLX, int NV, bool STAGE, bool OCC,
           bool CMP, bool XR>
 __global__ __launch_bounds__(APPLY_BLOCK, OCC ? OCC_WAVES : 1) void k_apply(ApplyArgs A) {
+    // the 4-wave sublattice copy pipelines its gathers (registers to spare)
+    constexpr bool PIPE = KIND == K_SUB && !OCC && !CMP;
     extern __shared__ __align__(16) unsigned char smem[];
     __shared__ uint32_t s_tile;
     __shared__ SectorDesc s_desc;
@@ -634,7 +696,7 @@ __global__ __launch_bounds__(APPLY_BLOCK, OCC ? OCC_WAVES : 1) void k_apply(Appl
         stage<KIND, AC, STAGE>(d, smem, S);
         __syncthreads();
         const int64_t stride = (int64_t)gridDim.x * blockDim.x;
-        process_range<W, KIND, T, AC, CPLX, NV, CMP, XR>(d, S, 0, d.dim,
+        process_range<W, KIND, T, AC, CPLX, NV, CMP, XR, PIPE>(d, S, 0, d.dim,
                                                 (int64_t)blockIdx.x * blockDim.x + threadIdx.x,
                                                 stride, A.nvec, A.v0);
         return;
@@ -662,7 +724,7 @@ __global__ __launch_bounds__(APPLY_BLOCK, OCC ? OCC_WAVES : 1) void k_apply(Appl
         const int64_t r0 = (int64_t)(tile - A.tile_prefix[lo]) * A.tile_rows;
         int64_t r1 = r0 + A.tile_rows;
         r1 = r1 < d.dim ? r1 : d.dim;
-        process_range<W, KIND, T, AC, CPLX, NV, CMP, XR>(d, S, r0, r1, threadIdx.x, blockDim.x,
+        process_range<W, KIND, T, AC, CPLX, NV, CMP, XR, PIPE>(d, S, r0, r1, threadIdx.x, blockDim.x,
                                                      A.nvec, A.v0);
         __syncthreads();
     }
