@@ -685,8 +685,8 @@ __device__ __forceinline__ uint32_t count_row(const SectorDesc &d, const Staged<
 template <class W, int KIND, class T, class AC, bool CPLX, int NV, bool STAGE, bool OCC,
           bool CMP, bool XR>
 __global__ __launch_bounds__(APPLY_BLOCK, OCC ? OCC_WAVES : 1) void k_apply(ApplyArgs A) {
-    // the 4-wave sublattice copy pipelines its gathers (registers to spare)
-    constexpr bool PIPE = KIND == K_SUB && !OCC && !CMP;
+    // the sublattice row loop pipelines its gathers
+    constexpr bool PIPE = KIND == K_SUB && !CMP;
     extern __shared__ __align__(16) unsigned char smem[];
     __shared__ uint32_t s_tile;
     __shared__ SectorDesc s_desc;
