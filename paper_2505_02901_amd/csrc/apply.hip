@@ -151,7 +151,7 @@ int form_of(const xdg_basis_s *b, int dtype, int64_t nvec, Form *f) {
 // scalars per row); the other slots hold zeros.
 template <class W, class T>
 __global__ __launch_bounds__(256) void k_xr_scatter(const W *reps, int64_t dim, int spr,
-                                                   const T *x, T *xr, const void *rtab,
+                                                   const T *x, T *xr, const uint32_t *rtab,
                                                    RankLayout L, int B, const uint64_t *top,
                                                    uint64_t slots) {
     const int64_t stride = (int64_t)gridDim.x * 256;
@@ -206,23 +206,23 @@ int xr_prepare(xdg_ham_s *h, const void *x, const Form &f, hipStream_t st, bool 
         if (f.single)
             hipLaunchKernelGGL((k_xr_scatter<uint64_t, float>), dim3(g), dim3(256), 0, st,
                                b->reps.as<uint64_t>(), b->dim, spr, (const float *)x,
-                               h->xr_buf.as<float>(), b->rtab.p, b->rank, b->xr_bits, top,
+                               h->xr_buf.as<float>(), b->xr_rtab.as<uint32_t>(), b->rank, b->xr_bits, top,
                                b->xr_slots);
         else
             hipLaunchKernelGGL((k_xr_scatter<uint64_t, double>), dim3(g), dim3(256), 0, st,
                                b->reps.as<uint64_t>(), b->dim, spr, (const double *)x,
-                               h->xr_buf.as<double>(), b->rtab.p, b->rank, b->xr_bits, top,
+                               h->xr_buf.as<double>(), b->xr_rtab.as<uint32_t>(), b->rank, b->xr_bits, top,
                                b->xr_slots);
     } else {
         if (f.single)
             hipLaunchKernelGGL((k_xr_scatter<uint32_t, float>), dim3(g), dim3(256), 0, st,
                                b->reps.as<uint32_t>(), b->dim, spr, (const float *)x,
-                               h->xr_buf.as<float>(), b->rtab.p, b->rank, b->xr_bits, top,
+                               h->xr_buf.as<float>(), b->xr_rtab.as<uint32_t>(), b->rank, b->xr_bits, top,
                                b->xr_slots);
         else
             hipLaunchKernelGGL((k_xr_scatter<uint32_t, double>), dim3(g), dim3(256), 0, st,
                                b->reps.as<uint32_t>(), b->dim, spr, (const double *)x,
-                               h->xr_buf.as<double>(), b->rtab.p, b->rank, b->xr_bits, top,
+                               h->xr_buf.as<double>(), b->xr_rtab.as<uint32_t>(), b->rank, b->xr_bits, top,
                                b->xr_slots);
     }
     XDG_TRY_HIP(hipGetLastError());
@@ -285,6 +285,7 @@ int apply_launch(xdg_ham_s *h, const void *x, void *y, int64_t nvec, int dtype, 
         A.one.xr_slots = b->xr_slots;
         A.one.xr_bits = b->xr_bits;
         A.one.xr_rows = b->xr_rows;
+        A.one.xr_rtab = b->xr_rtab.as<uint32_t>();
         const size_t lx = f.tsingle ? stage_bytes<float>(A.one, b->plan.kind, 1)
                                     : stage_bytes<double>(A.one, b->plan.kind, 1);
         if (lx > lds_budget()) {

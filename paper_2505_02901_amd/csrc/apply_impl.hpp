@@ -87,7 +87,8 @@ struct SectorDesc {
     const uint32_t *xr_top32;    // the same in 4 bytes (0xFFFFFFFF if none), when all fit; or null
     uint64_t xr_slots;           // slots of xr (beyond the last one: not in the block)
     int xr_bits;                 // sites below the top block
-    int xr_rows;                 // rows of the rank tables for the chunks below the top block
+    const uint32_t *xr_rtab;     // the rank tables' rows for the chunks below it, 4-byte entries
+    int xr_rows;                 // rows of xr_rtab
     const void *x;
     void *y;
 };
@@ -119,9 +120,9 @@ __host__ __device__ inline size_t sub_table_bytes(const SectorDesc &d) {
 
 __host__ __device__ inline size_t rank_table_bytes(const SectorDesc &d) {
     if (!d.rwords) return 0;
-    // the rank-addressed x reads only the rows of the chunks below the top block
-    const size_t rows = d.xr ? (size_t)d.xr_rows : (size_t)d.rl.rows;
-    return (rows << d.rl.cb) * (d.rl.e32 ? 4 : 8);
+    // the rank-addressed x reads only its 4-byte rows of the chunks below the top block
+    if (d.xr) return ((size_t)d.xr_rows << d.rl.cb) * 4;
+    return ((size_t)d.rl.rows << d.rl.cb) * (d.rl.e32 ? 4 : 8);
 }
 
 // bytes of the first-rank table of the rank-addressed x in LDS
@@ -190,7 +191,8 @@ __device__ inline void stage(const SectorDesc &d, unsigned char *smem, Staged<T>
         const T *ls = stage_copy(smem, off, reinterpret_cast<const T *>(d.sqrtt), 2 * (d.n_sym + 1));
         S.sq = ls;
         S.rsq = ls + d.n_sym + 1;
-        S.rtab = stage_copy(smem, off, reinterpret_cast<const uint32_t *>(d.rtab),
+        S.rtab = stage_copy(smem, off,
+                            reinterpret_cast<const uint32_t *>(d.xr ? d.xr_rtab : d.rtab),
                             rank_table_bytes(d) / 4);
         if constexpr (KIND == K_AFF) {
             S.aff = stage_copy(smem, off, d.aff, d.n_sym);
@@ -288,9 +290,10 @@ __device__ __forceinline__ typename IndexT<W>::type locate(const SectorDesc &d, 
         }
         if constexpr (KIND == K_SUB && XR) {
             // the slot of rep in the rank-addressed x (zeros unless rep is a basis state)
+            const uint32_t *T32 = static_cast<const uint32_t *>(S.rtab);
             const uint64_t r = S.xr_w32
-                                   ? top_rank32<W>(S.rtab, d.rl, d.xr_bits, S.xr_top32, rep)
-                                   : top_rank<W>(S.rtab, d.rl, d.xr_bits, S.xr_top, rep);
+                                   ? top_rank32<W>(T32, d.rl, d.xr_bits, S.xr_top32, rep)
+                                   : top_rank<W>(T32, d.rl, d.xr_bits, S.xr_top, rep);
             return r < d.xr_slots ? (I)r : (I)-1;
         }
         if (d.rwords) {

@@ -642,11 +642,25 @@ uint64_t colex_rank_host(uint64_t s) {
     return r;
 }
 
+// The rows of the chunk tables (layout L) for the chunks below B, in 4-byte
+// entries: shares of sites below 32 are exact; larger ones (read only for
+// bits above B, which the rank clears) saturate.
+template <class E>
+int xr_lower_rows(const RankLayout &L, const E *T, int B, int n_up, std::vector<uint32_t> &out) {
+    const int nlc = (B + L.cb - 1) / L.cb;
+    const int rows = L.rbase[nlc - 1] + rank_hi(n_up, L.cb, nlc - 1) + 1;
+    out.resize((size_t)rows << L.cb);
+    for (size_t e = 0; e < out.size(); ++e)
+        out[e] = T[e] > (E)0xFFFFFFFFu ? 0xFFFFFFFFu : (uint32_t)T[e];
+    return rows;
+}
+
 // First rank of every top block for rank-addressed vectors (top_rank): the
 // blocks that are the minimal top of their own content, ascending, each
 // followed by the colex ranks of the states of the remaining popcount on the
 // B sites below it.  Not set up when the blocks do not tile the sites or B
-// exceeds 31.  first, last: the block's smallest and largest basis states.
+// exceeds 31.  T: the block's chunk tables (u32 or u64 entries, layout L);
+// first, last: its smallest and largest basis states.
 template <class W>
 int build_xr(xdg_basis_s *b, const void *T, const RankLayout &L, W first, W last) {
     const SublatticeTables &S = b->plan.sub;
@@ -662,8 +676,11 @@ int build_xr(xdg_basis_s *b, const void *T, const RankLayout &L, W first, W last
         top[c] = acc;
         acc += binomial(B, k);
     }
-    const uint64_t r0 = top_rank<W>(T, L, B, top.data(), first);
-    const uint64_t r1 = top_rank<W>(T, L, B, top.data(), last);
+    std::vector<uint32_t> low;
+    const int rows = L.e32 ? xr_lower_rows(L, static_cast<const uint32_t *>(T), B, b->n_up, low)
+                           : xr_lower_rows(L, static_cast<const uint64_t *>(T), B, b->n_up, low);
+    const uint64_t r0 = top_rank<W>(low.data(), L, B, top.data(), first);
+    const uint64_t r1 = top_rank<W>(low.data(), L, B, top.data(), last);
     if (r0 == ~0ull || r1 == ~0ull || r0 > r1 || r1 >= acc) {
         set_error("internal: a representative lies outside the top-block rank space");
         return XDG_EINVAL;
@@ -674,8 +691,8 @@ int build_xr(xdg_basis_s *b, const void *T, const RankLayout &L, W first, W last
         for (uint32_t c = 0; c < V; ++c) t32[c] = top[c] == ~0ull ? 0xFFFFFFFFu : (uint32_t)top[c];
         XDG_RETURN_IF(b->xr_top32.upload(t32.data(), sizeof(uint32_t) * V));
     }
-    const int nlc = (B + L.cb - 1) / L.cb;
-    b->xr_rows = L.rbase[nlc - 1] + rank_hi(b->n_up, L.cb, nlc - 1) + 1;
+    XDG_RETURN_IF(b->xr_rtab.upload(low.data(), sizeof(uint32_t) * low.size()));
+    b->xr_rows = rows;
     b->xr_slots = r1 + 1;
     b->xr_bits = B;
     return XDG_OK;

@@ -195,53 +195,41 @@ __host__ __device__ __forceinline__ uint32_t colex_rank_sat(const uint32_t *T32,
 // is): states ordered by c, then by the colex rank of the B bits below the
 // top block.  top[c] is the first rank of top block c, ~0 when c is never a
 // minimal top (the result is then ~0).  The bits below the top block lie in
-// the low 32 bits (B <= 31); the chunk tables' rows give their colex rank,
-// the chunk across the boundary read with its upper bits cleared (a set
-// bit's share depends only on its site and on the set bits below it; only
-// the rows of the chunks below B are read).  Ascending states keep
-// ascending ranks.
+// the low 32 bits (B <= 31), and their colex rank comes from T32: the rows
+// of the chunk tables for the chunks below B (layout L), in 4-byte entries
+// (every share of a site below 32 fits; the chunk across the boundary is
+// read with its upper bits cleared, since a set bit's share depends only on
+// its site and on the set bits below it).  Ascending states keep ascending
+// ranks.
 template <class W>
-__host__ __device__ __forceinline__ uint64_t below_top_rank(const void *T, const RankLayout &L,
-                                                            int B, W s) {
+__host__ __device__ __forceinline__ uint32_t below_top_rank(const uint32_t *T32,
+                                                            const RankLayout &L, int B, W s) {
     const int cb = L.cb;
     const uint32_t lo = (uint32_t)s & ((1u << B) - 1u), mask = (1u << cb) - 1u;
     const int nlc = (B + cb - 1) / cb;
-    uint32_t below = 0;
-    if (L.e32) {
-        // every share of a bit below site 31 is exact in 4 bytes, and so is their sum
-        const uint32_t *T32 = static_cast<const uint32_t *>(T);
-        uint32_t q = 0;
-        for (int k = 0; k < nlc; ++k) {
-            const uint32_t v = (lo >> (k * cb)) & mask;
-            q += T32[(((uint32_t)L.rbase[k] + below) << cb) | v];
-            below += (uint32_t)__builtin_popcount(v);
-        }
-        return q;
-    }
-    const uint64_t *T64 = static_cast<const uint64_t *>(T);
-    uint64_t r = 0;
+    uint32_t below = 0, q = 0;
     for (int k = 0; k < nlc; ++k) {
         const uint32_t v = (lo >> (k * cb)) & mask;
-        r += T64[(((uint32_t)L.rbase[k] + below) << cb) | v];
+        q += T32[(((uint32_t)L.rbase[k] + below) << cb) | v];
         below += (uint32_t)__builtin_popcount(v);
     }
-    return r;
+    return q;
 }
 
 template <class W>
-__host__ __device__ __forceinline__ uint64_t top_rank(const void *T, const RankLayout &L, int B,
-                                                      const uint64_t *top, W s) {
+__host__ __device__ __forceinline__ uint64_t top_rank(const uint32_t *T32, const RankLayout &L,
+                                                      int B, const uint64_t *top, W s) {
     const uint64_t base = top[(uint32_t)((uint64_t)s >> B)];
-    return base == ~0ull ? ~0ull : base + below_top_rank<W>(T, L, B, s);
+    return base == ~0ull ? ~0ull : base + below_top_rank<W>(T32, L, B, s);
 }
 
 // The same with 4-byte first ranks (every rank below 2^32 - 1; 0xFFFFFFFF
 // marks a top block that is never a minimal top).
 template <class W>
-__host__ __device__ __forceinline__ uint64_t top_rank32(const void *T, const RankLayout &L, int B,
-                                                        const uint32_t *top, W s) {
+__host__ __device__ __forceinline__ uint64_t top_rank32(const uint32_t *T32, const RankLayout &L,
+                                                        int B, const uint32_t *top, W s) {
     const uint32_t base = top[(uint32_t)((uint64_t)s >> B)];
-    return base == 0xFFFFFFFFu ? ~0ull : (uint64_t)base + below_top_rank<W>(T, L, B, s);
+    return base == 0xFFFFFFFFu ? ~0ull : (uint64_t)base + below_top_rank<W>(T32, L, B, s);
 }
 
 // Position of the state of colex rank r, or -1: words[r / 32] holds the

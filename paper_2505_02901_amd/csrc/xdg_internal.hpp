@@ -169,9 +169,10 @@ struct xdg_basis_s {
     // each top block (u64 [2^m], ~0 for a block that is never a minimal top),
     // the slots up to the last basis state and the sites below the top block
     xdg::DevBuf xr_top, xr_top32;   // xr_top32: u32 copy when every first rank fits
+    xdg::DevBuf xr_rtab;        // u32 rows of the rank tables for the chunks below the top block
     uint64_t xr_slots = 0;      // 0: not available
     int xr_bits = 0;
-    int xr_rows = 0;            // rank-table rows of the chunks below the top block
+    int xr_rows = 0;            // rows of xr_rtab
     int lin_nlo = 0, lin_nhi = 0;
     // sublattice tables on the device: t_pid = u32 [n_sym][n_s], the offset of
     // the block permutation's tables in t_tperm << 8 | first bit of the source block

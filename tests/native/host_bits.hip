@@ -147,16 +147,17 @@ static int check_top_rank(int N, int n_up, uint64_t max_rank, std::mt19937_64 &g
     const int m = N / 4, B = 3 * m;
     if (m < 1 || 4 * m != N || B > 31) return 0;
     const RankLayout L = rank_layout(N, n_up, sizeof(W) == 8, max_rank);
-    std::vector<uint32_t> T32;
+    // the library's 4-byte rows of the chunks below B, from either entry size
+    std::vector<uint32_t> T32, low;
     std::vector<uint64_t> T64;
-    const void *T;
     if (L.e32) {
         rank_tables<uint32_t>(N, n_up, L, T32);
-        T = T32.data();
+        xr_lower_rows(L, T32.data(), B, n_up, low);
     } else {
         rank_tables<uint64_t>(N, n_up, L, T64);
-        T = T64.data();
+        xr_lower_rows(L, T64.data(), B, n_up, low);
     }
+    const uint32_t *T = low.data();
     const uint32_t V = 1u << m;
     std::vector<uint64_t> top(V, ~0ull);
     uint64_t total = 0;
