@@ -99,7 +99,8 @@ def alg_bytes(dim: int, n_sites: int, n_up: int, n_bonds: int, vec: int, nvec: i
 APPLY_SOURCES = ["include/xdg.h"] + [
     "paper_2505_02901_amd/csrc/" + f for f in (
         "xdg_internal.hpp", "device_common.hpp", "apply_impl.hpp", "apply.hip",
-        "apply_u1.hip", "apply_aff.hip", "apply_sub.hip", "apply_sub_xr.hip", "apply_tab.hip")]
+        "apply_u1.hip", "apply_aff.hip", "apply_sub.hip", "apply_sub_xr.hip",
+        "apply_sub_xr_trivial.hip", "apply_tab.hip")]
 
 
 def source_hash() -> str:

@@ -316,7 +316,10 @@ int apply_launch(xdg_ham_s *h, const void *x, void *y, int64_t nvec, int dtype, 
     for (int64_t v0 = 0; v0 < f.cols;) {
         const int nv = pick_nv(f.cols - v0, cap);
         A.v0 = (int)v0;
-        if (xr_on)
+        if (xr_on && b->chi_trivial && !f.cplx_kernel)
+            XDG_RETURN_IF(launch_sub_xr_trivial(b->wide, f.single, f.acc64, nv, A, grid, block,
+                                                lds, st));
+        else if (xr_on)
             XDG_RETURN_IF(launch_sub_xr(b->wide, f.single, f.acc64, f.cplx_kernel, nv, A, grid,
                                         block, lds, st));
         else

@@ -255,8 +255,9 @@ template <> struct IndexT<uint32_t> { using type = int32_t; };
 // is not in the block.  On success writes u and |Stab(s)|.  key: t's key for
 // the packed sublattice search (computed here from t when null and that
 // search is on).  XR: the position is the slot in the rank-addressed x
-// (sublattice coding with d.xr set).
-template <class W, int KIND, class T, bool XR = false>
+// (sublattice coding with d.xr set); XR = 2: every character is 1, so the
+// search does not keep the element (u is left unset).
+template <class W, int KIND, class T, int XR = 0>
 __device__ __forceinline__ typename IndexT<W>::type locate(const SectorDesc &d, const Staged<T> &S,
                                                            W t, int &u, int &cnt,
                                                            const SubKey *key = nullptr) {
@@ -278,9 +279,10 @@ __device__ __forceinline__ typename IndexT<W>::type locate(const SectorDesc &d, 
         } else if constexpr (KIND == K_SUB) {
             if (S.subf) {
                 if (key)
-                    sub_search_packed<W>(S.sub, S.amask, *key, rep, u, cnt);
+                    sub_search_packed<W, XR != 2>(S.sub, S.amask, *key, rep, u, cnt);
                 else
-                    sub_search_packed<W>(S.sub, S.amask, sub_key<W>(t, d.m, d.pb), rep, u, cnt);
+                    sub_search_packed<W, XR != 2>(S.sub, S.amask, sub_key<W>(t, d.m, d.pb), rep,
+                                                  u, cnt);
             } else if (d.n_s == 4)
                 sub_search<W, 4>(S.sub, t, rep, u, cnt);
             else
@@ -288,7 +290,7 @@ __device__ __forceinline__ typename IndexT<W>::type locate(const SectorDesc &d, 
         } else {
             tab_search<W>(d.bytetab, d.n_bchunks, d.n_sym, t, rep, u, cnt);
         }
-        if constexpr (KIND == K_SUB && XR) {
+        if constexpr (KIND == K_SUB && XR != 0) {
             // the slot of rep in the rank-addressed x (zeros unless rep is a basis state)
             const uint32_t *T32 = static_cast<const uint32_t *>(S.rtab);
             const uint64_t r = S.xr_w32
@@ -317,11 +319,12 @@ __device__ __forceinline__ typename IndexT<W>::type locate(const SectorDesc &d, 
 
 // T: storage type of x and y; A: type of the amplitudes and of the per-row
 // accumulation (each output element is rounded to T once, at the store).
-// XR: the terms read the rank-addressed x (sublattice coding, d.xr set).
-// PIPE: each term's gather is added at the next term of the row (or after
-// its last bond), so that its latency overlaps the next search; the same
-// fused multiply-adds in the same order.
-template <class W, int KIND, class T, class A, bool CPLX, int NV, bool XR = false,
+// XR: the terms read the rank-addressed x (sublattice coding, d.xr set);
+// XR = 2: every character is 1 (the amplitude skips chi(u), a product by
+// exactly 1).  PIPE: each term's gather is added at the next term of the row
+// (or after its last bond), so that its latency overlaps the next search;
+// the same fused multiply-adds in the same order.
+template <class W, int KIND, class T, class A, bool CPLX, int NV, int XR = 0,
           bool PIPE = false>
 __device__ __forceinline__ void process_row(const SectorDesc &d, const Staged<A> &S, int64_t row,
                                             int64_t nvec, int v0) {
@@ -331,7 +334,8 @@ __device__ __forceinline__ void process_row(const SectorDesc &d, const Staged<A>
     const T *X = reinterpret_cast<const T *>(d.x);
     T *Y = reinterpret_cast<T *>(d.y);
     // the terms' x: rank-addressed (the same values at other places) or x itself
-    const T *XT = XR ? reinterpret_cast<const T *>(d.xr) : X;
+    const T *XT = XR != 0 ? reinterpret_cast<const T *>(d.xr) : X;
+    static_assert(XR != 2 || (PIPE && !CPLX), "trivial characters: real blocks, pipelined loop");
     const int nb = d.n_bonds;
     // Diagonal: sum_b Jz_b (+1/4 if the spins of b are equal, -1/4 if not)
     // = (1/4) sum_b Jz_b - (1/2) sum over the unequal-spin bonds of Jz_b; the
@@ -372,9 +376,13 @@ __device__ __forceinline__ void process_row(const SectorDesc &d, const Staged<A>
             A ar = 0, ai = 0;
             if (ok) {
                 const A f = bd.h * S.sq[cnt];
-                const auto c = S.chi[u];
-                ar = f * c.x;
-                if constexpr (CPLX) ai = f * c.y;
+                if constexpr (XR == 2) {
+                    ar = f;   // chi(u) = 1
+                } else {
+                    const auto c = S.chi[u];
+                    ar = f * c.x;
+                    if constexpr (CPLX) ai = f * c.y;
+                }
             }
             // the previous gather (issued one search ago) is added first, so
             // that the new one can land in the same registers
@@ -655,7 +663,7 @@ __device__ __forceinline__ void process_window(const SectorDesc &d, const Staged
 // lane of a wave takes part in its permutes; `first` and `stride` count
 // lanes, so wave w of the launch starts at window w); otherwise a lane per
 // row, reading the rank-addressed x when XR.
-template <class W, int KIND, class T, class A, bool CPLX, int NV, bool CMP, bool XR, bool PIPE>
+template <class W, int KIND, class T, class A, bool CPLX, int NV, bool CMP, int XR, bool PIPE>
 __device__ __forceinline__ void process_range(const SectorDesc &d, const Staged<A> &S, int64_t r0,
                                               int64_t r1, int64_t first, int64_t stride,
                                               int64_t nvec, int v0) {
@@ -686,7 +694,7 @@ __device__ __forceinline__ uint32_t count_row(const SectorDesc &d, const Staged<
 }
 
 template <class W, int KIND, class T, class AC, bool CPLX, int NV, bool STAGE, bool OCC,
-          bool CMP, bool XR>
+          bool CMP, int XR>
 __global__ __launch_bounds__(APPLY_BLOCK, OCC ? OCC_WAVES : 1) void k_apply(ApplyArgs A) {
     // the sublattice row loop pipelines its gathers
     constexpr bool PIPE = KIND == K_SUB && !CMP;
@@ -764,23 +772,25 @@ template <int KIND>
 int launch_count_kind(bool wide, const ApplyArgs &A, unsigned grid, unsigned block, size_t lds,
                       hipStream_t st);
 
-// The sublattice kernels whose terms read the rank-addressed x (their own
-// translation unit).
+// The sublattice kernels whose terms read the rank-addressed x: any
+// characters, and every character 1 (one translation unit each).
 int launch_sub_xr(bool wide, bool single, bool acc64, bool cplx, int nv, const ApplyArgs &A,
                   unsigned grid, unsigned block, size_t lds, hipStream_t st);
+int launch_sub_xr_trivial(bool wide, bool single, bool acc64, int nv, const ApplyArgs &A,
+                          unsigned grid, unsigned block, size_t lds, hipStream_t st);
 
 // XR (the rank-addressed x): passes of at most two vectors.
 template <class W, int KIND, class T, class AC, bool CPLX, bool STAGE, bool OCC, bool CMP,
-          bool XR = false>
+          int XR = 0>
 void (*apply_kernel(int nv))(ApplyArgs) {
     switch (nv) {
         case 1: return k_apply<W, KIND, T, AC, CPLX, 1, STAGE, OCC, CMP, XR>;
         case 2: return k_apply<W, KIND, T, AC, CPLX, 2, STAGE, OCC, CMP, XR>;
     }
-    if constexpr (!CMP && !XR) {
+    if constexpr (!CMP && XR == 0) {
         switch (nv) {
-            case 4: return k_apply<W, KIND, T, AC, CPLX, 4, STAGE, OCC, false, false>;
-            case 8: return k_apply<W, KIND, T, AC, CPLX, 8, STAGE, OCC, false, false>;
+            case 4: return k_apply<W, KIND, T, AC, CPLX, 4, STAGE, OCC, false, 0>;
+            case 8: return k_apply<W, KIND, T, AC, CPLX, 8, STAGE, OCC, false, 0>;
         }
     }
     return nullptr;
@@ -798,7 +808,7 @@ void (*apply_kernel_loop(int nv, bool compact))(ApplyArgs) {
     return apply_kernel<W, KIND, T, AC, CPLX, STAGE, OCC, false>(nv);
 }
 
-template <class W, int KIND, class T, class AC, bool CPLX, bool XR>
+template <class W, int KIND, class T, class AC, bool CPLX, int XR>
 int launch_nv(int nv, const ApplyArgs &A, unsigned grid, unsigned block, size_t lds,
               hipStream_t st) {
     void (*f)(ApplyArgs) = nullptr;
@@ -807,10 +817,13 @@ int launch_nv(int nv, const ApplyArgs &A, unsigned grid, unsigned block, size_t 
     // scalars: with more it spills them (complex 8-vector passes: 200 bytes)
     const bool occ = A.occ && nv * (CPLX ? 2 : 1) <= 2;
     const bool cmp = A.compact != 0;
-    if constexpr (XR) {   // row loop, tables in LDS
+    if constexpr (XR == 2 && CPLX) {
+        set_error("internal: the trivial-character kernels serve real blocks");
+        return XDG_EINVAL;
+    } else if constexpr (XR != 0) {   // row loop, tables in LDS
         if (A.stage_sub)
-            f = occ ? apply_kernel<W, KIND, T, AC, CPLX, true, true, false, true>(nv)
-                    : apply_kernel<W, KIND, T, AC, CPLX, true, false, false, true>(nv);
+            f = occ ? apply_kernel<W, KIND, T, AC, CPLX, true, true, false, XR>(nv)
+                    : apply_kernel<W, KIND, T, AC, CPLX, true, false, false, XR>(nv);
     } else if (KIND != K_SUB || A.stage_sub)
         f = occ ? apply_kernel_loop<W, KIND, T, AC, CPLX, true, true>(nv, cmp)
                 : apply_kernel_loop<W, KIND, T, AC, CPLX, true, false>(nv, cmp);
@@ -829,7 +842,7 @@ int launch_nv(int nv, const ApplyArgs &A, unsigned grid, unsigned block, size_t 
     return XDG_OK;
 }
 
-template <class W, int KIND, bool CPLX, bool XR>
+template <class W, int KIND, bool CPLX, int XR>
 int launch_prec(bool single, bool acc64, int nv, const ApplyArgs &A, unsigned grid,
                 unsigned block, size_t lds, hipStream_t st) {
     if (!single) return launch_nv<W, KIND, double, double, CPLX, XR>(nv, A, grid, block, lds, st);
@@ -837,7 +850,7 @@ int launch_prec(bool single, bool acc64, int nv, const ApplyArgs &A, unsigned gr
     return launch_nv<W, KIND, float, float, CPLX, XR>(nv, A, grid, block, lds, st);
 }
 
-template <int KIND, bool XR = false>
+template <int KIND, int XR = 0>
 int launch_kind_impl(bool wide, bool single, bool acc64, bool cplx, int nv, const ApplyArgs &A,
                      unsigned grid, unsigned block, size_t lds, hipStream_t st) {
     if constexpr (KIND == K_U1) {

@@ -788,6 +788,9 @@ int basis_build_device(xdg_basis_s *b) {
     const Plan &P = b->plan;
     if (b->n_sym) {
         XDG_RETURN_IF(b->chi_d.upload(b->chi.data(), b->chi.size() * sizeof(double)));
+        b->chi_trivial = true;
+        for (int g = 0; g < b->n_sym; ++g)
+            b->chi_trivial &= b->chi[2 * g] == 1.0 && b->chi[2 * g + 1] == 0.0;
         std::vector<float> cf(b->chi.begin(), b->chi.end());
         XDG_RETURN_IF(b->chi_f.upload(cf.data(), cf.size() * sizeof(float)));
         std::vector<double> sq(2 * (b->n_sym + 1));

@@ -669,7 +669,8 @@ __device__ __forceinline__ SubKey sub_key_flip(const SubKey &K, const BondX &x) 
 }
 
 // C.sp holds the packed (element, block) entries; amask = ~(4E - 1).
-template <class W>
+// KEEP_U = false: the element reaching the minimum is not kept (u = 0).
+template <class W, bool KEEP_U = true>
 __device__ __forceinline__ void sub_search_packed(const SubCtx &C, uint32_t amask,
                                                   const SubKey &K, W &best, int &u, int &cnt) {
     const int m = C.m;
@@ -698,7 +699,7 @@ __device__ __forceinline__ void sub_search_packed(const SubCtx &C, uint32_t amas
         }
         const uint32_t img = (((v[2] << m) | v[1]) << m) | v[0];
         const bool lt = img < bl, eq = img == bl;
-        bu = lt ? g : bu;
+        if constexpr (KEEP_U) bu = lt ? g : bu;
         bc = lt ? 1u : bc + (eq ? 1u : 0u);
         bl = lt ? img : bl;
     };
@@ -719,7 +720,7 @@ __device__ __forceinline__ void sub_search_packed(const SubCtx &C, uint32_t amas
         }
     }
     best = ((W)mt << (3 * m)) | (W)bl;
-    u = (int)bu;
+    u = KEEP_U ? (int)bu : 0;
     cnt = (int)bc;
 }
 

@@ -149,6 +149,7 @@ struct xdg_basis_s {
     int n_sites = 0, n_up = 0, n_sym = 0;
     bool wide = false;          // 64-bit state words (n_sites > 32)
     bool is_complex = false;
+    bool chi_trivial = false;   // every character is exactly 1
     int64_t dim = 0;
     std::vector<int32_t> perm;  // [n_sym][n_sites]
     std::vector<double> chi;    // [n_sym][2]
