@@ -246,6 +246,31 @@ __device__ __forceinline__ double wave_sum(double v) {
     return v;
 }
 
+// N values per lane summed over the wave together: each exchange step first
+// halves the values a lane keeps (the lanes of one half of the exchange keep
+// the lower values, the others the upper ones), then the last value is
+// summed over the remaining lane groups.  Lane l returns the wave total of
+// value l / (64 / N): N - 1 + 6 - log2(N) exchanges of a double instead of 6 N.
+template <int N>
+__device__ __forceinline__ double wave_sum_n(double (&v)[N], int lane) {
+    static_assert(N == 1 || N == 2 || N == 4 || N == 8, "N in {1, 2, 4, 8}");
+    int o = 32;
+#pragma unroll
+    for (int n = N; n > 1; n >>= 1, o >>= 1) {
+        const bool up = (lane & o) != 0;
+#pragma unroll
+        for (int i = 0; i < n / 2; ++i) {
+            const double keep = up ? v[i + n / 2] : v[i];
+            const double send = up ? v[i] : v[i + n / 2];
+            v[i] = keep + __shfl_xor(send, o, 64);
+        }
+    }
+    double r = v[0];
+#pragma unroll
+    for (; o >= 1; o >>= 1) r += __shfl_xor(r, o, 64);
+    return r;
+}
+
 // partials[(i C + c) nb + block] = the block's share of Re / Im <V_i, w>.
 // skip (may be null): a device flag; when set the pass does nothing.
 template <class T, int C>
@@ -271,6 +296,7 @@ __global__ __launch_bounds__(RB) void k_reorth_dots(const T *V, uint64_t ld, int
                 load_chunk<T>(V + (size_t)i * ld, tile0 + ((uint64_t)u * RB + t) * L, nsc,
                               vr[g] + u * L);
         }
+        double part[RG * C];   // value g C + c: Re (c = 0) / Im of <V_{i0+g}, w>
 #pragma unroll
         for (int g = 0; g < RG; ++g) {
             double re = 0.0, im = 0.0;
@@ -284,12 +310,13 @@ __global__ __launch_bounds__(RB) void k_reorth_dots(const T *V, uint64_t ld, int
                     im = fma(a, y, fma(-b, x, im));
                 }
             }
-            re = wave_sum(re);
-            if (C == 2) im = wave_sum(im);
-            if (lane == 0) {
-                sh[wave][g * C] = re;
-                if (C == 2) sh[wave][g * C + 1] = im;
-            }
+            part[g * C] = re;
+            if (C == 2) part[g * C + 1] = im;
+        }
+        {
+            constexpr int Q = 64 / (RG * C);   // lanes per value after the exchanges
+            const double r = wave_sum_n<RG * C>(part, lane);
+            if ((lane & (Q - 1)) == 0) sh[wave][lane / Q] = r;
         }
         __syncthreads();
         if (t < RG * C && i0 + t / C < k) {
