@@ -71,3 +71,27 @@ def test_counter_summaries_apply_only_to_their_sources():
         assert got["valu_wave_insts"] == t["valu_wave_insts"]
         assert abs(got["issue_ms"] - t["valu_wave_insts"] / bench.VALU_PEAK_WAVE_INSTS * 1e3) < 1e-12
         assert bench.load_issue(t["workload"], "0" * 16, 1e-3) is None
+
+
+def test_apply_dispatch_selection():
+    """The counter summaries take the last apply dispatch and, when the terms
+    read the rank-addressed x, the scatter launched just before it (both are
+    inside the timed launch); a scatter before an earlier apply is not
+    counted, and rows of other kernels (several counters per dispatch) are
+    ignored."""
+    def rows(seq):
+        out = []
+        for i, name in seq:
+            for c in ("SQ_INSTS_VALU", "SQ_WAVES"):
+                out.append({"Dispatch_Id": str(i), "Kernel_Name": name, "Counter_Name": c,
+                            "Counter_Value": "1"})
+        return out
+    sc = "void xdg::(anonymous namespace)::k_xr_scatter<unsigned long, float>(...)"
+    ap = "void xdg::k_apply<unsigned long, 3, float, double, false, 1, true, true, false, 1>(...)"
+    seq = [(1, sc), (2, ap), (3, sc), (4, ap), (5, "copyBuffer"), (6, "k_count")]
+    assert bench.apply_dispatches(rows(seq)) == {3, 4}
+    # index form: no scatter before the last apply
+    seq = [(1, sc), (2, ap), (3, ap), (4, "copyBuffer")]
+    assert bench.apply_dispatches(rows(seq)) == {3}
+    seq = [(7, ap)]
+    assert bench.apply_dispatches(rows(seq)) == {7}
