@@ -257,6 +257,17 @@ def test_fp32_accumulation_modes(X):
         y1 = gpu_apply(X, X.Hamiltonian.from_model(b1, m), x32, torch.complex64)
         assert rel_err(y0, y_or) < 1.2e-7, m.name
         assert rel_err(y1, y_or) < TOL32, m.name
+    # the rank-addressed x with FP32 accumulation (general and all-one characters)
+    for irrep in ("B1", "A1"):
+        m = W.torus_model((4, 2), (-2, 4), 1.0, 0.0, irrep, reflections=False)
+        b1 = X.Basis.from_model(m, flags=X.XDG_FLAG_F32_ACCUMULATE)
+        H1 = X.Hamiltonian.from_model(b1, m)
+        x = torch.randn(b1.dim, 2, dtype=torch.float32, device="cuda")
+        ref, y = torch.empty_like(x), torch.full_like(x, float("nan"))
+        X.xdg_apply_with_config(H1.handle, x, ref, xr=0)
+        X.xdg_apply_with_config(H1.handle, x, y, xr=1)
+        torch.cuda.synchronize()
+        assert torch.equal(y, ref), irrep
     with pytest.raises(X.XdgError):
         X.Basis(8, 4, flags=64)
 
